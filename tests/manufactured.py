@@ -1,0 +1,43 @@
+"""Manufactured solutions used by the oracle tests (exact u, f = lap u + k^2 u)."""
+import math
+
+from oracle.functions import Cos, Exp, Poly, Separable, Sin, Term, helmholtz_source
+
+
+def table3_u(k):
+    """Section 4.2.1: u = x^3(1-x)^3 * y(1-y)cos(k pi y) * sin(k pi z)."""
+    return Separable([Term(1.0, Poly((0, 0, 0, 1, -3, 3, -1)),
+                           Poly((0, 1, -1)) * Cos(k * math.pi), Sin(k * math.pi))])
+
+
+def table5_u(k):
+    """Section 4.2.2: as Table 3 with cos(k pi z) (u_z = 0 at z = 0, u = u_b at z = 1)."""
+    return Separable([Term(1.0, Poly((0, 0, 0, 1, -3, 3, -1)),
+                           Poly((0, 1, -1)) * Cos(k * math.pi), Cos(k * math.pi))])
+
+
+def neumann_z_u():
+    """u_z(0) = 0, u(1) = 0 and u_zzz(0) != 0, so the Neumann source terms are active."""
+    return Separable([Term(1.0, Sin(math.pi), Sin(2 * math.pi), Cos(math.pi / 2) * Poly((1, 0, 0, 1)))])
+
+
+def neumann_y_factor():
+    """Y'(0) = Y'(1) = 0 and Y'''(0) = -12: an active Neumann pair on y."""
+    return Cos(math.pi) + Poly((0, 0, 1, -2, 1))
+
+
+def sommerfeld_z_factor(k):
+    """psi(z) = e^{-ikz}(1 + c z^2), c = ik/(1 - ik): u_z + iku = 0 at z = 0 and
+    u_z - iku = 0 at z = 1 (the printed test function of Table 7 satisfies only
+    the second condition, so it is not used)."""
+    c = 1j * k / (1 - 1j * k)
+    return Exp(-1j * k) * Poly((1, 0, c))
+
+
+def mixed_pattern_u(k):
+    """x Dirichlet, y Neumann, z Sommerfeld: the face pattern of the benchmark grids."""
+    return Separable([Term(1.0, Sin(math.pi), neumann_y_factor(), sommerfeld_z_factor(k))])
+
+
+def source(u, k):
+    return helmholtz_source(u, k)
