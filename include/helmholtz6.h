@@ -1,0 +1,147 @@
+/*
+ * helmholtz6 - sixth-order compact Helmholtz solver for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gryazin, "Preconditioned Krylov subspace methods for sixth order
+ * compact approximations of the Helmholtz equation" (arXiv:1212.1397).
+ *   - Problem and faces: Section 1, eqs. (problem) and (bc).
+ *   - Operator A: Section 3.1, eq. (scheme), with the Neumann closure of
+ *     Section 3.2.1, eq. (3DN), and the Sommerfeld-like closure of
+ *     Section 3.2.2, eq. (3DDISCS).
+ *   - Preconditioner A_p: Section 3.3, eq. (3DAP).
+ *   - Solvers: right-preconditioned GMRES (Section 2, eq. (AAP)) and the SKS
+ *     iteration (Section 2, Algorithm 1).
+ *
+ * Every entry point is extern "C" and never throws.  All vectors are device
+ * pointers to complex128 values stored as interleaved (re, im) doubles, x
+ * fastest: element (i, j, l) of an n'x x n'y x n'z grid sits at
+ * i + n'x * (j + n'y * l).  n'a = n[a] + (number of Neumann/Sommerfeld faces
+ * on axis a), see helmholtz6_dims.  Pointers must be 16-byte aligned.
+ *
+ * Ownership: the caller owns every vector buffer; the library owns a plan and
+ * its device workspace (allocated by helmholtz6_setup / helmholtz6_solve,
+ * released by helmholtz6_destroy).  No caller pointer is kept after a call
+ * returns.  apply_* and rhs_* only enqueue work on the given HIP stream (NULL
+ * means the legacy default stream); the caller keeps buffers alive until the
+ * stream is synchronised.  helmholtz6_solve synchronises the stream before it
+ * returns.  A plan must not be used from two host threads at once.
+ *
+ * Errors: a negative status means the call failed and outputs are
+ * unspecified; helmholtz6_last_error(plan) gives a message.  Non-negative
+ * statuses other than H6_OK (not converged, diverged) leave a valid iterate.
+ */
+#ifndef HELMHOLTZ6_H
+#define HELMHOLTZ6_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H6_OK = 0,
+  H6_NOT_CONVERGED = 1,      /* maxit reached; U holds the last iterate */
+  H6_DIVERGED = 2,           /* SKS: relative residual > 1e4 or not finite; U = last iterate */
+  H6_ERR_ARG = -1,           /* invalid argument (null pointer, bad size, bad enum) */
+  H6_ERR_UNSUPPORTED_BC = -2,/* face pattern without a preconditioner in Section 3.3 */
+  H6_ERR_ALLOC = -3,         /* device allocation failed */
+  H6_ERR_HIP = -4,           /* a HIP runtime call or kernel launch failed */
+  H6_ERR_SINGULAR = -5       /* zero or non-finite pivot in a z tridiagonal of A_p:
+                                k^2 lies on the spectrum of the 7-point operator */
+} h6_status;
+
+typedef enum { H6_DIRICHLET = 0, H6_NEUMANN = 1, H6_SOMMERFELD = 2 } h6_bc;
+typedef enum { H6_GMRES = 0, H6_FGMRES = 1, H6_SKS = 2 } h6_method;
+typedef enum { H6_FP64 = 0, H6_MIXED = 1 } h6_precision;
+
+typedef struct h6_plan_s* h6_plan;
+
+typedef struct {
+  int n[3];        /* interior node counts nx, ny, nz (>= 1); domain length on axis a is (n[a]+1)*h */
+  double h;        /* grid step, common to all axes (Section 3.3: same step in x, y, z) */
+  double k_re;     /* wavenumber k = k_re + i k_im (Section 1: k may be complex) */
+  double k_im;
+  int bc[6];       /* h6_bc of faces x-, x+, y-, y+, z-, z+.  Section 3.3 covers x/y faces
+                      as a Dirichlet or a Neumann pair; z faces may be any of the three,
+                      independently.  Other patterns give H6_ERR_UNSUPPORTED_BC. */
+  int precision;   /* h6_precision.  H6_MIXED runs the preconditioner's transforms and
+                      tridiagonal solves in complex64 (FP32 arithmetic); the operator,
+                      residuals, Arnoldi and Hessenberg stay FP64.  Use H6_FGMRES or
+                      H6_SKS with it (plain GMRES assumes an exact preconditioner). */
+} h6_params;
+
+typedef struct {
+  int method;        /* in: h6_method */
+  int restart;       /* in: GMRES/FGMRES cycle length m (1..256); ignored by SKS */
+  int maxit;         /* in: maximum number of A A_p^{-1} applications (>= 1) */
+  double tol;        /* in: stop when ||F - A U||_2 / ||F||_2 <= tol (true residual) */
+  int iters;         /* out: A A_p^{-1} applications made, counted across restarts */
+  double rel_resid;  /* out: true FP64 relative residual of the returned U */
+  double* history;   /* in (optional, host): per-iteration residual estimates (GMRES: the
+                        least-squares residual; SKS: the true residual), relative to ||F|| */
+  int history_len;   /* in: capacity of history; out: entries written */
+} h6_solve_info;
+
+/* Builds a plan: validates the parameters, derives the unknown counts, the
+ * complex coefficients of A (Section 3.1-3.2) and A_p (Section 3.3), the
+ * transverse eigenvalue tables, transform plans, and checks every z
+ * tridiagonal of A_p for a zero pivot (H6_ERR_SINGULAR).  hip_stream: the
+ * stream used for table uploads.  On failure *out is NULL.  */
+h6_status helmholtz6_setup(const h6_params* p, void* hip_stream, h6_plan* out);
+
+/* Unknown counts dims = {n'x, n'y, n'z}. */
+h6_status helmholtz6_dims(h6_plan plan, int dims[3]);
+
+/* y = A x: the h^2-scaled 27-point compact operator of eq. (scheme) with the
+ * Neumann (3DN) and Sommerfeld (3DDISCS) closure rows.  x and y must not
+ * alias.  Enqueue only. */
+h6_status helmholtz6_apply_A(h6_plan plan, const void* x, void* y, void* hip_stream);
+
+/* z = A_p^{-1} r for the h^2-scaled 7-point operator of eq. (3DAP): forward
+ * sine/cosine transforms in x and y, one tridiagonal solve per transverse
+ * mode in z, inverse transforms.  r is not modified; r and z must not alias.
+ * In H6_MIXED plans the arithmetic is complex64 (r and z stay complex128).
+ * Enqueue only. */
+h6_status helmholtz6_apply_Pinv(h6_plan plan, const void* r, void* z, void* hip_stream);
+
+/* F = h^2-scaled compact right-hand side (eq. (scheme) right side, with the
+ * mixed fourth-derivative coefficient h^4/180, plus the Neumann and
+ * Sommerfeld face terms of (3DN) and (3DIMP)/(3DDISCS)) for the source
+ *   f(x,y,z) = sum_s amp_s exp(-|x - c_s|^2 / (2 sigma^2)).
+ * centres: host array of 3*nsrc doubles (x, y, z per source); amps: host
+ * array of 2*nsrc doubles (re, im per source); nsrc in 0..64.  Enqueue only. */
+h6_status helmholtz6_rhs_gaussians(h6_plan plan, int nsrc, const double* centres,
+                                   const double* amps, double sigma, void* F, void* hip_stream);
+
+/* Solves A U = F.  U is the initial guess on entry (may be zero) and the
+ * solution on return.  F and U must not alias.  GMRES/FGMRES: right
+ * preconditioning, modified Gram-Schmidt Arnoldi, Givens least squares in FP64
+ * on the host, restart every info->restart steps.  SKS: Algorithm 1 written
+ * in correction form U += A_p^{-1} r (identical iterates for U0 = 0).
+ * Synchronises hip_stream before returning. */
+h6_status helmholtz6_solve(h6_plan plan, const void* F, void* U, h6_solve_info* info,
+                           void* hip_stream);
+
+/* Per-kernel timing: when enabled, the library records HIP events around
+ * every kernel it launches and accumulates their durations per kernel class.
+ * helmholtz6_kernel_time reads (and with reset != 0 clears) the total
+ * milliseconds and launch count of one class by name ("stencil",
+ * "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm", "axpy",
+ * "rhs"); it synchronises the plan's timing events.  Returns H6_ERR_ARG for
+ * an unknown name. */
+h6_status helmholtz6_profile(h6_plan plan, int enable);
+h6_status helmholtz6_kernel_time(h6_plan plan, const char* name, int reset, double* ms,
+                                 long long* launches);
+
+/* Releases the plan and its workspace (NULL is accepted). */
+void helmholtz6_destroy(h6_plan plan);
+
+/* Static description of a status code. */
+const char* helmholtz6_status_string(h6_status s);
+
+/* Detail of the last failing call on this plan (empty if none); valid until
+ * the next call on the plan.  With plan == NULL: the last setup failure. */
+const char* helmholtz6_last_error(h6_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELMHOLTZ6_H */

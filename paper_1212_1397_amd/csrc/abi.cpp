@@ -1,0 +1,431 @@
+// C ABI of the helmholtz6 library: parameter validation, plan construction
+// (coefficients of Section 3.1-3.3), workspace, status strings and timing.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "h6_internal.h"
+
+namespace h6 {
+
+const char* const kKernelClassNames[KC_COUNT] = {
+    "stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm", "axpy", "rhs"};
+
+namespace {
+
+std::string g_setup_error;
+std::mutex g_setup_mutex;
+
+W9 to_w9(cplx alpha, cplx beta, cplx gamma) {
+  cplx c = alpha - 4.0 * beta + 4.0 * gamma, e = beta - 2.0 * gamma, k = gamma;
+  return W9{make_double2(c.real(), c.imag()), make_double2(e.real(), e.imag()),
+            make_double2(k.real(), k.imag())};
+}
+
+W9 w9_lin(const W9& a, double sa, const W9& b, double sb) {
+  auto f = [&](double2 x, double2 y) {
+    return make_double2(sa * x.x + sb * y.x, sa * x.y + sb * y.y);
+  };
+  return W9{f(a.c, b.c), f(a.e, b.e), f(a.k, b.k)};
+}
+
+const W9 kZeroW9{make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+
+// Stencil weights.  With D_a = h^2 delta_a^2 and kappa = (kh)^2, eq. (scheme)
+// times h^2 is D_z G + P with
+//   G = I + a (D_x + D_y) + (1/30) D_x D_y,            a = (1 + kappa/30) / 6,
+//   P = D_x + D_y + a D_x D_y + kappa c_K I,           c_K = 1 - kappa/12 + kappa^2/360,
+// so an interior row is G U_{l-1} + (P - 2G) U_l + G U_{l+1}.  A closure row
+// replaces G U_ghost by G U_1 (Neumann, eq. (3DN)) or by Q U_1 + R U_0
+// (Sommerfeld, eq. (3DDISCS)).
+void build_stencil(h6_plan P) {
+  const cplx I(0.0, 1.0);
+  const cplx kap = P->kappa;
+  const cplx kh = P->k * P->p.h;
+  const cplx ikh = I * kh;
+  const cplx a = (1.0 + kap / 30.0) / 6.0;
+  const cplx cK = 1.0 - kap / 12.0 + kap * kap / 360.0;
+  const W9 G = to_w9(1.0, a, 1.0 / 30.0);
+  const W9 Pw = to_w9(kap * cK, 1.0, a);
+  const W9 Pm2G = w9_lin(Pw, 1.0, G, -2.0);
+
+  // Section 3.2.2: mu_3, mu_1 chosen to match the interior scheme.
+  const cplx mu3 = 1.0 / (1.0 + (2.0 * ikh / 3.0) * (1.0 + 2.0 * kap / 15.0));
+  const cplx mu1 = (ikh / 90.0 + (1.0 + kap / 30.0) / (6.0 * mu3)) / (1.0 + 2.0 * ikh / 3.0);
+  const cplx q = std::exp(2.0 * ikh) * mu3;
+  const W9 Q = to_w9(q * (1.0 - 2.0 * ikh / 3.0 - 4.0 * I * kh * kh * kh / 45.0),
+                     q * (mu1 + (2.0 * ikh / 3.0) * (1.0 / 60.0 - mu1)), q / (30.0 * mu3));
+  const cplx r = std::exp(ikh) * mu3;
+  const W9 R = to_w9(r * (4.0 * ikh / 3.0) * (1.0 + 2.0 * kap / 15.0),
+                     -r * (4.0 * ikh / 3.0) * (1.0 / 60.0 - mu1), 0.0);
+
+  StencilTable& T = P->stencil;
+  T.w[0][0] = G;
+  T.w[0][1] = Pm2G;
+  T.w[0][2] = G;
+  const int lo = P->p.bc[4], hi = P->p.bc[5];
+  // low-z closure row: ghost plane (offset -1) eliminated
+  T.w[1][0] = kZeroW9;
+  if (lo == H6_SOMMERFELD) {
+    T.w[1][1] = w9_lin(Pm2G, 1.0, R, 1.0);
+    T.w[1][2] = w9_lin(G, 1.0, Q, 1.0);
+  } else {
+    T.w[1][1] = Pm2G;
+    T.w[1][2] = w9_lin(G, 2.0, G, 0.0);
+  }
+  // high-z closure row: ghost plane (offset +1) eliminated
+  T.w[2][2] = kZeroW9;
+  if (hi == H6_SOMMERFELD) {
+    T.w[2][1] = w9_lin(Pm2G, 1.0, R, 1.0);
+    T.w[2][0] = w9_lin(G, 1.0, Q, 1.0);
+  } else {
+    T.w[2][1] = Pm2G;
+    T.w[2][0] = w9_lin(G, 2.0, G, 0.0);
+  }
+}
+
+// lambda(m) = -4 sin^2(pi m / (2M)); modes m = 1..n (Dirichlet) or 0..M (Neumann).
+std::vector<double> mode_lambdas(const AxisXform& a) {
+  std::vector<double> l(a.L);
+  for (int i = 0; i < a.L; ++i) {
+    const int m = a.neumann ? i : i + 1;
+    const double s = std::sin(M_PI * m / (2.0 * a.M));
+    l[i] = -4.0 * s * s;
+  }
+  return l;
+}
+
+std::vector<double> trig_table(int M) {
+  std::vector<double> t(4 * M);
+  for (int i = 0; i < 2 * M; ++i) {
+    t[i] = std::sin(M_PI * i / M);
+    t[2 * M + i] = std::cos(M_PI * i / M);
+  }
+  return t;
+}
+
+// T_z of eq. (3DAP): tridiag(1, -2, 1), corner entry 2 next to a Neumann or
+// Sommerfeld face (beta_z = 1), diagonal + 2ikh on a Sommerfeld face.
+void z_tridiagonal(h6_plan P, std::vector<cplx>& sub, std::vector<cplx>& diag,
+                   std::vector<cplx>& sup) {
+  const int L = P->dims[2];
+  sub.assign(L, 1.0);
+  sup.assign(L, 1.0);
+  diag.assign(L, -2.0);
+  sub[0] = 0.0;
+  sup[L - 1] = 0.0;
+  const cplx alpha = cplx(0.0, 2.0) * P->k * P->p.h;
+  if (P->p.bc[4] != H6_DIRICHLET && L > 1) {
+    sup[0] = 2.0;
+    if (P->p.bc[4] == H6_SOMMERFELD) diag[0] += alpha;
+  }
+  if (P->p.bc[5] != H6_DIRICHLET && L > 1) {
+    sub[L - 1] = 2.0;
+    if (P->p.bc[5] == H6_SOMMERFELD) diag[L - 1] += alpha;
+  }
+}
+
+// Gaussian elimination pivots of every z system T_z + (kappa + lx + ly) I;
+// a pivot below 1e-12 (4 + |shift|) or non-finite means A_p is singular.
+bool singular_modes(h6_plan P, const std::vector<double>& lx, const std::vector<double>& ly,
+                    const std::vector<cplx>& sub, const std::vector<cplx>& diag,
+                    const std::vector<cplx>& sup, std::string& where) {
+  const int L = P->dims[2];
+  for (size_t j = 0; j < ly.size(); ++j)
+    for (size_t i = 0; i < lx.size(); ++i) {
+      const cplx shift = P->kappa + lx[i] + ly[j];
+      const double tol = 1e-12 * (4.0 + std::abs(shift));
+      cplx cprev = 0.0;
+      for (int l = 0; l < L; ++l) {
+        const cplx piv = diag[l] + shift - (l > 0 ? sub[l] * cprev : cplx(0.0));
+        if (!std::isfinite(piv.real()) || !std::isfinite(piv.imag()) || std::abs(piv) <= tol) {
+          where = "zero pivot in z row " + std::to_string(l) + " of mode (" + std::to_string(i) +
+                  ", " + std::to_string(j) + ")";
+          return true;
+        }
+        cprev = sup[l] / piv;
+      }
+    }
+  return false;
+}
+
+void free_plan(h6_plan P) {
+  if (!P) return;
+  (void)hipFree(P->d_stencil);
+  (void)hipFree(P->d_lambda_x);
+  (void)hipFree(P->d_lambda_y);
+  (void)hipFree(P->d_trig_x);
+  (void)hipFree(P->d_trig_y);
+  (void)hipFree(P->d_tri);
+  for (void* w : P->w_pc) (void)hipFree(w);
+  (void)hipFree(P->V);
+  (void)hipFree(P->Z);
+  (void)hipFree(P->r);
+  (void)hipFree(P->t);
+  (void)hipFree(P->partials);
+  (void)hipFree(P->d_scal);
+  if (P->h_pinned) (void)hipHostFree(P->h_pinned);
+  for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
+  for (auto& pe : P->timing.pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  delete P;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::string& err) {
+  *out = nullptr;
+  if (!p) { err = "params is NULL"; return H6_ERR_ARG; }
+  for (int a = 0; a < 3; ++a)
+    if (p->n[a] < 1 || p->n[a] > 100000) { err = "n[a] must be in 1..100000"; return H6_ERR_ARG; }
+  if (!(p->h > 0.0) || !std::isfinite(p->h)) { err = "h must be positive and finite"; return H6_ERR_ARG; }
+  if (!std::isfinite(p->k_re) || !std::isfinite(p->k_im)) { err = "k must be finite"; return H6_ERR_ARG; }
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] < H6_DIRICHLET || p->bc[f] > H6_SOMMERFELD) { err = "bad bc code"; return H6_ERR_ARG; }
+  if (p->precision != H6_FP64 && p->precision != H6_MIXED) { err = "bad precision"; return H6_ERR_ARG; }
+  for (int a = 0; a < 2; ++a) {
+    if (p->bc[2 * a] == H6_SOMMERFELD || p->bc[2 * a + 1] == H6_SOMMERFELD) {
+      err = "Sommerfeld faces are supported on z only";
+      return H6_ERR_UNSUPPORTED_BC;
+    }
+    if (p->bc[2 * a] != p->bc[2 * a + 1]) {
+      err = "x and y faces must be a Dirichlet or a Neumann pair";
+      return H6_ERR_UNSUPPORTED_BC;
+    }
+  }
+  h6_plan P = new (std::nothrow) h6_plan_s();
+  if (!P) { err = "host allocation failed"; return H6_ERR_ALLOC; }
+  P->p = *p;
+  for (int a = 0; a < 3; ++a)
+    P->dims[a] = p->n[a] + (p->bc[2 * a] != H6_DIRICHLET) + (p->bc[2 * a + 1] != H6_DIRICHLET);
+  P->N = size_t(P->dims[0]) * P->dims[1] * P->dims[2];
+  if (P->N > (size_t(1) << 31)) { err = "grid too large"; free_plan(P); return H6_ERR_ARG; }
+  P->xmirror = p->bc[0] == H6_NEUMANN;
+  P->ymirror = p->bc[2] == H6_NEUMANN;
+  P->zlo_closure = p->bc[4] != H6_DIRICHLET;
+  P->zhi_closure = p->bc[5] != H6_DIRICHLET;
+  P->k = cplx(p->k_re, p->k_im);
+  P->kappa = (P->k * p->h) * (P->k * p->h);
+  build_stencil(P);
+  for (int a = 0; a < 2; ++a) {
+    P->ax[a].L = P->dims[a];
+    P->ax[a].M = p->n[a] + 1;
+    P->ax[a].neumann = p->bc[2 * a] == H6_NEUMANN;
+  }
+  std::vector<double> lx = mode_lambdas(P->ax[0]), ly = mode_lambdas(P->ax[1]);
+  std::vector<cplx> sub, diag, sup;
+  z_tridiagonal(P, sub, diag, sup);
+  std::string where;
+  if (singular_modes(P, lx, ly, sub, diag, sup, where)) {
+    err = "preconditioner is singular: " + where;
+    free_plan(P);
+    return H6_ERR_SINGULAR;
+  }
+  std::vector<double2> tri(3 * P->dims[2]);
+  for (int l = 0; l < P->dims[2]; ++l) {
+    tri[l] = make_double2(sub[l].real(), sub[l].imag());
+    tri[P->dims[2] + l] = make_double2(diag[l].real(), diag[l].imag());
+    tri[2 * P->dims[2] + l] = make_double2(sup[l].real(), sup[l].imag());
+  }
+  hipError_t e = hipSuccess;
+  std::vector<StencilTable> st(1, P->stencil);
+  if (e == hipSuccess) e = upload(&P->d_stencil, st, s);
+  if (e == hipSuccess) e = upload(&P->d_lambda_x, lx, s);
+  if (e == hipSuccess) e = upload(&P->d_lambda_y, ly, s);
+  if (e == hipSuccess) e = upload(&P->d_trig_x, trig_table(P->ax[0].M), s);
+  if (e == hipSuccess) e = upload(&P->d_trig_y, trig_table(P->ax[1].M), s);
+  if (e == hipSuccess) e = upload(&P->d_tri, tri, s);
+  const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
+  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMalloc(&P->w_pc[i], P->N * elem);
+  if (e == hipSuccess) e = hipMalloc(&P->partials, sizeof(double) * 2 * kMaxPartials);
+  if (e == hipSuccess) e = hipMalloc(&P->d_scal, sizeof(double2) * kScal);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), sizeof(double2) * kScal);
+  if (e != hipSuccess) {
+    err = std::string("device setup failed: ") + hipGetErrorString(e);
+    const bool oom = e == hipErrorOutOfMemory;
+    free_plan(P);
+    return oom ? H6_ERR_ALLOC : H6_ERR_HIP;
+  }
+  *out = P;
+  return H6_OK;
+}
+
+}  // namespace
+
+void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a) {
+  (void)cls;
+  *a = nullptr;
+  if (!P->timing.enabled) return;
+  if (P->timing.pool.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return;
+    P->timing.pool.push_back(ev);
+  }
+  *a = P->timing.pool.back();
+  P->timing.pool.pop_back();
+  (void)hipEventRecord(*a, s);
+}
+
+void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a) {
+  if (!P->timing.enabled || !a) return;
+  hipEvent_t b;
+  if (P->timing.pool.empty()) {
+    if (hipEventCreate(&b) != hipSuccess) { P->timing.pool.push_back(a); return; }
+  } else {
+    b = P->timing.pool.back();
+    P->timing.pool.pop_back();
+  }
+  (void)hipEventRecord(b, s);
+  P->timing.pending.push_back({a, b, cls});
+}
+
+}  // namespace h6
+
+using namespace h6;
+
+extern "C" {
+
+h6_status helmholtz6_setup(const h6_params* p, void* hip_stream, h6_plan* out) {
+  if (!out) return H6_ERR_ARG;
+  std::string err;
+  h6_status st;
+  try {
+    st = setup_impl(p, static_cast<hipStream_t>(hip_stream), out, err);
+  } catch (...) {
+    st = H6_ERR_ALLOC;
+    err = "exception during setup";
+    *out = nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_setup_mutex);
+  g_setup_error = err;
+  return st;
+}
+
+h6_status helmholtz6_dims(h6_plan P, int dims[3]) {
+  if (!P || !dims) return H6_ERR_ARG;
+  for (int a = 0; a < 3; ++a) dims[a] = P->dims[a];
+  return H6_OK;
+}
+
+h6_status helmholtz6_apply_A(h6_plan P, const void* x, void* y, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!x || !y || x == y) { P->last_error = "x, y must be distinct non-null pointers"; return H6_ERR_ARG; }
+  H6_TRY_HIP(launch_stencil(P, static_cast<const double2*>(x), static_cast<double2*>(y), nullptr,
+                            nullptr, nullptr, static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_apply_Pinv(h6_plan P, const void* r, void* z, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!r || !z || r == z) { P->last_error = "r, z must be distinct non-null pointers"; return H6_ERR_ARG; }
+  H6_TRY_HIP(launch_pinv(P, static_cast<const double2*>(r), static_cast<double2*>(z),
+                         static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_rhs_gaussians(h6_plan P, int nsrc, const double* centres, const double* amps,
+                                   double sigma, void* F, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!F || nsrc < 0 || nsrc > 64 || (nsrc > 0 && (!centres || !amps)) || !(sigma > 0.0)) {
+    P->last_error = "bad rhs arguments";
+    return H6_ERR_ARG;
+  }
+  H6_TRY_HIP(launch_rhs(P, nsrc, centres, amps, sigma, static_cast<double2*>(F),
+                        static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_solve(h6_plan P, const void* F, void* U, h6_solve_info* info,
+                           void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!F || !U || !info || F == U) { P->last_error = "bad solve arguments"; return H6_ERR_ARG; }
+  if (info->method < H6_GMRES || info->method > H6_SKS || info->maxit < 1 || !(info->tol >= 0.0) ||
+      ((info->method != H6_SKS) && (info->restart < 1 || info->restart > 256)) ||
+      (info->history_len < 0) || (info->history_len > 0 && !info->history)) {
+    P->last_error = "bad solve info";
+    return H6_ERR_ARG;
+  }
+  if (P->p.precision == H6_MIXED && info->method == H6_GMRES) {
+    P->last_error = "mixed precision needs FGMRES or SKS (the preconditioner is inexact)";
+    return H6_ERR_ARG;
+  }
+  try {
+    return run_solve(P, static_cast<const double2*>(F), static_cast<double2*>(U), info,
+                     static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    P->last_error = "exception during solve";
+    return H6_ERR_ALLOC;
+  }
+}
+
+h6_status helmholtz6_profile(h6_plan P, int enable) {
+  if (!P) return H6_ERR_ARG;
+  P->timing.enabled = enable != 0;
+  return H6_OK;
+}
+
+h6_status helmholtz6_kernel_time(h6_plan P, const char* name, int reset, double* ms,
+                                 long long* launches) {
+  if (!P || !name) return H6_ERR_ARG;
+  int cls = -1;
+  for (int i = 0; i < KC_COUNT; ++i)
+    if (std::strcmp(name, kKernelClassNames[i]) == 0) cls = i;
+  if (cls < 0) { P->last_error = "unknown kernel class"; return H6_ERR_ARG; }
+  for (auto& pe : P->timing.pending) {
+    float t = 0.f;
+    if (hipEventSynchronize(pe.b) == hipSuccess && hipEventElapsedTime(&t, pe.a, pe.b) == hipSuccess) {
+      P->timing.ms[pe.cls] += t;
+      P->timing.launches[pe.cls] += 1;
+    }
+    P->timing.pool.push_back(pe.a);
+    P->timing.pool.push_back(pe.b);
+  }
+  P->timing.pending.clear();
+  if (ms) *ms = P->timing.ms[cls];
+  if (launches) *launches = P->timing.launches[cls];
+  if (reset) {
+    P->timing.ms[cls] = 0.0;
+    P->timing.launches[cls] = 0;
+  }
+  return H6_OK;
+}
+
+void helmholtz6_destroy(h6_plan P) { free_plan(P); }
+
+const char* helmholtz6_status_string(h6_status s) {
+  switch (s) {
+    case H6_OK: return "ok";
+    case H6_NOT_CONVERGED: return "not converged (maxit reached)";
+    case H6_DIVERGED: return "diverged";
+    case H6_ERR_ARG: return "invalid argument";
+    case H6_ERR_UNSUPPORTED_BC: return "unsupported boundary-condition pattern";
+    case H6_ERR_ALLOC: return "allocation failed";
+    case H6_ERR_HIP: return "HIP runtime error";
+    case H6_ERR_SINGULAR: return "preconditioner singular (k^2 on the 7-point spectrum)";
+  }
+  return "unknown status";
+}
+
+const char* helmholtz6_last_error(h6_plan P) {
+  if (!P) {
+    std::lock_guard<std::mutex> g(g_setup_mutex);
+    return g_setup_error.c_str();
+  }
+  return P->last_error.c_str();
+}
+
+}  // extern "C"

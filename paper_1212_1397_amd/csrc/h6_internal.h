@@ -1,0 +1,144 @@
+// Internal declarations shared by the host plan, the solver loops and the HIP
+// kernels of the helmholtz6 library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/helmholtz6.h"
+
+namespace h6 {
+
+using cplx = std::complex<double>;
+
+// Weights of one 9-point in-plane operator acting on (centre, sum of the four
+// edge neighbours, sum of the four corner neighbours).  Any operator
+// alpha I + beta (D_x + D_y) + gamma D_x D_y has
+//   centre = alpha - 4 beta + 4 gamma, edge = beta - 2 gamma, corner = gamma.
+struct W9 {
+  double2 c, e, k;
+};
+
+// Stencil weight table: [row type][plane offset -1, 0, +1], row types
+// 0 = interior row, 1 = low-z closure row, 2 = high-z closure row.
+struct StencilTable {
+  W9 w[3][3];
+};
+
+enum KernelClass {
+  KC_STENCIL = 0,
+  KC_STENCIL_RESID,
+  KC_XFORM_X,
+  KC_XFORM_Y,
+  KC_TRIDIAG,
+  KC_MGS,
+  KC_NORM,
+  KC_AXPY,
+  KC_RHS,
+  KC_COUNT
+};
+extern const char* const kKernelClassNames[KC_COUNT];
+
+// Transform along one transverse axis (Section 3.3): a sine basis for a
+// Dirichlet pair, a cosine basis for a Neumann pair; M = n + 1.
+struct AxisXform {
+  int L = 0;        // unknowns on the axis (n for D, n + 2 for N)
+  int M = 0;        // n + 1
+  int neumann = 0;  // 0: DST-I pair, 1: DCT-I pair
+};
+
+struct Timing {
+  bool enabled = false;
+  double ms[KC_COUNT] = {0};
+  long long launches[KC_COUNT] = {0};
+  std::vector<hipEvent_t> pool;     // recycled events
+  struct Pending { hipEvent_t a, b; int cls; };
+  std::vector<Pending> pending;
+};
+
+}  // namespace h6
+
+struct h6_plan_s {
+  h6_params p{};
+  int dims[3] = {0, 0, 0};          // n'x, n'y, n'z
+  size_t N = 0;                     // unknowns
+  int zlo_closure = 0, zhi_closure = 0;   // z face is N or S (closure row present)
+  int xmirror = 0, ymirror = 0;           // x / y pair is Neumann
+  h6::cplx k, kappa;
+  h6::StencilTable stencil{};
+  h6::AxisXform ax[2];
+
+  // device tables
+  h6::StencilTable* d_stencil = nullptr;
+  double* d_lambda_x = nullptr;     // transverse eigenvalues per mode
+  double* d_lambda_y = nullptr;
+  double* d_trig_x = nullptr;       // sin, cos (pi t / M), t = 0..2M-1 (2 * 2M doubles)
+  double* d_trig_y = nullptr;
+  double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
+
+  // preconditioner workspace (complex128 vectors, or complex64 in mixed plans)
+  void* w_pc[3] = {nullptr, nullptr, nullptr};
+
+  // Krylov workspace (allocated on first solve, grown as needed)
+  double2* V = nullptr;   int V_cols = 0;      // (m+1) basis vectors
+  void* Z = nullptr;      int Z_cols = 0;      // FGMRES preconditioned vectors
+  double2* r = nullptr;                        // residual / scratch vector
+  double2* t = nullptr;                        // scratch vector
+  double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
+  double2* d_scal = nullptr;                   // device scalars: h column, norms (kScal entries)
+  double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
+
+  h6::Timing timing;
+  std::string last_error;
+};
+
+namespace h6 {
+
+constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
+constexpr int kMaxPartials = 1 << 20;
+constexpr int kScal = 1024;        // device scalar slots
+
+// kernel launchers (stream-ordered, no synchronisation)
+hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
+                          double* partials, int* nparts, hipStream_t s);
+hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s);
+hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
+                      double sigma, double2* F, hipStream_t s);
+
+// Krylov helpers (double2 vectors of length P->N)
+hipError_t launch_dot_partials(const double2* a, const double2* b, size_t n, double* partials,
+                               hipStream_t s);                     // sum conj(a) b
+hipError_t launch_mgs_step(double2* w, const double2* vprev, const double2* hprev,
+                           const double2* vcur, size_t n, double* partials, hipStream_t s);
+hipError_t launch_norm2_partials(const double2* a, size_t n, double* partials, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int nparts, int ncomp, double2* out,
+                         hipStream_t s);
+hipError_t launch_axpy_norm(double2* w, const double2* v, const double2* h, size_t n,
+                            double* partials, hipStream_t s);   // w -= h v; partial |w|^2
+hipError_t launch_scale_inv_norm(double2* v, const double2* src, const double2* nrm, size_t n,
+                                 hipStream_t s);                 // v = src / sqrt(nrm.x)
+hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
+                             int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
+hipError_t launch_add(double2* U, const double2* z, size_t n, hipStream_t s);   // U += z
+
+// timing helpers
+void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a);
+void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a);
+
+// solver
+h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s);
+
+}  // namespace h6
+
+#define H6_TRY_HIP(expr)                                                         \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess) {                                                      \
+      P->last_error = std::string(#expr) + ": " + hipGetErrorString(_e);         \
+      return H6_ERR_HIP;                                                         \
+    }                                                                            \
+  } while (0)

@@ -1,0 +1,199 @@
+// y = A x (or r = F - A x with partial |r|^2): the h^2-scaled sixth-order
+// compact 27-point operator of eq. (scheme) with the Neumann (3DN) and
+// Sommerfeld (3DDISCS) closure rows, complex128.
+//
+// Each row is sum_{d=-1,0,1} W[rowtype][d] . S_{l+d}, where S_p holds, for
+// plane p, the centre value, the sum of the four edge neighbours and the sum
+// of the four corner neighbours of a point (the in-plane parts of D_x + D_y
+// and D_x D_y).  Neumann x/y faces enter through mirror ghosts, Dirichlet
+// faces through zeros.
+//
+// Launch shape (2.5D march): a workgroup of 256 threads owns a 64 x 8 x-y tile
+// and a chunk of up to kTZ z-planes.  It streams the planes of its chunk plus
+// one halo plane on each side through a double-buffered LDS tile of 66 x 10
+// complex values, computes S_p once per plane, and scatters it into the two
+// running row accumulators.  Each plane is read from HBM once per tile
+// (halo columns and the two halo planes are the only re-reads).  Workgroup
+// ids are remapped so that consecutive tiles land on the same XCD (shared L2
+// for halos).
+#include "h6_internal.h"
+
+namespace h6 {
+namespace {
+
+constexpr int kTX = 64, kTY = 8, kTZ = 16;
+constexpr int kLX = kTX + 2, kLY = kTY + 2;
+constexpr int kThreads = 256;
+constexpr int kLoads = (kLX * kLY + kThreads - 1) / kThreads;   // 3
+
+__device__ __forceinline__ int xcd_remap(int bid, int nwg) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+struct S3 {
+  double2 c, e, k;
+};
+
+__device__ __forceinline__ void cmac(double2& acc, double2 w, double2 s) {
+  acc.x = fma(w.x, s.x, acc.x);
+  acc.x = fma(-w.y, s.y, acc.x);
+  acc.y = fma(w.x, s.y, acc.y);
+  acc.y = fma(w.y, s.x, acc.y);
+}
+
+__device__ __forceinline__ void apply_w(double2& acc, const W9& w, const S3& s) {
+  cmac(acc, w.c, s.c);
+  cmac(acc, w.e, s.e);
+  cmac(acc, w.k, s.k);
+}
+
+__device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+template <bool RESID>
+__global__ __launch_bounds__(kThreads) void stencil_kernel(
+    const double2* __restrict__ x, double2* __restrict__ y, const double2* __restrict__ F,
+    double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
+    int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg) {
+  __shared__ double2 tile[2][kLY][kLX];
+  __shared__ double red[kThreads / 64];
+
+  const int L = xcd_remap(blockIdx.x, nwg);
+  const int tx_i = L % ntx;
+  const int ty_i = (L / ntx) % nty;
+  const int tz_i = L / (ntx * nty);
+  const int x0 = tx_i * kTX, y0 = ty_i * kTY, z0 = tz_i * kTZ;
+  const int z1 = min(z0 + kTZ, nz);
+  const int tid = threadIdx.x;
+  const int tx = tid & 63, ty = tid >> 6;
+  const size_t plane = size_t(nx) * ny;
+
+  // element e of the (kLY x kLX) tile -> global (gx, gy) with ghost rules;
+  // returns -1 for a zero value
+  int src_off[kLoads];
+#pragma unroll
+  for (int i = 0; i < kLoads; ++i) {
+    const int e = tid + i * kThreads;
+    int off = -1;
+    if (e < kLX * kLY) {
+      const int r = e / kLX, c = e - r * kLX;
+      int gx = x0 - 1 + c, gy = y0 - 1 + r;
+      bool ok = true;
+      if (gx < 0) { if (xmir) gx = 1; else ok = false; }
+      else if (gx == nx) { if (xmir) gx = nx - 2; else ok = false; }
+      else if (gx > nx) ok = false;
+      if (gy < 0) { if (ymir) gy = 1; else ok = false; }
+      else if (gy == ny) { if (ymir) gy = ny - 2; else ok = false; }
+      else if (gy > ny) ok = false;
+      if (ok) off = gx + nx * gy;
+    }
+    src_off[i] = off;
+  }
+
+  auto load_plane = [&](int p, double2 (&v)[kLoads]) {
+#pragma unroll
+    for (int i = 0; i < kLoads; ++i) {
+      v[i] = make_double2(0.0, 0.0);
+      if (p >= 0 && p < nz && src_off[i] >= 0) v[i] = x[size_t(p) * plane + src_off[i]];
+    }
+  };
+  auto store_plane = [&](int b, const double2 (&v)[kLoads]) {
+#pragma unroll
+    for (int i = 0; i < kLoads; ++i) {
+      const int e = tid + i * kThreads;
+      if (e < kLX * kLY) (&tile[b][0][0])[e] = v[i];
+    }
+  };
+
+  auto row_type = [&](int l) { return (l == 0 && zlo_cl) ? 1 : ((l == nz - 1 && zhi_cl) ? 2 : 0); };
+
+  double2 acc_a[2], acc_b[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) acc_a[s] = acc_b[s] = make_double2(0.0, 0.0);
+  double nrm = 0.0;
+
+  double2 v[kLoads];
+  load_plane(z0 - 1, v);
+  store_plane(0, v);
+  __syncthreads();
+
+  const int nplanes = z1 - z0 + 2;
+  for (int it = 0; it < nplanes; ++it) {
+    const int p = z0 - 1 + it;
+    const bool more = it + 1 < nplanes;
+    if (more) load_plane(p + 1, v);
+    const int b = it & 1;
+    // row types of the three rows this plane feeds (uniform across the block)
+    const W9 w_prev = W->w[row_type(p - 1)][2];
+    const W9 w_cur = W->w[row_type(p)][1];
+    const W9 w_next = W->w[row_type(p + 1)][0];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int r = ty + 4 * s + 1, c = tx + 1;
+      S3 S;
+      S.c = tile[b][r][c];
+      S.e = add2(add2(tile[b][r][c - 1], tile[b][r][c + 1]), add2(tile[b][r - 1][c], tile[b][r + 1][c]));
+      S.k = add2(add2(tile[b][r - 1][c - 1], tile[b][r - 1][c + 1]),
+                 add2(tile[b][r + 1][c - 1], tile[b][r + 1][c + 1]));
+      // row p-1 receives its +1 plane and is complete
+      if (p - 1 >= z0) {
+        apply_w(acc_a[s], w_prev, S);
+        const int gx = x0 + tx, gy = y0 + ty + 4 * s;
+        if (gx < nx && gy < ny) {
+          const size_t o = size_t(p - 1) * plane + gx + size_t(nx) * gy;
+          double2 out = acc_a[s];
+          if (RESID) {
+            const double2 f = F[o];
+            out = make_double2(f.x - out.x, f.y - out.y);
+            nrm = fma(out.x, out.x, fma(out.y, out.y, nrm));
+          }
+          y[o] = out;
+        }
+      }
+      acc_a[s] = acc_b[s];
+      apply_w(acc_a[s], w_cur, S);
+      acc_b[s] = make_double2(0.0, 0.0);
+      apply_w(acc_b[s], w_next, S);
+    }
+    if (more) store_plane(b ^ 1, v);
+    __syncthreads();
+  }
+
+  if (RESID) {
+    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_down(nrm, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = nrm;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+      partials[blockIdx.x] = t;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
+                          double* partials, int* nparts, hipStream_t s) {
+  const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
+  const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
+  const int nwg = ntx * nty * ntz;
+  const bool resid = F != nullptr;
+  if (resid && nwg > kMaxPartials) return hipErrorInvalidValue;
+  hipEvent_t ev;
+  timing_begin(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, &ev);
+  if (resid)
+    hipLaunchKernelGGL(stencil_kernel<true>, dim3(nwg), dim3(kThreads), 0, s, x, y, F, partials,
+                       P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
+                       P->zhi_closure, ntx, nty, nwg);
+  else
+    hipLaunchKernelGGL(stencil_kernel<false>, dim3(nwg), dim3(kThreads), 0, s, x, y, nullptr,
+                       nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
+                       P->zlo_closure, P->zhi_closure, ntx, nty, nwg);
+  timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev);
+  if (nparts) *nparts = nwg;
+  return hipGetLastError();
+}
+
+}  // namespace h6

@@ -1,0 +1,193 @@
+"""Python binding of the helmholtz6 C ABI (include/helmholtz6.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Vectors are torch complex128 tensors on the GPU, contiguous, of
+shape (n'z, n'y, n'x) (x fastest); PyTorch supplies device memory and the
+current HIP stream.  If the compiled library is missing this module raises at
+import time; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelmholtz6.so")
+
+H6_OK, H6_NOT_CONVERGED, H6_DIVERGED = 0, 1, 2
+H6_ERR_ARG, H6_ERR_UNSUPPORTED_BC, H6_ERR_ALLOC, H6_ERR_HIP, H6_ERR_SINGULAR = -1, -2, -3, -4, -5
+BC_CODES = {"D": 0, "N": 1, "S": 2}
+METHODS = {"gmres": 0, "fgmres": 1, "sks": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm",
+                  "axpy", "rhs")
+
+EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
+            "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
+            "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
+            "helmholtz6_last_error")
+
+
+class H6Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double), ("k_re", ctypes.c_double),
+                ("k_im", ctypes.c_double), ("bc", ctypes.c_int * 6), ("precision", ctypes.c_int)]
+
+
+class H6SolveInfo(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("tol", ctypes.c_double), ("iters", ctypes.c_int), ("rel_resid", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"helmholtz6 HIP library not found at {path}; build it with "
+                           "`python -m paper_1212_1397_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, ip = ctypes.c_void_p, ctypes.c_int
+    lib.helmholtz6_setup.argtypes = [ctypes.POINTER(H6Params), vp, ctypes.POINTER(vp)]
+    lib.helmholtz6_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.helmholtz6_apply_A.argtypes = [vp, vp, vp, vp]
+    lib.helmholtz6_apply_Pinv.argtypes = [vp, vp, vp, vp]
+    lib.helmholtz6_rhs_gaussians.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp]
+    lib.helmholtz6_solve.argtypes = [vp, vp, vp, ctypes.POINTER(H6SolveInfo), vp]
+    lib.helmholtz6_profile.argtypes = [vp, ip]
+    lib.helmholtz6_kernel_time.argtypes = [vp, ctypes.c_char_p, ip, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_longlong)]
+    lib.helmholtz6_destroy.argtypes = [vp]
+    lib.helmholtz6_destroy.restype = None
+    lib.helmholtz6_status_string.argtypes = [ip]
+    lib.helmholtz6_status_string.restype = ctypes.c_char_p
+    lib.helmholtz6_last_error.argtypes = [vp]
+    lib.helmholtz6_last_error.restype = ctypes.c_char_p
+    for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
+                 "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
+                 "helmholtz6_kernel_time"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+class H6Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"helmholtz6 status {status}: {msg}")
+        self.status = status
+
+
+def _stream_handle(stream=None):
+    if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(None)     # legacy default stream (argument checks only)
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A solver plan for one grid, wavenumber and face pattern (helmholtz6_setup)."""
+
+    def __init__(self, n, h: float, k: complex, bc: str = "DDDDDD", precision: str = "fp64",
+                 stream=None):
+        if isinstance(n, int):
+            n = (n, n, n)
+        p = H6Params()
+        for a in range(3):
+            p.n[a] = int(n[a])
+        p.h = float(h)
+        k = complex(k)
+        p.k_re, p.k_im = k.real, k.imag
+        for f, c in enumerate(bc):
+            p.bc[f] = BC_CODES[c]
+        p.precision = PRECISIONS[precision]
+        self._plan = ctypes.c_void_p()
+        st = _lib.helmholtz6_setup(ctypes.byref(p), _stream_handle(stream), ctypes.byref(self._plan))
+        if st != H6_OK:
+            raise H6Error(st, _lib.helmholtz6_last_error(None).decode())
+        dims = (ctypes.c_int * 3)()
+        _lib.helmholtz6_dims(self._plan, dims)
+        self.dims = tuple(dims)
+        self.n, self.h, self.k, self.bc, self.precision = tuple(n), float(h), k, bc, precision
+
+    @property
+    def shape(self):
+        return (self.dims[2], self.dims[1], self.dims[0])
+
+    def _check(self, st):
+        if st < 0:
+            raise H6Error(st, _lib.helmholtz6_last_error(self._plan).decode())
+        return st
+
+    def _vec(self, t, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
+                and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=torch.complex128, device="cuda")
+
+    def apply_A(self, x, out=None, stream=None):
+        out = self.empty() if out is None else out
+        self._check(_lib.helmholtz6_apply_A(self._plan, self._vec(x, "x"), self._vec(out, "out"),
+                                           _stream_handle(stream)))
+        return out
+
+    def apply_Pinv(self, r, out=None, stream=None):
+        out = self.empty() if out is None else out
+        self._check(_lib.helmholtz6_apply_Pinv(self._plan, self._vec(r, "r"), self._vec(out, "out"),
+                                              _stream_handle(stream)))
+        return out
+
+    def rhs_gaussians(self, centres, amps, sigma: float, out=None, stream=None):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+        a = np.asarray(amps, dtype=np.complex128).reshape(-1)
+        ab = np.ascontiguousarray(np.stack([a.real, a.imag], 1))
+        out = self.empty() if out is None else out
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(_lib.helmholtz6_rhs_gaussians(
+            self._plan, int(c.shape[0]), c.ctypes.data_as(dp), ab.ctypes.data_as(dp), float(sigma),
+            self._vec(out, "out"), _stream_handle(stream)))
+        return out
+
+    def solve(self, F, U=None, method="gmres", restart=30, maxit=1000, tol=1e-10, history=512,
+              stream=None):
+        """Solve A U = F (U: initial guess, overwritten).  Returns (U, info dict)."""
+        U = torch.zeros_like(F) if U is None else U
+        hist = (ctypes.c_double * max(history, 1))()
+        info = H6SolveInfo(METHODS[method], int(restart), int(maxit), float(tol), 0, 0.0,
+                           ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(history))
+        st = self._check(_lib.helmholtz6_solve(self._plan, self._vec(F, "F"), self._vec(U, "U"),
+                                               ctypes.byref(info), _stream_handle(stream)))
+        status = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}[st]
+        return U, dict(status=status, iters=info.iters, rel_resid=info.rel_resid,
+                       history=list(hist[:info.history_len]))
+
+    def profile(self, enable: bool = True):
+        self._check(_lib.helmholtz6_profile(self._plan, int(enable)))
+
+    def kernel_time(self, name: str, reset: bool = False):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        self._check(_lib.helmholtz6_kernel_time(self._plan, name.encode(), int(reset), ctypes.byref(ms),
+                                                ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_plan", None) and self._plan.value:
+            _lib.helmholtz6_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def status_string(status: int) -> str:
+    return _lib.helmholtz6_status_string(int(status)).decode()

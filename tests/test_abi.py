@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every symbol of include/helmholtz6.h and
+rejects invalid plans before touching the GPU (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1212_1397_amd", "libhelmholtz6.so")
+HEADER = os.path.join(ROOT, "include", "helmholtz6.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(helmholtz6_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("helmholtz6_setup", "helmholtz6_apply_A", "helmholtz6_apply_Pinv", "helmholtz6_solve",
+              "helmholtz6_destroy", "helmholtz6_dims", "helmholtz6_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import torch  # noqa: F401  (the library shares torch's HIP runtime)
+    lib = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_binding_lists_every_symbol():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    assert sorted(h6.EXPORTED) == declared_functions()
+
+
+def test_status_strings():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    for st in (0, 1, 2, -1, -2, -3, -4, -5):
+        assert h6.status_string(st) and h6.status_string(st) != "unknown status"
+
+
+@pytest.mark.parametrize("bc,status", [("SSDDDD", -2), ("DDSSDD", -2), ("DNDDDD", -2), ("DDNDDD", -2)])
+def test_unsupported_faces_rejected(bc, status):
+    from paper_1212_1397_amd import helmholtz6 as h6
+    with pytest.raises(h6.H6Error) as e:
+        h6.Plan(8, 1 / 9, 3.0, bc)
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("kw", [dict(n=0, h=0.1), dict(n=4, h=-1.0), dict(n=4, h=float("nan")),
+                                dict(n=4, h=0.2, k=float("inf"))])
+def test_invalid_arguments_rejected(kw):
+    from paper_1212_1397_amd import helmholtz6 as h6
+    k = kw.pop("k", 1.0)
+    with pytest.raises(h6.H6Error) as e:
+        h6.Plan(kw["n"], kw["h"], k)
+    assert e.value.status == -1
+
+
+def test_singular_preconditioner_rejected_at_setup():
+    """k^2 h^2 = 12 sin^2(pi h / 2): the (1,1,1) mode of A_p vanishes (host-side check)."""
+    import math
+    from paper_1212_1397_amd import helmholtz6 as h6
+    n = 8
+    h = 1.0 / (n + 1)
+    k = math.sqrt(12.0 * math.sin(math.pi * h / 2) ** 2) / h
+    with pytest.raises(h6.H6Error) as e:
+        h6.Plan(n, h, k)
+    assert e.value.status == -5
