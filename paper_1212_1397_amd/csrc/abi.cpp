@@ -1,6 +1,7 @@
 // C ABI of the helmholtz6 library: parameter validation, plan construction
 // (coefficients of Section 3.1-3.3), workspace, status strings and timing.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -150,8 +151,75 @@ bool singular_modes(h6_plan P, const std::vector<double>& lx, const std::vector<
   return false;
 }
 
+// Tables of the Rader path for a prime M with M - 1 = 256 (xform_rader.hip).
+hipError_t build_rader(AxisXform& ax, hipStream_t s) {
+  const int M = ax.M, P1 = M - 1;
+  auto powmod = [M](long long b, long long e) {
+    long long r = 1;
+    b %= M;
+    while (e > 0) {
+      if (e & 1) r = r * b % M;
+      b = b * b % M;
+      e >>= 1;
+    }
+    return int(r);
+  };
+  int g = 2;                                   // primitive root: g^((M-1)/2) != 1 (M-1 = 2^8)
+  while (powmod(g, P1 / 2) == 1) ++g;
+  const int ginv = powmod(g, M - 2);
+  std::vector<int> pin(P1), pout(P1);
+  for (int a = 0; a < P1; ++a) {
+    pin[a] = powmod(ginv, a);
+    pout[a] = powmod(g, a);
+  }
+  std::vector<double2> kf(P1), tw(256);
+  for (int k = 0; k < P1; ++k) {
+    long double re = 0.0L, im = 0.0L;
+    for (int c = 0; c < P1; ++c) {
+      // K[c] = exp(-2 pi i g^c / M), times exp(-2 pi i c k / (M-1))
+      const long double ang = -2.0L * M_PIl * ((long double)pout[c] / M + (long double)((c * (long long)k) % P1) / P1);
+      re += cosl(ang);
+      im += sinl(ang);
+    }
+    kf[k] = make_double2(double(re / P1), double(im / P1));
+  }
+  for (int t = 0; t < 256; ++t)
+    tw[t] = make_double2(std::cos(-2.0 * M_PI * t / 256.0), std::sin(-2.0 * M_PI * t / 256.0));
+  std::vector<double> sq(M + 1), cq(M + 1);
+  for (int q = 0; q <= M; ++q) {
+    sq[q] = std::sin(M_PI * q / M);
+    cq[q] = std::cos(M_PI * q / M);
+  }
+  const size_t bytes = 2 * P1 * sizeof(int) + 2 * P1 * sizeof(double2) + 2 * (M + 1) * sizeof(double) + 256;
+  char* mem = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&mem), bytes + 64);
+  if (e != hipSuccess) return e;
+  ax.rader_mem = mem;
+  std::vector<char> host(bytes + 64, 0);
+  size_t off = 0;
+  auto put = [&](const void* src, size_t n) {
+    off = (off + 15) & ~size_t(15);
+    std::memcpy(host.data() + off, src, n);
+    const size_t at = off;
+    off += n;
+    return mem + at;
+  };
+  ax.rader.kf = reinterpret_cast<const double2*>(put(kf.data(), P1 * sizeof(double2)));
+  ax.rader.tw256 = reinterpret_cast<const double2*>(put(tw.data(), 256 * sizeof(double2)));
+  ax.rader.sin_q = reinterpret_cast<const double*>(put(sq.data(), (M + 1) * sizeof(double)));
+  ax.rader.cos_q = reinterpret_cast<const double*>(put(cq.data(), (M + 1) * sizeof(double)));
+  ax.rader.perm_in = reinterpret_cast<const int*>(put(pin.data(), P1 * sizeof(int)));
+  ax.rader.perm_out = reinterpret_cast<const int*>(put(pout.data(), P1 * sizeof(int)));
+  if (off > bytes + 64) return hipErrorInvalidValue;
+  e = hipMemcpyAsync(mem, host.data(), off, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  ax.fast = 1;
+  return hipStreamSynchronize(s);
+}
+
 void free_plan(h6_plan P) {
   if (!P) return;
+  for (auto& a : P->ax) (void)hipFree(a.rader_mem);
   (void)hipFree(P->d_stencil);
   (void)hipFree(P->d_lambda_x);
   (void)hipFree(P->d_lambda_y);
@@ -245,6 +313,8 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   if (e == hipSuccess) e = upload(&P->d_trig_x, trig_table(P->ax[0].M), s);
   if (e == hipSuccess) e = upload(&P->d_trig_y, trig_table(P->ax[1].M), s);
   if (e == hipSuccess) e = upload(&P->d_tri, tri, s);
+  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+    if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
   const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
   for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMalloc(&P->w_pc[i], P->N * elem);
   if (e == hipSuccess) e = hipMalloc(&P->partials, sizeof(double) * 2 * kMaxPartials);

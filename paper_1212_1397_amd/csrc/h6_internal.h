@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/helmholtz6.h"
+#include "xform_rader.h"
 
 namespace h6 {
 
@@ -49,6 +50,9 @@ struct AxisXform {
   int L = 0;        // unknowns on the axis (n for D, n + 2 for N)
   int M = 0;        // n + 1
   int neumann = 0;  // 0: DST-I pair, 1: DCT-I pair
+  int fast = 0;     // 1: Rader FFT path (M = 257), 0: dense sums in LDS
+  RaderTables rader{};
+  void* rader_mem = nullptr;   // one device allocation holding the tables
 };
 
 struct Timing {

@@ -11,6 +11,8 @@
 //
 // Compute type R is double (FP64 plans) or float (mixed plans, complex64
 // intermediates); the input r and output z are complex128 in both.
+#include <type_traits>
+
 #include "h6_internal.h"
 
 namespace h6 {
@@ -204,27 +206,35 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
   const dim3 gx((nlines_x + kXLines - 1) / kXLines), gy((nx + kYCols - 1) / kYCols, nz);
   hipEvent_t ev;
 
-  timing_begin(P, KC_XFORM_X, s, &ev);
-  hipLaunchKernelGGL((xform_x_kernel<double2, T2, R>), gx, dim3(256), shx, s, r, w0, nlines_x,
-                     X.L, X.M, X.neumann, 0, P->d_trig_x);
-  timing_end(P, KC_XFORM_X, s, ev);
-  timing_begin(P, KC_XFORM_Y, s, &ev);
-  hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, w0, w1, nx, Y.L, Y.M,
-                     Y.neumann, 0, P->d_trig_y);
-  timing_end(P, KC_XFORM_Y, s, ev);
+  auto xform_x = [&](bool inv, auto* src, auto* dst) {
+    timing_begin(P, KC_XFORM_X, s, &ev);
+    if (X.fast)
+      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s);
+    else
+      hipLaunchKernelGGL((xform_x_kernel<std::remove_cv_t<std::remove_pointer_t<decltype(src)>>,
+                                         std::remove_pointer_t<decltype(dst)>, R>),
+                         gx, dim3(256), shx, s, src, dst, nlines_x, X.L, X.M, X.neumann, inv ? 1 : 0,
+                         P->d_trig_x);
+    timing_end(P, KC_XFORM_X, s, ev);
+  };
+  auto xform_y = [&](bool inv, const T2* src, T2* dst) {
+    timing_begin(P, KC_XFORM_Y, s, &ev);
+    if (Y.fast)
+      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s);
+    else
+      hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, src, dst, nx, Y.L, Y.M,
+                         Y.neumann, inv ? 1 : 0, P->d_trig_y);
+    timing_end(P, KC_XFORM_Y, s, ev);
+  };
+  xform_x(false, r, w0);
+  xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
   hipLaunchKernelGGL((tridiag_z_kernel<R>), dim3((nx * ny + 255) / 256), dim3(256), 0, s, w1, w0,
                      w2, P->d_tri, P->d_lambda_x, P->d_lambda_y, P->kappa.real(),
                      P->kappa.imag(), nx, ny, nz);
   timing_end(P, KC_TRIDIAG, s, ev);
-  timing_begin(P, KC_XFORM_Y, s, &ev);
-  hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, w0, w1, nx, Y.L, Y.M,
-                     Y.neumann, 1, P->d_trig_y);
-  timing_end(P, KC_XFORM_Y, s, ev);
-  timing_begin(P, KC_XFORM_X, s, &ev);
-  hipLaunchKernelGGL((xform_x_kernel<T2, double2, R>), gx, dim3(256), shx, s, w1, z, nlines_x,
-                     X.L, X.M, X.neumann, 1, P->d_trig_x);
-  timing_end(P, KC_XFORM_X, s, ev);
+  xform_y(true, w0, w1);
+  xform_x(true, static_cast<const T2*>(w1), z);
   return hipGetLastError();
 }
 

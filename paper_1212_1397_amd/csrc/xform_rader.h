@@ -1,0 +1,27 @@
+// Fast transform path for the period parameter M = 257 (n = 256): device
+// tables and launchers (see xform_rader.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace h6 {
+
+struct RaderTables {
+  const int* perm_in;      // g^{-a} mod M, a = 0..M-2
+  const int* perm_out;     // g^{b} mod M,  b = 0..M-2
+  const double2* kf;       // FFT_{M-1} of w^{g^c} (w = e^{-2 pi i / M}), divided by M-1
+  const double2* tw256;    // e^{-2 pi i t / 256}
+  const double* sin_q;     // sin(pi q / M), q = 0..M
+  const double* cos_q;     // cos(pi q / M), q = 0..M
+};
+
+constexpr int kRaderM = 257;
+
+template <typename R, typename Tin, typename Tout>
+hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
+                          const RaderTables& tab, hipStream_t s);
+template <typename R, typename T>
+hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
+                          const RaderTables& tab, hipStream_t s);
+
+}  // namespace h6

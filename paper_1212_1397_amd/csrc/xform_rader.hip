@@ -1,0 +1,350 @@
+// Fast sine / cosine transforms of Section 3.3 for a prime period parameter
+// M with M - 1 = 256 (the 256^3 grids: n = 256, M = n + 1 = 257).
+//
+// Reduction to one complex DFT of length M per line.  For a line x of complex
+// values, with s_q = x_q + x_{M-q}, d_q = x_q - x_{M-q}, q = 1..M-1:
+//
+//  sine sum    S_m = sum_{q=1}^{M-1} x_q sin(pi q m / M), m = 1..M-1:
+//     y_q = s_q sin(pi q/M) + d_q,  Y = DFT_M(y),
+//     S_{2j}   = (i/4)(Y_j - Y_{M-j}),
+//     S_{2j+1} = Y_0/2 + sum_{i=1..j} (Y_i + Y_{M-i})/2;
+//  cosine sum  C_m = sum_{q=0}^{M} x_q cos(pi q m / M), m = 0..M:
+//     y_q = s_q + d_q sin(pi q/M),  Y = DFT_M(y),
+//     C_{2j}   = x_0 + x_M + (Y_j + Y_{M-j})/4,
+//     C_{2j+1} = x_0 - x_M + C'_1 - i sum_{i=1..j} (Y_i - Y_{M-i})/2,
+//     C'_1     = (1/2) sum_q d_q cos(pi q/M).
+// (Both follow from splitting y into its symmetric and antisymmetric parts,
+// whose DFTs are the cosine and (-i times) the sine sums, and from the
+// identities sin(a+b) - sin(a-b) = 2 cos a sin b, cos(a+b) - cos(a-b) =
+// -2 sin a sin b for the odd outputs.)
+//
+// DFT_M for prime M by Rader's algorithm: with a primitive root g of M,
+// Y_{g^b} = y_0 + sum_a y_{g^{-a}} w^{g^{b-a}} (w = e^{-2 pi i / M}), a cyclic
+// convolution of length M - 1 = 256, done as FFT_256 -> pointwise product
+// with the precomputed FFT of the kernel -> inverse FFT_256.  FFT_256 is the
+// four-step 16 x 16 algorithm: 16 threads per line, each holding 16 values in
+// registers; a radix-4 x 4 FFT16 per thread, twiddles, one LDS transpose.
+// Forward output order is kept for the pointwise product and undone by the
+// inverse, so the convolution costs two LDS transposes.
+//
+// Forward transforms apply W^{-1} ((2/M) sine sum, or (2/M) C W^T C for the
+// cosine basis, C = diag(1/2, 1, .., 1, 1/2)); inverse transforms apply W
+// (plain sums).  Lines are staged through LDS with coalesced loads/stores;
+// along x a workgroup owns kLines whole lines, along y a tile of kLines
+// consecutive x columns at one z.
+#include "h6_internal.h"
+#include "xform_rader.h"
+
+namespace h6 {
+namespace {
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+template <typename R>
+__device__ __forceinline__ typename V2<R>::T mk2(R a, R b) {
+  typename V2<R>::T v;
+  v.x = a;
+  v.y = b;
+  return v;
+}
+
+template <typename D, typename S>
+__device__ __forceinline__ D cv(S v) {
+  D d;
+  d.x = v.x;
+  d.y = v.y;
+  return d;
+}
+
+#define T2 typename V2<R>::T
+
+template <typename R>
+__device__ __forceinline__ T2 add(T2 a, T2 b) { return mk2<R>(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ T2 sub(T2 a, T2 b) { return mk2<R>(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ T2 mul(T2 a, T2 b) {
+  return mk2<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R>
+__device__ __forceinline__ T2 scl(T2 a, R s) { return mk2<R>(a.x * s, a.y * s); }
+
+// radix-4 butterfly; forward uses w4 = -i, inverse w4 = +i
+template <typename R, bool INV>
+__device__ __forceinline__ void fft4(T2& a0, T2& a1, T2& a2, T2& a3) {
+  const T2 s0 = add<R>(a0, a2), s1 = sub<R>(a0, a2), s2 = add<R>(a1, a3), d = sub<R>(a1, a3);
+  const T2 s3 = INV ? mk2<R>(-d.y, d.x) : mk2<R>(d.y, -d.x);
+  a0 = add<R>(s0, s2);
+  a2 = sub<R>(s0, s2);
+  a1 = add<R>(s1, s3);
+  a3 = sub<R>(s1, s3);
+}
+
+// In-register FFT of length 16 (natural order in and out), 16 = 4 x 4.
+template <typename R, bool INV>
+__device__ __forceinline__ void fft16(T2 (&v)[16]) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+  constexpr double c2 = 0.70710678118654752440;
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) fft4<R, INV>(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+  // twiddles w16^{n1 k2} on element n1 + 4 k2; w16 = e^{-+ 2 pi i / 16}
+  const R sg = INV ? R(1) : R(-1);
+  const T2 w1 = mk2<R>(R(c1), sg * R(s1)), w2 = mk2<R>(R(c2), sg * R(c2)),
+           w3 = mk2<R>(R(s1), sg * R(c1)), w6 = mk2<R>(-R(c2), sg * R(c2)),
+           w9 = mk2<R>(-R(c1), -sg * R(s1));
+  const T2 w4 = mk2<R>(R(0), sg);
+  v[1 + 4 * 1] = mul<R>(v[1 + 4 * 1], w1);
+  v[1 + 4 * 2] = mul<R>(v[1 + 4 * 2], w2);
+  v[1 + 4 * 3] = mul<R>(v[1 + 4 * 3], w3);
+  v[2 + 4 * 1] = mul<R>(v[2 + 4 * 1], w2);
+  v[2 + 4 * 2] = mul<R>(v[2 + 4 * 2], w4);
+  v[2 + 4 * 3] = mul<R>(v[2 + 4 * 3], w6);
+  v[3 + 4 * 1] = mul<R>(v[3 + 4 * 1], w3);
+  v[3 + 4 * 2] = mul<R>(v[3 + 4 * 2], w6);
+  v[3 + 4 * 3] = mul<R>(v[3 + 4 * 3], w9);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) fft4<R, INV>(v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]);
+  // X[4 k1 + k2] sits at v[k1 + 4 k2]: transpose the 4 x 4 index grid
+  T2 t[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[4 * k1 + k2] = v[k1 + 4 * k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+constexpr int kLines = 8;          // lines per workgroup (16 threads each)
+constexpr int kStride = 273;       // LDS row stride (complex) per line, >= 258 and >= 16*17
+constexpr int kHalf = 128;         // (M - 1) / 2
+
+template <typename R, int AXIS, bool NEU, bool INV, typename Tin, typename Tout>
+__global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __restrict__ in,
+                                                               Tout* __restrict__ out, int nlines,
+                                                               int nx, int L, RaderTables tab) {
+  __shared__ T2 buf[kLines][kStride];
+  constexpr int M = 257;
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, t = tid & 15;
+  // ---- load kLines lines into LDS (coalesced) ----
+  int line0, nl;
+  size_t gbase;            // AXIS 0: first element of line0; AXIS 1: (z, i0) offset
+  if (AXIS == 0) {
+    line0 = blockIdx.x * kLines;
+    nl = min(kLines, nlines - line0);
+    gbase = size_t(line0) * L;
+    for (int e = tid; e < nl * L; e += kLines * 16) {
+      const int b = e / L, q = e - b * L;
+      buf[b][q] = cv<T2>(in[gbase + e]);
+    }
+  } else {
+    line0 = blockIdx.x * kLines;          // x column i0
+    nl = min(kLines, nx - line0);
+    gbase = size_t(blockIdx.y) * nx * L + line0;
+    for (int e = tid; e < kLines * L; e += kLines * 16) {
+      const int q = e / kLines, b = e - q * kLines;
+      if (b < nl) buf[b][q] = cv<T2>(in[gbase + size_t(q) * nx + b]);
+    }
+  }
+  __syncthreads();
+
+  // ---- gather y_{g^{-a}} (a = t + 16 n2) with the pre-processing ----
+  const int off = NEU ? 0 : -1;   // array index of node q is q + off
+  T2 v[16];
+  T2 y0sum = mk2<R>(0, 0), c1sum = mk2<R>(0, 0);
+  T2 xa = mk2<R>(0, 0), xb = mk2<R>(0, 0);  // x_0 and x_M (cosine sums)
+  if (NEU) {
+    xa = buf[g][0];
+    xb = buf[g][M];
+    if (!INV) {
+      xa = scl<R>(xa, R(0.5));
+      xb = scl<R>(xb, R(0.5));
+    }
+  }
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) {
+    const int q = tab.perm_in[t + 16 * n2];
+    const T2 xq = buf[g][q + off], xr = buf[g][M - q + off];
+    const T2 s = add<R>(xq, xr), d = sub<R>(xq, xr);
+    const R sn = R(tab.sin_q[q]);
+    T2 y;
+    if (NEU) {
+      y = add<R>(s, scl<R>(d, sn));
+      c1sum = add<R>(c1sum, scl<R>(d, R(0.5) * R(tab.cos_q[q])));
+    } else {
+      y = add<R>(scl<R>(s, sn), d);
+    }
+    y0sum = add<R>(y0sum, y);
+    v[n2] = y;
+  }
+  // group sums over the 16 threads of the line
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    y0sum.x += __shfl_xor(y0sum.x, o, 16);
+    y0sum.y += __shfl_xor(y0sum.y, o, 16);
+    if (NEU) {
+      c1sum.x += __shfl_xor(c1sum.x, o, 16);
+      c1sum.y += __shfl_xor(c1sum.y, o, 16);
+    }
+  }
+  __syncthreads();
+
+  // ---- forward FFT_256: thread t = n1 holds element n1 + 16 n2 in v[n2] ----
+  fft16<R, false>(v);                      // over n2 -> v[k2]
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    const T2 w = cv<T2>(tab.tw256[(t * k2) & 255]);
+    buf[g][17 * t + k2] = mul<R>(v[k2], w);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = buf[g][17 * n1 + t];   // thread t = k2
+  fft16<R, false>(v);                      // over n1 -> X[16 k1 + k2] in v[k1]
+  // pointwise product with the kernel spectrum (1/256 folded in), then
+  // inverse FFT_256 back to the natural index
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) v[k1] = mul<R>(v[k1], cv<T2>(tab.kf[16 * k1 + t]));
+  fft16<R, true>(v);                       // over k1 -> Z[n1][k2] in v[n1]
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const double2 w = tab.tw256[(n1 * t) & 255];
+    buf[g][17 * n1 + t] = mul<R>(v[n1], mk2<R>(R(w.x), -R(w.y)));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) v[k2] = buf[g][17 * t + k2];   // thread t = n1
+  fft16<R, true>(v);                       // -> conv[n1 + 16 n2] in v[n2]
+  __syncthreads();
+  // Y_{g^b} = conv[b]; Y_0 = sum y
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) buf[g][tab.perm_out[t + 16 * n2]] = v[n2];
+  if (t == 0) buf[g][0] = y0sum;
+  __syncthreads();
+
+  // ---- post-processing: j = 0..128, 9 consecutive j per thread ----
+  const int jb = 9 * t, je = min(jb + 9, kHalf + 1);
+  T2 pre = mk2<R>(0, 0);                   // local sums of the odd-output increments
+  T2 inc[9];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const int j = jb + u;
+    inc[u] = mk2<R>(0, 0);
+    if (j < je && j >= 1) {
+      const T2 Yj = buf[g][j], Ym = buf[g][M - j];
+      inc[u] = NEU ? scl<R>(sub<R>(Yj, Ym), R(0.5)) : scl<R>(add<R>(Yj, Ym), R(0.5));
+      pre = add<R>(pre, inc[u]);
+    }
+  }
+  // exclusive scan of the per-thread totals across the 16 threads
+  T2 scan = pre;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const R px = __shfl_up(scan.x, o, 16), py = __shfl_up(scan.y, o, 16);
+    if (t >= o) { scan.x += px; scan.y += py; }
+  }
+  T2 run = sub<R>(scan, pre);
+  T2 ev[9], od[9];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const int j = jb + u;
+    run = add<R>(run, inc[u]);
+    if (j < je) {
+      const T2 Yj = buf[g][j == 0 ? 0 : j], Ym = buf[g][j == 0 ? 0 : M - j];
+      if (NEU) {
+        // C_{2j} and C_{2j+1}
+        const T2 A = (j == 0) ? Yj : scl<R>(add<R>(Yj, Ym), R(0.5));
+        ev[u] = add<R>(add<R>(xa, xb), scl<R>(A, R(0.5)));
+        // C'_{2j+1} = C'_1 - i * run
+        od[u] = add<R>(sub<R>(xa, xb), add<R>(c1sum, mk2<R>(run.y, -run.x)));
+      } else {
+        // S_{2j} (j >= 1) and S_{2j+1} (j <= 127)
+        const T2 D = sub<R>(Yj, Ym);
+        ev[u] = mk2<R>(-R(0.25) * D.y, R(0.25) * D.x);
+        od[u] = add<R>(scl<R>(y0sum, R(0.5)), run);
+      }
+    }
+  }
+  __syncthreads();
+  // scaled outputs into LDS in natural order
+  const R fs = INV ? R(1) : R(2) / R(M);
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const int j = jb + u;
+    if (j >= je) continue;
+    if (NEU) {
+      const int me = 2 * j, mo = 2 * j + 1;              // m = 0..M
+      R se = fs, so = fs;
+      if (!INV && (me == 0 || me == M)) se *= R(0.5);
+      if (!INV && mo == M) so *= R(0.5);
+      buf[g][me] = scl<R>(ev[u], se);
+      if (mo <= M) buf[g][mo] = scl<R>(od[u], so);
+    } else {
+      if (j >= 1) buf[g][2 * j - 1] = scl<R>(ev[u], fs);     // m = 2j -> index 2j - 1
+      if (2 * j + 1 <= M - 2) buf[g][2 * j] = scl<R>(od[u], fs);   // m = 2j + 1
+    }
+  }
+  __syncthreads();
+  // ---- store (coalesced) ----
+  if (AXIS == 0) {
+    for (int e = tid; e < nl * L; e += kLines * 16) {
+      const int b = e / L, q = e - b * L;
+      out[gbase + e] = cv<Tout>(buf[b][q]);
+    }
+  } else {
+    for (int e = tid; e < kLines * L; e += kLines * 16) {
+      const int q = e / kLines, b = e - q * kLines;
+      if (b < nl) out[gbase + size_t(q) * nx + b] = cv<Tout>(buf[b][q]);
+    }
+  }
+}
+
+#undef T2
+
+template <typename R, int AXIS, bool NEU, typename Tin, typename Tout>
+void launch_one(bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
+                const RaderTables& tab, hipStream_t s) {
+  const dim3 grid = AXIS == 0 ? dim3((nlines + kLines - 1) / kLines) : dim3((nx + kLines - 1) / kLines, nz);
+  if (inv)
+    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, true, Tin, Tout>), grid, dim3(kLines * 16), 0,
+                       s, in, out, nlines, nx, L, tab);
+  else
+    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, false, Tin, Tout>), grid, dim3(kLines * 16), 0,
+                       s, in, out, nlines, nx, L, tab);
+}
+
+}  // namespace
+
+template <typename R, typename Tin, typename Tout>
+hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
+                          const RaderTables& tab, hipStream_t s) {
+  if (neumann)
+    launch_one<R, 0, true>(inverse, in, out, nlines, 0, L, 0, tab, s);
+  else
+    launch_one<R, 0, false>(inverse, in, out, nlines, 0, L, 0, tab, s);
+  return hipGetLastError();
+}
+
+template <typename R, typename T>
+hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
+                          const RaderTables& tab, hipStream_t s) {
+  if (neumann)
+    launch_one<R, 1, true>(inverse, in, out, 0, nx, L, nz, tab, s);
+  else
+    launch_one<R, 1, false>(inverse, in, out, 0, nx, L, nz, tab, s);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rader_x<double, double2, double2>(bool, bool, const double2*, double2*,
+                                                             int, int, const RaderTables&, hipStream_t);
+template hipError_t launch_rader_x<float, double2, float2>(bool, bool, const double2*, float2*, int,
+                                                           int, const RaderTables&, hipStream_t);
+template hipError_t launch_rader_x<float, float2, double2>(bool, bool, const float2*, double2*, int,
+                                                           int, const RaderTables&, hipStream_t);
+template hipError_t launch_rader_y<double, double2>(bool, bool, const double2*, double2*, int, int,
+                                                    int, const RaderTables&, hipStream_t);
+template hipError_t launch_rader_y<float, float2>(bool, bool, const float2*, float2*, int, int, int,
+                                                  const RaderTables&, hipStream_t);
+
+}  // namespace h6

@@ -43,6 +43,9 @@ SMALL_CASES = [
     ((17, 12, 19), 4.0 + 1.0j, "DDNNDS"),
     ((1, 1, 1), 2.0, "DDDDDD"),
     ((1, 2, 1), 2.0 + 0.5j, "NNNNSS"),
+    # n = 256 on x and y: the M = 257 FFT (Rader) transform path, both bases
+    ((256, 256, 3), 30.0 + 0.3j, "DDNNSS"),
+    ((256, 256, 2), 25.0, "NNDDDN"),
 ]
 
 
