@@ -277,6 +277,11 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   for (int a = 0; a < 3; ++a)
     P->dims[a] = p->n[a] + (p->bc[2 * a] != H6_DIRICHLET) + (p->bc[2 * a + 1] != H6_DIRICHLET);
   P->N = size_t(P->dims[0]) * P->dims[1] * P->dims[2];
+  if (P->dims[2] > kMaxZ) {
+    err = "n'z = " + std::to_string(P->dims[2]) + " exceeds the z-solver limit of " + std::to_string(kMaxZ);
+    free_plan(P);
+    return H6_ERR_ARG;
+  }
   if (P->N > (size_t(1) << 31)) { err = "grid too large"; free_plan(P); return H6_ERR_ARG; }
   P->xmirror = p->bc[0] == H6_NEUMANN;
   P->ymirror = p->bc[2] == H6_NEUMANN;
@@ -316,7 +321,7 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   for (int a = 0; a < 2 && e == hipSuccess; ++a)
     if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
   const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
-  for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipMalloc(&P->w_pc[i], P->N * elem);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&P->w_pc[i], P->N * elem);
   if (e == hipSuccess) e = hipMalloc(&P->partials, sizeof(double) * 2 * kMaxPartials);
   if (e == hipSuccess) e = hipMalloc(&P->d_scal, sizeof(double2) * kScal);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), sizeof(double2) * kScal);

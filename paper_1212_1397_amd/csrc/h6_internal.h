@@ -85,7 +85,7 @@ struct h6_plan_s {
   double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
 
   // preconditioner workspace (complex128 vectors, or complex64 in mixed plans)
-  void* w_pc[3] = {nullptr, nullptr, nullptr};
+  void* w_pc[3] = {nullptr, nullptr, nullptr};   // two used
 
   // Krylov workspace (allocated on first solve, grown as needed)
   double2* V = nullptr;   int V_cols = 0;      // (m+1) basis vectors
@@ -93,7 +93,7 @@ struct h6_plan_s {
   double2* r = nullptr;                        // residual / scratch vector
   double2* t = nullptr;                        // scratch vector
   double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
-  double2* d_scal = nullptr;                   // device scalars: h column, norms (kScal entries)
+  double2* d_scal = nullptr;                   // device scalars: reduction results, coefficients (kScal entries)
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
 
   h6::Timing timing;
@@ -104,7 +104,8 @@ namespace h6 {
 
 constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
 constexpr int kMaxPartials = 1 << 20;
-constexpr int kScal = 1024;        // device scalar slots
+constexpr int kScal = 4096;        // device scalar slots (double2)
+constexpr int kMaxZ = 16 * 33;     // largest n'z of the partitioned z solver
 
 // kernel launchers (stream-ordered, no synchronisation)
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
@@ -113,18 +114,15 @@ hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s);
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
 
-// Krylov helpers (double2 vectors of length P->N)
-hipError_t launch_dot_partials(const double2* a, const double2* b, size_t n, double* partials,
-                               hipStream_t s);                     // sum conj(a) b
-hipError_t launch_mgs_step(double2* w, const double2* vprev, const double2* hprev,
-                           const double2* vcur, size_t n, double* partials, hipStream_t s);
-hipError_t launch_norm2_partials(const double2* a, size_t n, double* partials, hipStream_t s);
-hipError_t launch_reduce(const double* partials, int nparts, int ncomp, double2* out,
-                         hipStream_t s);
-hipError_t launch_axpy_norm(double2* w, const double2* v, const double2* h, size_t n,
-                            double* partials, hipStream_t s);   // w -= h v; partial |w|^2
-hipError_t launch_scale_inv_norm(double2* v, const double2* src, const double2* nrm, size_t n,
-                                 hipStream_t s);                 // v = src / sqrt(nrm.x)
+// Krylov helpers (double2 vectors of length P->N); reductions end in device doubles
+hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s);
+hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
+// out[4i..4i+3] = (<q_i, w>, <q_i, qn>) for i < m, q_i = Q + i n
+hipError_t launch_block_dots(const double2* Q, int m, const double2* w, const double2* qn, size_t n,
+                             double* partials, double* out, hipStream_t s);
+// w -= sum_{i<m} c_i q_i; out[0] = |w|^2
+hipError_t launch_update_norm(double2* w, const double2* Q, const double2* c, int m, size_t n,
+                              double* partials, double* out, hipStream_t s);
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
                              int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
 hipError_t launch_add(double2* U, const double2* z, size_t n, hipStream_t s);   // U += z

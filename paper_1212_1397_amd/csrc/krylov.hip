@@ -1,10 +1,17 @@
-// Vector kernels of the Krylov loops (GMRES Arnoldi with modified
-// Gram-Schmidt, cycle updates, SKS updates), complex128.
+// Vector kernels of the Krylov loops, complex128.
+//
+// GMRES orthogonalisation is modified Gram-Schmidt written in its inverse
+// compact WY form: for a new vector w and an (unnormalised) basis Q, one pass
+// forms all inner products <q_i, w> together with the inner products of the
+// newest basis vector with the older ones; the host turns them into the MGS
+// coefficients (a small triangular solve with the Gram matrix), and one more
+// pass applies w -= sum_i c_i q_i and forms |w|^2.  This moves (2j + 3)
+// vectors per Arnoldi step instead of (4j + 5) for the one-projection-per-
+// pass form, with the same coefficients in exact arithmetic.
 //
 // Reductions are deterministic: a fixed grid of kRedBlocks blocks writes one
-// partial per block (grid-stride order fixed), and a single-block kernel sums
-// the partials in a fixed tree order.  The inner products stay on the device;
-// only Hessenberg columns and residual norms are copied to the host.
+// partial per block and component (grid-stride order fixed), and a second
+// kernel sums each component's partials in a fixed tree order.
 #include "h6_internal.h"
 
 namespace h6 {
@@ -17,92 +24,96 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
-// Block-level sum of (a, b) into partials[2*blockIdx.x + {0,1}].
-__device__ __forceinline__ void block_store2(double a, double b, double* partials) {
-  __shared__ double sa[kThreads / 64], sb[kThreads / 64];
-  a = warp_sum(a);
-  b = warp_sum(b);
+// Block sum of NV per-thread values; partials laid out [component][block].
+template <int NV>
+__device__ __forceinline__ void block_store(double (&v)[NV], double* partials, int comp0,
+                                            int nblocks) {
+  __shared__ double s[kThreads / 64][NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = warp_sum(v[c]);
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { sa[w] = a; sb[w] = b; }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) s[w][c] = v[c];
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int i = 0; i < kThreads / 64; ++i) { ta += sa[i]; tb += sb[i]; }
-    partials[2 * blockIdx.x] = ta;
-    partials[2 * blockIdx.x + 1] = tb;
+  for (int c = threadIdx.x; c < NV; c += kThreads) {
+    double t = 0.0;
+    for (int i = 0; i < kThreads / 64; ++i) t += s[i][c];
+    partials[size_t(comp0 + c) * nblocks + blockIdx.x] = t;
   }
 }
 
-// partial sum of conj(a) * b
-__global__ __launch_bounds__(kThreads) void dot_kernel(const double2* __restrict__ a,
-                                                       const double2* __restrict__ b, size_t n,
-                                                       double* __restrict__ partials) {
-  double re = 0.0, im = 0.0;
+// |a|^2 partials (component 0)
+__global__ __launch_bounds__(kThreads) void norm2_kernel(const double2* __restrict__ a, size_t n,
+                                                         double* __restrict__ partials) {
+  double v[1] = {0.0};
   for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-    const double2 u = a[i], v = b[i];
-    re = fma(u.x, v.x, fma(u.y, v.y, re));
-    im = fma(u.x, v.y, fma(-u.y, v.x, im));
+    const double2 x = a[i];
+    v[0] = fma(x.x, x.x, fma(x.y, x.y, v[0]));
   }
-  block_store2(re, im, partials);
+  block_store<1>(v, partials, 0, gridDim.x);
 }
 
-// w -= h * vprev (if vprev), then partial conj(vcur) * w (if vcur) or |w|^2.
-__global__ __launch_bounds__(kThreads) void mgs_kernel(double2* __restrict__ w,
-                                                       const double2* __restrict__ vprev,
-                                                       const double2* __restrict__ hprev,
-                                                       const double2* __restrict__ vcur, size_t n,
-                                                       double* __restrict__ partials) {
-  double2 h = make_double2(0.0, 0.0);
-  if (vprev) h = *hprev;
-  double re = 0.0, im = 0.0;
-  for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-    double2 x = w[i];
-    if (vprev) {
-      const double2 v = vprev[i];
-      x.x -= h.x * v.x - h.y * v.y;
-      x.y -= h.x * v.y + h.y * v.x;
-      w[i] = x;
-    }
-    if (vcur) {
-      const double2 u = vcur[i];
-      re = fma(u.x, x.x, fma(u.y, x.y, re));
-      im = fma(u.x, x.y, fma(-u.y, x.x, im));
-    } else {
-      re = fma(x.x, x.x, fma(x.y, x.y, re));
+// For basis vectors q_{i0 .. i0+cnt-1} (stride n from Q): partials of
+// <q_i, w> (components 4 i, 4 i + 1 = re, im) and <q_i, qn> (4 i + 2, 4 i + 3).
+template <int CH>
+__global__ __launch_bounds__(kThreads) void block_dots_kernel(const double2* __restrict__ Q, int i0,
+                                                              int cnt, const double2* __restrict__ w,
+                                                              const double2* __restrict__ qn,
+                                                              size_t n, double* __restrict__ partials) {
+  double acc[4 * CH];
+#pragma unroll
+  for (int c = 0; c < 4 * CH; ++c) acc[c] = 0.0;
+  for (size_t k = blockIdx.x * size_t(kThreads) + threadIdx.x; k < n; k += size_t(gridDim.x) * kThreads) {
+    const double2 x = w[k], y = qn[k];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      if (i < cnt) {
+        const double2 q = Q[size_t(i0 + i) * n + k];
+        acc[4 * i] = fma(q.x, x.x, fma(q.y, x.y, acc[4 * i]));
+        acc[4 * i + 1] = fma(q.x, x.y, fma(-q.y, x.x, acc[4 * i + 1]));
+        acc[4 * i + 2] = fma(q.x, y.x, fma(q.y, y.y, acc[4 * i + 2]));
+        acc[4 * i + 3] = fma(q.x, y.y, fma(-q.y, y.x, acc[4 * i + 3]));
+      }
     }
   }
-  block_store2(re, im, partials);
+  block_store<4 * CH>(acc, partials, 4 * i0, gridDim.x);
 }
 
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const double* __restrict__ partials,
-                                                          int nparts, int ncomp,
-                                                          double2* __restrict__ out) {
-  __shared__ double sa[kThreads], sb[kThreads];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) {
-    a += partials[ncomp * i];
-    if (ncomp == 2) b += partials[2 * i + 1];
+// w -= sum_{i < m} c_i q_i; partial |w|^2 (component 0)
+__global__ __launch_bounds__(kThreads) void update_norm_kernel(double2* __restrict__ w,
+                                                               const double2* __restrict__ Q,
+                                                               const double2* __restrict__ c, int m,
+                                                               size_t n, double* __restrict__ partials) {
+  double v[1] = {0.0};
+  for (size_t k = blockIdx.x * size_t(kThreads) + threadIdx.x; k < n; k += size_t(gridDim.x) * kThreads) {
+    double2 x = w[k];
+    for (int i = 0; i < m; ++i) {
+      const double2 a = c[i], q = Q[size_t(i) * n + k];
+      x.x -= a.x * q.x - a.y * q.y;
+      x.y -= a.x * q.y + a.y * q.x;
+    }
+    w[k] = x;
+    v[0] = fma(x.x, x.x, fma(x.y, x.y, v[0]));
   }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
+  block_store<1>(v, partials, 0, gridDim.x);
+}
+
+// out[c] = sum_b partials[c * nblocks + b], one block per component
+__global__ __launch_bounds__(kThreads) void reduce_cols_kernel(const double* __restrict__ partials,
+                                                               int nblocks, double* __restrict__ out) {
+  __shared__ double s[kThreads];
+  double a = 0.0;
+  const double* p = partials + size_t(blockIdx.x) * nblocks;
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) a += p[i];
+  s[threadIdx.x] = a;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sa[threadIdx.x] += sa[threadIdx.x + s];
-      sb[threadIdx.x] += sb[threadIdx.x + s];
-    }
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = make_double2(sa[0], sb[0]);
-}
-
-__global__ __launch_bounds__(kThreads) void scale_kernel(double2* v, const double2* src,
-                                                         const double2* __restrict__ nrm, size_t n) {
-  const double s = 1.0 / sqrt(nrm->x);
-  for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-    const double2 x = src[i];
-    v[i] = make_double2(x.x * s, x.y * s);
-  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
 }
 
 // out (+)= sum_i y_i V_i, V_i = V + i * n
@@ -134,43 +145,37 @@ int grid_for(size_t n) {
   return int(b < size_t(kRedBlocks) ? (b > 0 ? b : 1) : kRedBlocks);
 }
 
+constexpr int kDotChunk = 8;
+
 }  // namespace
 
-hipError_t launch_dot_partials(const double2* a, const double2* b, size_t n, double* partials,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(dot_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, b, n, partials);
+hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, n, partials);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
   return hipGetLastError();
 }
 
-hipError_t launch_mgs_step(double2* w, const double2* vprev, const double2* hprev,
-                           const double2* vcur, size_t n, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(mgs_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, w, vprev, hprev, vcur, n,
+hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_dots(const double2* Q, int m, const double2* w, const double2* qn, size_t n,
+                             double* partials, double* out, hipStream_t s) {
+  for (int i0 = 0; i0 < m; i0 += kDotChunk) {
+    const int cnt = m - i0 < kDotChunk ? m - i0 : kDotChunk;
+    hipLaunchKernelGGL(block_dots_kernel<kDotChunk>, dim3(kRedBlocks), dim3(kThreads), 0, s, Q, i0,
+                       cnt, w, qn, n, partials);
+  }
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(4 * m), dim3(kThreads), 0, s, partials, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_norm(double2* w, const double2* Q, const double2* c, int m, size_t n,
+                              double* partials, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(update_norm_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, w, Q, c, m, n,
                      partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_norm2_partials(const double2* a, size_t n, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(mgs_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, const_cast<double2*>(a),
-                     nullptr, nullptr, nullptr, n, partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce(const double* partials, int nparts, int ncomp, double2* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, ncomp, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_axpy_norm(double2* w, const double2* v, const double2* h, size_t n,
-                            double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(mgs_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, w, v, h, nullptr, n,
-                     partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_inv_norm(double2* v, const double2* src, const double2* nrm, size_t n,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, v, src, nrm, n);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
   return hipGetLastError();
 }
 

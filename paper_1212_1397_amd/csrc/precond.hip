@@ -152,42 +152,155 @@ __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename
   return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// One thread per transverse mode: Gaussian elimination without pivoting
-// (Thomas) on T_z + shift I; c' goes to scratch, d' to the output, then back
-// substitution in place.
+// Partitioned Gaussian elimination without pivoting (the Thomas algorithm
+// with its three recurrences re-associated) on T_z + shift I, one transverse
+// mode per line.  A workgroup owns 16 consecutive modes (lanes) and splits
+// every z line into kSegs segments of S <= kSmax rows, one thread each, rows
+// held in registers.  Thomas' recurrences
+//   c'_i = c_i / (b_i - a_i c'_{i-1})          (a Moebius map of c'_{i-1}),
+//   d'_i = (d_i - a_i d'_{i-1}) / (b_i - a_i c'_{i-1})   (affine in d'_{i-1}),
+//   x_i  = d'_i - c'_i x_{i+1}                  (affine in x_{i+1})
+// are composed over each segment (2 x 2 projective matrices, affine pairs),
+// the segment summaries are combined in order through LDS, and each thread
+// then replays its own rows from its exact start value.  HBM traffic is one
+// read and one write of the vector.
+constexpr int kSegs = 16;
+constexpr int kTriLines = 16;      // rows per segment: S <= kSmax (9, 17 or 33: n'z <= 528)
+
 template <typename R>
-__global__ __launch_bounds__(256) void tridiag_z_kernel(const typename C2<R>::T* __restrict__ in,
-                                                        typename C2<R>::T* __restrict__ out,
-                                                        typename C2<R>::T* __restrict__ cp,
-                                                        const double2* __restrict__ tri,
-                                                        const double* __restrict__ lx,
-                                                        const double* __restrict__ ly, double kap_re,
-                                                        double kap_im, int nx, int ny, int nz) {
+__device__ __forceinline__ typename C2<R>::T csub(typename C2<R>::T a, typename C2<R>::T b) {
+  return mk<R>(a.x - b.x, a.y - b.y);
+}
+template <typename R>
+__device__ __forceinline__ typename C2<R>::T cadd(typename C2<R>::T a, typename C2<R>::T b) {
+  return mk<R>(a.x + b.x, a.y + b.y);
+}
+template <typename R>
+__device__ __forceinline__ typename C2<R>::T crecip(typename C2<R>::T b) {
+  const R d = R(1) / (b.x * b.x + b.y * b.y);
+  return mk<R>(b.x * d, -b.y * d);
+}
+template <typename R>
+__device__ __forceinline__ R cabs1(typename C2<R>::T a) {
+  return fabs(a.x) + fabs(a.y);
+}
+
+template <typename R, int kSmax>
+__global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
+    const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
+    const double2* __restrict__ tri, const double* __restrict__ lx, const double* __restrict__ ly,
+    double kap_re, double kap_im, int nx, int ny, int nz) {
   using T2 = typename C2<R>::T;
-  const int mode = blockIdx.x * blockDim.x + threadIdx.x;
-  if (mode >= nx * ny) return;
-  const int i = mode % nx, j = mode / nx;
+  __shared__ T2 sh[kTriLines][kSegs][4];
+  const int lane = threadIdx.x % kTriLines;
+  const int seg = threadIdx.x / kTriLines;
+  const int nmodes = nx * ny;
+  const int mode = blockIdx.x * kTriLines + lane;
+  const bool active = mode < nmodes;
+  const int mc = active ? mode : nmodes - 1;
+  const int i = mc % nx, j = mc / nx;
   const size_t stride = size_t(nx) * ny;
+  const int S = (nz + kSegs - 1) / kSegs;
+  const int r0 = min(seg * S, nz), cnt = min(S, nz - r0);
   const T2 shift = mk<R>(R(kap_re + lx[i] + ly[j]), R(kap_im));
-  T2 cprev = mk<R>(0, 0), dprev = mk<R>(0, 0);
-  for (int l = 0; l < nz; ++l) {
-    const T2 sub = cvt<T2>(tri[l]), dia = cvt<T2>(tri[nz + l]), sup = cvt<T2>(tri[2 * nz + l]);
-    const T2 sc = cmulr<R>(sub, cprev);
-    const T2 piv = mk<R>(dia.x + shift.x - sc.x, dia.y + shift.y - sc.y);
-    const T2 rhs = in[mode + l * stride];
-    const T2 sd = cmulr<R>(sub, dprev);
-    cprev = cdiv<R>(sup, piv);
-    dprev = cdiv<R>(mk<R>(rhs.x - sd.x, rhs.y - sd.y), piv);
-    cp[mode + l * stride] = cprev;
-    out[mode + l * stride] = dprev;
+  const T2 one = mk<R>(1, 0), zero = mk<R>(0, 0);
+
+  T2 d[kSmax], cp[kSmax];
+#pragma unroll
+  for (int u = 0; u < kSmax; ++u)
+    d[u] = (u < cnt && active) ? in[mode + size_t(r0 + u) * stride] : zero;
+
+  // phase 1: projective product of the c' maps over the segment
+  T2 p00 = one, p01 = zero, p10 = zero, p11 = one;     // P = M_last ... M_first
+#pragma unroll
+  for (int u = 0; u < kSmax; ++u) {
+    if (u < cnt) {
+      const int r = r0 + u;
+      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift), c = cvt<T2>(tri[2 * nz + r]);
+      // M = [[0, c], [-a, b]]
+      const T2 n00 = cmulr<R>(c, p10), n01 = cmulr<R>(c, p11);
+      const T2 n10 = csub<R>(cmulr<R>(b, p10), cmulr<R>(a, p00));
+      const T2 n11 = csub<R>(cmulr<R>(b, p11), cmulr<R>(a, p01));
+      const R sc = R(1) / fmax(fmax(cabs1<R>(n00), cabs1<R>(n01)), fmax(cabs1<R>(n10), cabs1<R>(n11)));
+      p00 = mk<R>(n00.x * sc, n00.y * sc);
+      p01 = mk<R>(n01.x * sc, n01.y * sc);
+      p10 = mk<R>(n10.x * sc, n10.y * sc);
+      p11 = mk<R>(n11.x * sc, n11.y * sc);
+    }
   }
-  T2 xn = dprev;
-  for (int l = nz - 2; l >= 0; --l) {
-    const T2 c = cp[mode + l * stride];
-    const T2 d = out[mode + l * stride];
-    const T2 t = cmulr<R>(c, xn);
-    xn = mk<R>(d.x - t.x, d.y - t.y);
-    out[mode + l * stride] = xn;
+  sh[lane][seg][0] = p00;
+  sh[lane][seg][1] = p01;
+  sh[lane][seg][2] = p10;
+  sh[lane][seg][3] = p11;
+  __syncthreads();
+  T2 pp = zero, pq = one;                               // c'_{r0-1} = pp / pq
+  for (int s2 = 0; s2 < seg; ++s2) {
+    const T2 a00 = sh[lane][s2][0], a01 = sh[lane][s2][1], a10 = sh[lane][s2][2], a11 = sh[lane][s2][3];
+    const T2 np = cadd<R>(cmulr<R>(a00, pp), cmulr<R>(a01, pq));
+    const T2 nq = cadd<R>(cmulr<R>(a10, pp), cmulr<R>(a11, pq));
+    const R sc = R(1) / fmax(cabs1<R>(np), cabs1<R>(nq));
+    pp = mk<R>(np.x * sc, np.y * sc);
+    pq = mk<R>(nq.x * sc, nq.y * sc);
+  }
+  const T2 cstart = cmulr<R>(pp, crecip<R>(pq));
+
+  // phase 2: local c', and the affine map d'_{last} = A d'_{r0-1} + B
+  T2 cprev = cstart, A = one, B = zero;
+#pragma unroll
+  for (int u = 0; u < kSmax; ++u) {
+    if (u < cnt) {
+      const int r = r0 + u;
+      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift), c = cvt<T2>(tri[2 * nz + r]);
+      const T2 im = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
+      cp[u] = cmulr<R>(c, im);
+      const T2 al = mk<R>(-(a.x * im.x - a.y * im.y), -(a.x * im.y + a.y * im.x));
+      A = cmulr<R>(al, A);
+      B = cadd<R>(cmulr<R>(al, B), cmulr<R>(d[u], im));
+      cprev = cp[u];
+    } else {
+      cp[u] = zero;
+    }
+  }
+  __syncthreads();
+  sh[lane][seg][0] = A;
+  sh[lane][seg][1] = B;
+  __syncthreads();
+  T2 dprev = zero;
+  for (int s2 = 0; s2 < seg; ++s2) dprev = cadd<R>(cmulr<R>(sh[lane][s2][0], dprev), sh[lane][s2][1]);
+  cprev = cstart;
+#pragma unroll
+  for (int u = 0; u < kSmax; ++u) {
+    if (u < cnt) {
+      const int r = r0 + u;
+      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift);
+      const T2 im = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
+      d[u] = cmulr<R>(csub<R>(d[u], cmulr<R>(a, dprev)), im);
+      dprev = d[u];
+      cprev = cp[u];
+    }
+  }
+  // phase 3: back substitution, x_{r0} = C x_{r0+cnt} + D over the segment
+  T2 C = one, D = zero;
+#pragma unroll
+  for (int u = kSmax - 1; u >= 0; --u) {
+    if (u < cnt) {
+      const T2 nc = mk<R>(-cp[u].x, -cp[u].y);
+      D = cadd<R>(d[u], cmulr<R>(nc, D));
+      C = cmulr<R>(nc, C);
+    }
+  }
+  __syncthreads();
+  sh[lane][seg][0] = C;
+  sh[lane][seg][1] = D;
+  __syncthreads();
+  T2 x = zero;
+  for (int s2 = kSegs - 1; s2 > seg; --s2) x = cadd<R>(cmulr<R>(sh[lane][s2][0], x), sh[lane][s2][1]);
+#pragma unroll
+  for (int u = kSmax - 1; u >= 0; --u) {
+    if (u < cnt) {
+      x = csub<R>(d[u], cmulr<R>(cp[u], x));
+      if (active) out[mode + size_t(r0 + u) * stride] = x;
+    }
   }
 }
 
@@ -197,7 +310,6 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   T2* w0 = static_cast<T2*>(P->w_pc[0]);
   T2* w1 = static_cast<T2*>(P->w_pc[1]);
-  T2* w2 = static_cast<T2*>(P->w_pc[2]);
   const AxisXform& X = P->ax[0];
   const AxisXform& Y = P->ax[1];
   const int nlines_x = ny * nz;
@@ -229,9 +341,19 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
   xform_x(false, r, w0);
   xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
-  hipLaunchKernelGGL((tridiag_z_kernel<R>), dim3((nx * ny + 255) / 256), dim3(256), 0, s, w1, w0,
-                     w2, P->d_tri, P->d_lambda_x, P->d_lambda_y, P->kappa.real(),
-                     P->kappa.imag(), nx, ny, nz);
+  {
+    const dim3 gt((nx * ny + kTriLines - 1) / kTriLines), bt(kTriLines * kSegs);
+    const double kr = P->kappa.real(), ki = P->kappa.imag();
+    if (nz <= kSegs * 9)
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 9>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
+                         P->d_lambda_y, kr, ki, nx, ny, nz);
+    else if (nz <= kSegs * 17)
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 17>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
+                         P->d_lambda_y, kr, ki, nx, ny, nz);
+    else
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 33>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
+                         P->d_lambda_y, kr, ki, nx, ny, nz);
+  }
   timing_end(P, KC_TRIDIAG, s, ev);
   xform_y(true, w0, w1);
   xform_x(true, static_cast<const T2*>(w1), z);

@@ -1,11 +1,19 @@
 // Host control loops of the solvers: right-preconditioned restarted GMRES(m)
-// and flexible GMRES(m) with modified Gram-Schmidt Arnoldi (Section 2,
-// eq. (AAP)), and the SKS iteration (Section 2, Algorithm 1) in correction
-// form.  All vector work is enqueued on the caller's stream; per Arnoldi step
-// only the Hessenberg column (j + 2 complex values) crosses to the host, where
-// the complex Givens QR update and the least-squares residual estimate are
-// computed in FP64.  The stopping test of a cycle uses the least-squares
-// estimate; convergence is declared on the true residual ||F - A U|| / ||F||,
+// and flexible GMRES(m) (Section 2, eq. (AAP)), and the SKS iteration
+// (Section 2, Algorithm 1) in correction form.
+//
+// Arnoldi: modified Gram-Schmidt in inverse compact WY form.  The basis is
+// kept unnormalised on the device (q~_i = nu_i q_i with nu_i known on the
+// host), so no scaling pass is needed.  Step j:
+//   z~ = A_p^{-1} q~_j,  w~ = A z~                      (w = w~ / nu_j)
+//   one pass:  s~_i = <q~_i, w~>,  l~_i = <q~_i, q~_j>,  i <= j
+//   host:      s_i = s~_i / (nu_i nu_j),  G_{j,i} = conj(l~_i) / (nu_i nu_j),
+//              h_i = s_i - sum_{l<i} G_{i,l} h_l   (the MGS coefficients)
+//   one pass:  w~ -= sum_i (nu_j h_i / nu_i) q~_i, |w~|^2 -> nu_{j+1}
+//   H(0..j, j) = h,  H(j+1, j) = nu_{j+1} / nu_j,
+// followed by the complex Givens update of the least-squares problem on the
+// host (FP64).  The cycle's stopping test uses the least-squares residual;
+// convergence is declared on the true residual ||F - A U|| / ||F||,
 // recomputed at every restart.
 #include <cmath>
 #include <vector>
@@ -15,18 +23,19 @@
 namespace h6 {
 namespace {
 
+// device scalar layout (in doubles from P->d_scal) and pinned host mirror
+constexpr int kDots = 0;        // 4 (m + 1) doubles of block dot results
+constexpr int kNorm = 1100;     // one norm
+constexpr int kCoef = 1200;     // 2 (m + 1) doubles: update coefficients (double2)
+constexpr int kY = 2000;        // 2 m doubles: least-squares coefficients (double2)
+
 struct Ctx {
   h6_plan P;
   hipStream_t s;
   size_t N;
-  double2* d_h;       // device Hessenberg column / scratch scalars
-  double2* d_y;       // device least-squares coefficients
-  double2* d_norm;    // device norm slot
-  double2* d_beta;    // device slot holding beta^2 at a cycle start
+  double* dev;      // P->d_scal as doubles
+  double* host;     // P->h_pinned as doubles
 };
-
-// pinned host slots: [0, 300) Hessenberg column, 300 beta^2, [320, 576) y
-constexpr int kPinH = 0, kPinBeta = 300, kPinY = 320;
 
 h6_status ensure(h6_plan P, int method, int m) {
   const size_t vb = P->N * sizeof(double2);
@@ -52,18 +61,23 @@ h6_status ensure(h6_plan P, int method, int m) {
   return H6_OK;
 }
 
-// |v|^2 of a device vector into host (synchronises)
+h6_status fetch(Ctx& c, int off, int count) {
+  h6_plan P = c.P;
+  H6_TRY_HIP(hipMemcpyAsync(c.host + off, c.dev + off, sizeof(double) * count, hipMemcpyDeviceToHost, c.s));
+  H6_TRY_HIP(hipStreamSynchronize(c.s));
+  return H6_OK;
+}
+
+// |v|^2 on the host (synchronises)
 h6_status norm2(Ctx& c, const double2* v, double* out) {
   h6_plan P = c.P;
   hipEvent_t ev;
   timing_begin(P, KC_NORM, c.s, &ev);
-  H6_TRY_HIP(launch_norm2_partials(v, c.N, P->partials, c.s));
-  H6_TRY_HIP(launch_reduce(P->partials, kRedBlocks, 2, c.d_norm, c.s));
+  H6_TRY_HIP(launch_norm2(v, c.N, P->partials, c.dev + kNorm, c.s));
   timing_end(P, KC_NORM, c.s, ev);
-  H6_TRY_HIP(hipMemcpyAsync(P->h_pinned, c.d_norm, sizeof(double2), hipMemcpyDeviceToHost, c.s));
-  H6_TRY_HIP(hipStreamSynchronize(c.s));
-  *out = P->h_pinned[0].x;
-  return H6_OK;
+  h6_status st = fetch(c, kNorm, 1);
+  *out = c.host[kNorm];
+  return st;
 }
 
 // r = F - A U and |r|^2 on the host (synchronises)
@@ -71,11 +85,10 @@ h6_status residual(Ctx& c, const double2* F, const double2* U, double2* r, doubl
   h6_plan P = c.P;
   int nparts = 0;
   H6_TRY_HIP(launch_stencil(P, U, r, F, P->partials, &nparts, c.s));
-  H6_TRY_HIP(launch_reduce(P->partials, nparts, 1, c.d_norm, c.s));
-  H6_TRY_HIP(hipMemcpyAsync(P->h_pinned, c.d_norm, sizeof(double2), hipMemcpyDeviceToHost, c.s));
-  H6_TRY_HIP(hipStreamSynchronize(c.s));
-  *out = P->h_pinned[0].x;
-  return H6_OK;
+  H6_TRY_HIP(launch_reduce_sum(P->partials, nparts, c.dev + kNorm, c.s));
+  h6_status st = fetch(c, kNorm, 1);
+  *out = c.host[kNorm];
+  return st;
 }
 
 void record(h6_solve_info* info, int& nh, double v) {
@@ -93,6 +106,16 @@ void givens(cplx a, double b, double& c, cplx& s, cplx& r) {
   r = ph * t;
 }
 
+h6_status upload_coefs(Ctx& c, int off, const std::vector<cplx>& v, int count) {
+  h6_plan P = c.P;
+  for (int i = 0; i < count; ++i) {
+    c.host[off + 2 * i] = v[i].real();
+    c.host[off + 2 * i + 1] = v[i].imag();
+  }
+  H6_TRY_HIP(hipMemcpyAsync(c.dev + off, c.host + off, sizeof(double) * 2 * count, hipMemcpyHostToDevice, c.s));
+  return H6_OK;
+}
+
 h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
   h6_plan P = c.P;
   const int m = info->restart;
@@ -100,11 +123,15 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   const size_t N = c.N;
   int nh = 0;
   double beta2 = 0.0;
-  h6_status st = residual(c, F, U, P->r, &beta2);
+  // the residual goes straight into the first basis slot (unnormalised)
+  h6_status st = residual(c, F, U, P->V, &beta2);
   if (st != H6_OK) return st;
-  std::vector<cplx> H(size_t(m + 1) * m), g(m + 1), sn(m);
-  std::vector<double> cs(m);
+  std::vector<cplx> H(size_t(m + 1) * m), g(m + 1), sn(m), G(size_t(m + 1) * (m + 1)), hcol(m + 1),
+      coef(m + 1);
+  std::vector<double> cs(m), nu(m + 1);
   auto Hij = [&](int i, int j) -> cplx& { return H[size_t(i) * m + j]; };
+  auto Gij = [&](int i, int j) -> cplx& { return G[size_t(i) * (m + 1) + j]; };
+  const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
   info->iters = 0;
   while (true) {
     const double beta = std::sqrt(beta2);
@@ -112,39 +139,44 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
     if (!std::isfinite(info->rel_resid)) { info->history_len = nh; return H6_DIVERGED; }
     if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
     if (info->iters >= info->maxit) { info->history_len = nh; return H6_NOT_CONVERGED; }
-    // v_0 = r / beta
-    P->h_pinned[kPinBeta] = make_double2(beta2, 0.0);
-    H6_TRY_HIP(hipMemcpyAsync(c.d_beta, P->h_pinned + kPinBeta, sizeof(double2), hipMemcpyHostToDevice, c.s));
-    H6_TRY_HIP(launch_scale_inv_norm(P->V, P->r, c.d_beta, N, c.s));
+    nu[0] = beta;
     std::fill(g.begin(), g.end(), cplx(0.0));
     g[0] = beta;
     int jdone = 0;
     for (int j = 0; j < m; ++j) {
-      double2* vj = P->V + size_t(j) * N;
+      double2* qj = P->V + size_t(j) * N;
       double2* w = P->V + size_t(j + 1) * N;
       double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
-      H6_TRY_HIP(launch_pinv(P, vj, z, c.s));
+      H6_TRY_HIP(launch_pinv(P, qj, z, c.s));
       H6_TRY_HIP(launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s));
       info->iters += 1;
-      // modified Gram-Schmidt; kernel i applies the update of basis vector i-1
-      // and forms the partial inner product with basis vector i
       hipEvent_t ev;
       timing_begin(P, KC_MGS, c.s, &ev);
-      for (int i = 0; i <= j; ++i) {
-        const double2* vprev = i > 0 ? P->V + size_t(i - 1) * N : nullptr;
-        H6_TRY_HIP(launch_mgs_step(w, vprev, c.d_h + (i > 0 ? i - 1 : 0), P->V + size_t(i) * N, N,
-                                   P->partials, c.s));
-        H6_TRY_HIP(launch_reduce(P->partials, kRedBlocks, 2, c.d_h + i, c.s));
-      }
-      H6_TRY_HIP(launch_axpy_norm(w, vj, c.d_h + j, N, P->partials, c.s));
-      H6_TRY_HIP(launch_reduce(P->partials, kRedBlocks, 2, c.d_h + j + 1, c.s));
+      H6_TRY_HIP(launch_block_dots(P->V, j + 1, w, qj, N, P->partials, c.dev + kDots, c.s));
       timing_end(P, KC_MGS, c.s, ev);
-      H6_TRY_HIP(hipMemcpyAsync(P->h_pinned + kPinH, c.d_h, sizeof(double2) * (j + 2), hipMemcpyDeviceToHost, c.s));
-      H6_TRY_HIP(hipStreamSynchronize(c.s));
-      const double2* hc = P->h_pinned + kPinH;
-      for (int i = 0; i <= j; ++i) Hij(i, j) = cplx(hc[i].x, hc[i].y);
-      const double hn2 = hc[j + 1].x;
-      const double hn = std::sqrt(std::max(hn2, 0.0));
+      st = fetch(c, kDots, 4 * (j + 1));
+      if (st != H6_OK) return st;
+      // MGS coefficients from the inner products and the Gram row of q_j
+      for (int i = 0; i < j; ++i) {
+        const cplx l(c.host[kDots + 4 * i + 2], c.host[kDots + 4 * i + 3]);
+        Gij(j, i) = std::conj(l) / (nu[i] * nu[j]);
+      }
+      for (int i = 0; i <= j; ++i) {
+        cplx h = cplx(c.host[kDots + 4 * i], c.host[kDots + 4 * i + 1]) / (nu[i] * nu[j]);
+        for (int l = 0; l < i; ++l) h -= Gij(i, l) * hcol[l];
+        hcol[i] = h;
+        coef[i] = nu[j] * h / nu[i];
+      }
+      st = upload_coefs(c, kCoef, coef, j + 1);
+      if (st != H6_OK) return st;
+      timing_begin(P, KC_MGS, c.s, &ev);
+      H6_TRY_HIP(launch_update_norm(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s));
+      timing_end(P, KC_MGS, c.s, ev);
+      st = fetch(c, kNorm, 1);
+      if (st != H6_OK) return st;
+      nu[j + 1] = std::sqrt(std::max(c.host[kNorm], 0.0));
+      const double hn = nu[j + 1] / nu[j];
+      for (int i = 0; i <= j; ++i) Hij(i, j) = hcol[i];
       // previous rotations on column j
       for (int i = 0; i < j; ++i) {
         const cplx t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
@@ -162,35 +194,35 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
       jdone = j + 1;
       const double est = std::abs(g[j + 1]) / normF;
       record(info, nh, est);
-      const bool breakdown = !(hn > 1e-300 * beta);
-      if (est <= info->tol || info->iters >= info->maxit || breakdown || j + 1 == m) break;
-      // v_{j+1} = w / |w| (the device norm slot d_h[j+1] holds |w|^2)
-      H6_TRY_HIP(launch_scale_inv_norm(w, w, c.d_h + j + 1, N, c.s));
+      const bool breakdown = !(hn > 1e-300);
+      if (est <= info->tol || info->iters >= info->maxit || breakdown || !std::isfinite(est)) break;
     }
-    // y = R^{-1} g
+    // y = R^{-1} g; the update uses the unnormalised vectors, so y_i / nu_i
     std::vector<cplx> y(jdone);
     for (int i = jdone - 1; i >= 0; --i) {
       cplx acc = g[i];
       for (int k = i + 1; k < jdone; ++k) acc -= Hij(i, k) * y[k];
       y[i] = acc / Hij(i, i);
     }
-    for (int i = 0; i < jdone; ++i) P->h_pinned[kPinY + i] = make_double2(y[i].real(), y[i].imag());
-    H6_TRY_HIP(hipMemcpyAsync(c.d_y, P->h_pinned + kPinY, sizeof(double2) * jdone, hipMemcpyHostToDevice, c.s));
+    for (int i = 0; i < jdone; ++i) y[i] /= nu[i];
+    st = upload_coefs(c, kY, y, jdone);
+    if (st != H6_OK) return st;
+    const double2* dy = reinterpret_cast<const double2*>(c.dev + kY);
     hipEvent_t ev;
     if (flex) {
       timing_begin(P, KC_AXPY, c.s, &ev);
-      H6_TRY_HIP(launch_multi_axpy(U, static_cast<double2*>(P->Z), c.d_y, jdone, N, 1, c.s));
+      H6_TRY_HIP(launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, jdone, N, 1, c.s));
       timing_end(P, KC_AXPY, c.s, ev);
     } else {
       timing_begin(P, KC_AXPY, c.s, &ev);
-      H6_TRY_HIP(launch_multi_axpy(P->t, P->V, c.d_y, jdone, N, 0, c.s));
+      H6_TRY_HIP(launch_multi_axpy(P->t, P->V, dy, jdone, N, 0, c.s));
       timing_end(P, KC_AXPY, c.s, ev);
       H6_TRY_HIP(launch_pinv(P, P->t, P->r, c.s));
       timing_begin(P, KC_AXPY, c.s, &ev);
       H6_TRY_HIP(launch_add(U, P->r, N, c.s));
       timing_end(P, KC_AXPY, c.s, ev);
     }
-    st = residual(c, F, U, P->r, &beta2);
+    st = residual(c, F, U, P->V, &beta2);
     if (st != H6_OK) return st;
   }
 }
@@ -228,8 +260,7 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s) {
   h6_status st = ensure(P, info->method, info->restart);
   if (st != H6_OK) return st;
-  Ctx c{P, s, P->N, P->d_scal + 64, P->d_scal + 512, P->d_scal + 8, P->d_scal + 16};
-  if (info->method != H6_SKS && info->restart + 2 > 448) return H6_ERR_ARG;
+  Ctx c{P, s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
   double normF2 = 0.0;
   st = norm2(c, F, &normF2);
   if (st != H6_OK) return st;

