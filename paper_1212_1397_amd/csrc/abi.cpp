@@ -127,18 +127,25 @@ void z_tridiagonal(h6_plan P, std::vector<cplx>& sub, std::vector<cplx>& diag,
   }
 }
 
-// Gaussian elimination pivots of every z system T_z + (kappa + lx + ly) I;
-// a pivot below 1e-12 (4 + |shift|) or non-finite means A_p is singular.
-bool singular_modes(h6_plan P, const std::vector<double>& lx, const std::vector<double>& ly,
-                    const std::vector<cplx>& sub, const std::vector<cplx>& diag,
-                    const std::vector<cplx>& sup, std::string& where) {
+// Gaussian elimination of every z system T_z + (kappa + lx + ly) I: a pivot
+// below 1e-12 (4 + |shift|) or non-finite means A_p is singular.  Records
+// c'_{r0-1}, the value entering each of the kZSegs segments of rows
+// [r0, r0 + S), S = ceil(n'z / kZSegs), for the partitioned device solver.
+bool factor_modes(h6_plan P, const std::vector<double>& lx, const std::vector<double>& ly,
+                  const std::vector<cplx>& sub, const std::vector<cplx>& diag,
+                  const std::vector<cplx>& sup, std::vector<cplx>& cstart, std::string& where) {
   const int L = P->dims[2];
+  const size_t nmodes = lx.size() * ly.size();
+  const int S = (L + kZSegs - 1) / kZSegs;
+  cstart.assign(kZSegs * nmodes, cplx(0.0));
   for (size_t j = 0; j < ly.size(); ++j)
     for (size_t i = 0; i < lx.size(); ++i) {
+      const size_t mode = i + lx.size() * j;
       const cplx shift = P->kappa + lx[i] + ly[j];
       const double tol = 1e-12 * (4.0 + std::abs(shift));
       cplx cprev = 0.0;
       for (int l = 0; l < L; ++l) {
+        if (l % S == 0) cstart[size_t(l / S) * nmodes + mode] = cprev;
         const cplx piv = diag[l] + shift - (l > 0 ? sub[l] * cprev : cplx(0.0));
         if (!std::isfinite(piv.real()) || !std::isfinite(piv.imag()) || std::abs(piv) <= tol) {
           where = "zero pivot in z row " + std::to_string(l) + " of mode (" + std::to_string(i) +
@@ -185,12 +192,20 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
   }
   for (int t = 0; t < 256; ++t)
     tw[t] = make_double2(std::cos(-2.0 * M_PI * t / 256.0), std::sin(-2.0 * M_PI * t / 256.0));
-  std::vector<double> sq(M + 1), cq(M + 1);
-  for (int q = 0; q <= M; ++q) {
-    sq[q] = std::sin(M_PI * q / M);
-    cq[q] = std::cos(M_PI * q / M);
+  std::vector<double> sa(P1), ca(P1);
+  std::vector<int> slot_of_q(M + 1, -1);
+  for (int a = 0; a < P1; ++a) {
+    sa[a] = std::sin(M_PI * pin[a] / M);
+    ca[a] = std::cos(M_PI * pin[a] / M);
+    slot_of_q[pin[a]] = a;
   }
-  const size_t bytes = 2 * P1 * sizeof(int) + 2 * P1 * sizeof(double2) + 2 * (M + 1) * sizeof(double) + 256;
+  slot_of_q[0] = P1;          // cosine-basis end nodes
+  slot_of_q[M] = P1 + 1;
+  std::vector<int> slot_d(M - 1), slot_n(M + 1);
+  for (int p = 0; p < M - 1; ++p) slot_d[p] = slot_of_q[p + 1];
+  for (int p = 0; p <= M; ++p) slot_n[p] = slot_of_q[p];
+  const size_t bytes = 2 * P1 * sizeof(int) + 2 * P1 * sizeof(double2) + 2 * P1 * sizeof(double) +
+                       (2 * M + 1) * sizeof(int) + 256;
   char* mem = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&mem), bytes + 64);
   if (e != hipSuccess) return e;
@@ -206,8 +221,10 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
   };
   ax.rader.kf = reinterpret_cast<const double2*>(put(kf.data(), P1 * sizeof(double2)));
   ax.rader.tw256 = reinterpret_cast<const double2*>(put(tw.data(), 256 * sizeof(double2)));
-  ax.rader.sin_q = reinterpret_cast<const double*>(put(sq.data(), (M + 1) * sizeof(double)));
-  ax.rader.cos_q = reinterpret_cast<const double*>(put(cq.data(), (M + 1) * sizeof(double)));
+  ax.rader.sin_a = reinterpret_cast<const double*>(put(sa.data(), P1 * sizeof(double)));
+  ax.rader.cos_a = reinterpret_cast<const double*>(put(ca.data(), P1 * sizeof(double)));
+  ax.rader.slot_d = reinterpret_cast<const int*>(put(slot_d.data(), (M - 1) * sizeof(int)));
+  ax.rader.slot_n = reinterpret_cast<const int*>(put(slot_n.data(), (M + 1) * sizeof(int)));
   ax.rader.perm_in = reinterpret_cast<const int*>(put(pin.data(), P1 * sizeof(int)));
   ax.rader.perm_out = reinterpret_cast<const int*>(put(pout.data(), P1 * sizeof(int)));
   if (off > bytes + 64) return hipErrorInvalidValue;
@@ -226,6 +243,7 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->d_trig_x);
   (void)hipFree(P->d_trig_y);
   (void)hipFree(P->d_tri);
+  (void)hipFree(P->d_cstart);
   for (void* w : P->w_pc) (void)hipFree(w);
   (void)hipFree(P->V);
   (void)hipFree(P->Z);
@@ -299,7 +317,8 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   std::vector<cplx> sub, diag, sup;
   z_tridiagonal(P, sub, diag, sup);
   std::string where;
-  if (singular_modes(P, lx, ly, sub, diag, sup, where)) {
+  std::vector<cplx> cstart;
+  if (factor_modes(P, lx, ly, sub, diag, sup, cstart, where)) {
     err = "preconditioner is singular: " + where;
     free_plan(P);
     return H6_ERR_SINGULAR;
@@ -318,6 +337,17 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   if (e == hipSuccess) e = upload(&P->d_trig_x, trig_table(P->ax[0].M), s);
   if (e == hipSuccess) e = upload(&P->d_trig_y, trig_table(P->ax[1].M), s);
   if (e == hipSuccess) e = upload(&P->d_tri, tri, s);
+  if (e == hipSuccess) {
+    if (p->precision == H6_MIXED) {
+      std::vector<float2> cf(cstart.size());
+      for (size_t i = 0; i < cf.size(); ++i) cf[i] = make_float2(float(cstart[i].real()), float(cstart[i].imag()));
+      e = upload(reinterpret_cast<float2**>(&P->d_cstart), cf, s);
+    } else {
+      std::vector<double2> cd(cstart.size());
+      for (size_t i = 0; i < cd.size(); ++i) cd[i] = make_double2(cstart[i].real(), cstart[i].imag());
+      e = upload(reinterpret_cast<double2**>(&P->d_cstart), cd, s);
+    }
+  }
   for (int a = 0; a < 2 && e == hipSuccess; ++a)
     if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
   const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);

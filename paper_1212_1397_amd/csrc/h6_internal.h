@@ -83,6 +83,8 @@ struct h6_plan_s {
   double* d_trig_x = nullptr;       // sin, cos (pi t / M), t = 0..2M-1 (2 * 2M doubles)
   double* d_trig_y = nullptr;
   double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
+  void* d_cstart = nullptr;         // Thomas c' entering each z segment: [kZSegs][n'x n'y], complex
+                                    // (double2, or float2 in mixed plans)
 
   // preconditioner workspace (complex128 vectors, or complex64 in mixed plans)
   void* w_pc[3] = {nullptr, nullptr, nullptr};   // two used
@@ -105,7 +107,8 @@ namespace h6 {
 constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
 constexpr int kMaxPartials = 1 << 20;
 constexpr int kScal = 4096;        // device scalar slots (double2)
-constexpr int kMaxZ = 16 * 33;     // largest n'z of the partitioned z solver
+constexpr int kZSegs = 32;         // segments per z line in the partitioned z solver
+constexpr int kMaxZ = kZSegs * 17; // largest n'z of the partitioned z solver
 
 // kernel launchers (stream-ordered, no synchronisation)
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,

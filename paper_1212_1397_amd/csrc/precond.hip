@@ -153,19 +153,20 @@ __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename
 }
 
 // Partitioned Gaussian elimination without pivoting (the Thomas algorithm
-// with its three recurrences re-associated) on T_z + shift I, one transverse
-// mode per line.  A workgroup owns 16 consecutive modes (lanes) and splits
-// every z line into kSegs segments of S <= kSmax rows, one thread each, rows
-// held in registers.  Thomas' recurrences
-//   c'_i = c_i / (b_i - a_i c'_{i-1})          (a Moebius map of c'_{i-1}),
-//   d'_i = (d_i - a_i d'_{i-1}) / (b_i - a_i c'_{i-1})   (affine in d'_{i-1}),
-//   x_i  = d'_i - c'_i x_{i+1}                  (affine in x_{i+1})
-// are composed over each segment (2 x 2 projective matrices, affine pairs),
-// the segment summaries are combined in order through LDS, and each thread
-// then replays its own rows from its exact start value.  HBM traffic is one
-// read and one write of the vector.
-constexpr int kSegs = 16;
-constexpr int kTriLines = 16;      // rows per segment: S <= kSmax (9, 17 or 33: n'z <= 528)
+// with its recurrences re-associated) on T_z + shift I, one transverse mode per
+// line.  A workgroup owns kTriLines consecutive modes (lanes) and splits every
+// z line into kSegs segments of S <= kSmax rows, one thread each, rows held in
+// registers.  Thomas' recurrences are
+//   c'_i = c_i / m_i,  m_i = b_i - a_i c'_{i-1}        (data independent),
+//   d'_i = (d_i - a_i d'_{i-1}) / m_i                   (affine in d'_{i-1}),
+//   x_i  = d'_i - c'_i x_{i+1}                           (affine in x_{i+1}).
+// The c' value entering each segment depends only on the matrix, so the plan
+// stores it (cstart[seg][mode], computed in FP64 at setup with the pivot
+// check).  Each thread replays c' over its rows, composes the two affine maps
+// over its segment, and the segment maps are chained in order through LDS.
+// HBM traffic: one read and one write of the vector plus the small cstart table.
+constexpr int kSegs = kZSegs;      // 32 segments per line
+constexpr int kTriLines = 16;      // rows per segment: S <= kSmax (5, 9 or 17: n'z <= 544)
 
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T csub(typename C2<R>::T a, typename C2<R>::T b) {
@@ -175,23 +176,31 @@ template <typename R>
 __device__ __forceinline__ typename C2<R>::T cadd(typename C2<R>::T a, typename C2<R>::T b) {
   return mk<R>(a.x + b.x, a.y + b.y);
 }
+
+// 1/x for x > 0: hardware reciprocal refined by Newton steps (FP64: two steps)
+__device__ __forceinline__ double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_pos(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T crecip(typename C2<R>::T b) {
-  const R d = R(1) / (b.x * b.x + b.y * b.y);
+  const R d = rcp_pos(b.x * b.x + b.y * b.y);
   return mk<R>(b.x * d, -b.y * d);
-}
-template <typename R>
-__device__ __forceinline__ R cabs1(typename C2<R>::T a) {
-  return fabs(a.x) + fabs(a.y);
 }
 
 template <typename R, int kSmax>
 __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
     const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
-    const double2* __restrict__ tri, const double* __restrict__ lx, const double* __restrict__ ly,
-    double kap_re, double kap_im, int nx, int ny, int nz) {
+    const double2* __restrict__ tri, const typename C2<R>::T* __restrict__ cstart,
+    const double* __restrict__ lx, const double* __restrict__ ly, double kap_re, double kap_im,
+    int nx, int ny, int nz) {
   using T2 = typename C2<R>::T;
-  __shared__ T2 sh[kTriLines][kSegs][4];
+  __shared__ T2 sh[2][kSegs][kTriLines];
   const int lane = threadIdx.x % kTriLines;
   const int seg = threadIdx.x / kTriLines;
   const int nmodes = nx * ny;
@@ -205,100 +214,63 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
   const T2 shift = mk<R>(R(kap_re + lx[i] + ly[j]), R(kap_im));
   const T2 one = mk<R>(1, 0), zero = mk<R>(0, 0);
 
-  T2 d[kSmax], cp[kSmax];
+  T2 d[kSmax], ip[kSmax];     // right-hand side, then d'; inverse pivots 1/m_i
 #pragma unroll
   for (int u = 0; u < kSmax; ++u)
     d[u] = (u < cnt && active) ? in[mode + size_t(r0 + u) * stride] : zero;
 
-  // phase 1: projective product of the c' maps over the segment
-  T2 p00 = one, p01 = zero, p10 = zero, p11 = one;     // P = M_last ... M_first
+  // local pass: c' from the stored start value, inverse pivots, and the
+  // affine map d'_{last} = A d'_{r0-1} + B
+  T2 cprev = cstart[size_t(seg) * nmodes + mc], A = one, B = zero;
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
       const int r = r0 + u;
       const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift), c = cvt<T2>(tri[2 * nz + r]);
-      // M = [[0, c], [-a, b]]
-      const T2 n00 = cmulr<R>(c, p10), n01 = cmulr<R>(c, p11);
-      const T2 n10 = csub<R>(cmulr<R>(b, p10), cmulr<R>(a, p00));
-      const T2 n11 = csub<R>(cmulr<R>(b, p11), cmulr<R>(a, p01));
-      const R sc = R(1) / fmax(fmax(cabs1<R>(n00), cabs1<R>(n01)), fmax(cabs1<R>(n10), cabs1<R>(n11)));
-      p00 = mk<R>(n00.x * sc, n00.y * sc);
-      p01 = mk<R>(n01.x * sc, n01.y * sc);
-      p10 = mk<R>(n10.x * sc, n10.y * sc);
-      p11 = mk<R>(n11.x * sc, n11.y * sc);
-    }
-  }
-  sh[lane][seg][0] = p00;
-  sh[lane][seg][1] = p01;
-  sh[lane][seg][2] = p10;
-  sh[lane][seg][3] = p11;
-  __syncthreads();
-  T2 pp = zero, pq = one;                               // c'_{r0-1} = pp / pq
-  for (int s2 = 0; s2 < seg; ++s2) {
-    const T2 a00 = sh[lane][s2][0], a01 = sh[lane][s2][1], a10 = sh[lane][s2][2], a11 = sh[lane][s2][3];
-    const T2 np = cadd<R>(cmulr<R>(a00, pp), cmulr<R>(a01, pq));
-    const T2 nq = cadd<R>(cmulr<R>(a10, pp), cmulr<R>(a11, pq));
-    const R sc = R(1) / fmax(cabs1<R>(np), cabs1<R>(nq));
-    pp = mk<R>(np.x * sc, np.y * sc);
-    pq = mk<R>(nq.x * sc, nq.y * sc);
-  }
-  const T2 cstart = cmulr<R>(pp, crecip<R>(pq));
-
-  // phase 2: local c', and the affine map d'_{last} = A d'_{r0-1} + B
-  T2 cprev = cstart, A = one, B = zero;
-#pragma unroll
-  for (int u = 0; u < kSmax; ++u) {
-    if (u < cnt) {
-      const int r = r0 + u;
-      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift), c = cvt<T2>(tri[2 * nz + r]);
-      const T2 im = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
-      cp[u] = cmulr<R>(c, im);
-      const T2 al = mk<R>(-(a.x * im.x - a.y * im.y), -(a.x * im.y + a.y * im.x));
+      ip[u] = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
+      const T2 al = cmulr<R>(mk<R>(-a.x, -a.y), ip[u]);
       A = cmulr<R>(al, A);
-      B = cadd<R>(cmulr<R>(al, B), cmulr<R>(d[u], im));
-      cprev = cp[u];
+      B = cadd<R>(cmulr<R>(al, B), cmulr<R>(d[u], ip[u]));
+      cprev = cmulr<R>(c, ip[u]);
     } else {
-      cp[u] = zero;
+      ip[u] = zero;
     }
   }
-  __syncthreads();
-  sh[lane][seg][0] = A;
-  sh[lane][seg][1] = B;
+  sh[0][seg][lane] = A;
+  sh[1][seg][lane] = B;
   __syncthreads();
   T2 dprev = zero;
-  for (int s2 = 0; s2 < seg; ++s2) dprev = cadd<R>(cmulr<R>(sh[lane][s2][0], dprev), sh[lane][s2][1]);
-  cprev = cstart;
+  for (int s2 = 0; s2 < seg; ++s2) dprev = cadd<R>(cmulr<R>(sh[0][s2][lane], dprev), sh[1][s2][lane]);
+  // replay d', then compose the back substitution x_{r0} = C x_{r0+cnt} + D
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
-      const int r = r0 + u;
-      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift);
-      const T2 im = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
-      d[u] = cmulr<R>(csub<R>(d[u], cmulr<R>(a, dprev)), im);
+      const T2 a = cvt<T2>(tri[r0 + u]);
+      d[u] = cmulr<R>(csub<R>(d[u], cmulr<R>(a, dprev)), ip[u]);
       dprev = d[u];
-      cprev = cp[u];
     }
   }
-  // phase 3: back substitution, x_{r0} = C x_{r0+cnt} + D over the segment
   T2 C = one, D = zero;
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      const T2 nc = mk<R>(-cp[u].x, -cp[u].y);
-      D = cadd<R>(d[u], cmulr<R>(nc, D));
-      C = cmulr<R>(nc, C);
+      const T2 c = cvt<T2>(tri[2 * nz + r0 + u]);
+      const T2 ncp = cmulr<R>(mk<R>(-c.x, -c.y), ip[u]);      // -c'_u
+      D = cadd<R>(d[u], cmulr<R>(ncp, D));
+      C = cmulr<R>(ncp, C);
     }
   }
   __syncthreads();
-  sh[lane][seg][0] = C;
-  sh[lane][seg][1] = D;
+  sh[0][seg][lane] = C;
+  sh[1][seg][lane] = D;
   __syncthreads();
   T2 x = zero;
-  for (int s2 = kSegs - 1; s2 > seg; --s2) x = cadd<R>(cmulr<R>(sh[lane][s2][0], x), sh[lane][s2][1]);
+  for (int s2 = kSegs - 1; s2 > seg; --s2) x = cadd<R>(cmulr<R>(sh[0][s2][lane], x), sh[1][s2][lane]);
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      x = csub<R>(d[u], cmulr<R>(cp[u], x));
+      const T2 c = cvt<T2>(tri[2 * nz + r0 + u]);
+      x = csub<R>(d[u], cmulr<R>(cmulr<R>(c, ip[u]), x));
       if (active) out[mode + size_t(r0 + u) * stride] = x;
     }
   }
@@ -344,15 +316,16 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
   {
     const dim3 gt((nx * ny + kTriLines - 1) / kTriLines), bt(kTriLines * kSegs);
     const double kr = P->kappa.real(), ki = P->kappa.imag();
-    if (nz <= kSegs * 9)
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 9>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
-                         P->d_lambda_y, kr, ki, nx, ny, nz);
-    else if (nz <= kSegs * 17)
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 17>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
-                         P->d_lambda_y, kr, ki, nx, ny, nz);
+    const T2* cst = static_cast<const T2*>(P->d_cstart);
+    if (nz <= kSegs * 5)
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 5>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
+                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
+    else if (nz <= kSegs * 9)
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 9>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
+                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
     else
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 33>), gt, bt, 0, s, w1, w0, P->d_tri, P->d_lambda_x,
-                         P->d_lambda_y, kr, ki, nx, ny, nz);
+      hipLaunchKernelGGL((tridiag_z_kernel<R, 17>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
+                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
   }
   timing_end(P, KC_TRIDIAG, s, ev);
   xform_y(true, w0, w1);

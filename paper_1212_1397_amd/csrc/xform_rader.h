@@ -11,8 +11,10 @@ struct RaderTables {
   const int* perm_out;     // g^{b} mod M,  b = 0..M-2
   const double2* kf;       // FFT_{M-1} of w^{g^c} (w = e^{-2 pi i / M}), divided by M-1
   const double2* tw256;    // e^{-2 pi i t / 256}
-  const double* sin_q;     // sin(pi q / M), q = 0..M
-  const double* cos_q;     // cos(pi q / M), q = 0..M
+  const double* sin_a;     // sin(pi g^{-a} / M), a = 0..M-2
+  const double* cos_a;     // cos(pi g^{-a} / M), a = 0..M-2
+  const int* slot_d;       // LDS slot of array index p of a sine-basis line (node q = p + 1)
+  const int* slot_n;       // LDS slot of array index p of a cosine-basis line (node q = p)
 };
 
 constexpr int kRaderM = 257;

@@ -120,6 +120,12 @@ constexpr int kLines = 8;          // lines per workgroup (16 threads each)
 constexpr int kStride = 273;       // LDS row stride (complex) per line, >= 258 and >= 16*17
 constexpr int kHalf = 128;         // (M - 1) / 2
 
+// LDS use per line: the input is stored in Rader order (slot a holds node
+// q = g^{-a}; slot a + 128 then holds node M - q because g^{128} = -1 mod M;
+// the cosine basis keeps its end nodes q = 0, M in slots 256, 257), so the
+// gather of (x_q, x_{M-q}) pairs reads consecutive slots; the 16 x 16
+// transposes use a row stride of 17; Y is scattered to natural order and the
+// outputs are written back in natural order for a coalesced store.
 template <typename R, int AXIS, bool NEU, bool INV, typename Tin, typename Tout>
 __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __restrict__ in,
                                                                Tout* __restrict__ out, int nlines,
@@ -128,36 +134,57 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   constexpr int M = 257;
   const int tid = threadIdx.x;
   const int g = tid >> 4, t = tid & 15;
-  // ---- load kLines lines into LDS (coalesced) ----
-  int line0, nl;
-  size_t gbase;            // AXIS 0: first element of line0; AXIS 1: (z, i0) offset
+  const int* __restrict__ slot = NEU ? tab.slot_n : tab.slot_d;
+  // ---- load kLines lines into LDS in Rader order: all global reads of a
+  // thread are issued before any LDS write (coalesced, many loads in flight) ----
+  int nl;
+  size_t gbase;
+  const int line0 = blockIdx.x * kLines;
   if (AXIS == 0) {
-    line0 = blockIdx.x * kLines;
     nl = min(kLines, nlines - line0);
     gbase = size_t(line0) * L;
-    for (int e = tid; e < nl * L; e += kLines * 16) {
-      const int b = e / L, q = e - b * L;
-      buf[b][q] = cv<T2>(in[gbase + e]);
-    }
+    T2 r[kLines][3];
+#pragma unroll
+    for (int b = 0; b < kLines; ++b)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int p = tid + k * kLines * 16;
+        if (b < nl && p < L) r[b][k] = cv<T2>(in[gbase + size_t(b) * L + p]);
+      }
+#pragma unroll
+    for (int b = 0; b < kLines; ++b)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int p = tid + k * kLines * 16;
+        if (b < nl && p < L) buf[b][slot[p]] = r[b][k];
+      }
   } else {
-    line0 = blockIdx.x * kLines;          // x column i0
-    nl = min(kLines, nx - line0);
+    nl = min(kLines, nx - line0);                   // x columns i0 .. i0 + nl - 1
     gbase = size_t(blockIdx.y) * nx * L + line0;
-    for (int e = tid; e < kLines * L; e += kLines * 16) {
+    constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
+    T2 r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kLines * 16;
       const int q = e / kLines, b = e - q * kLines;
-      if (b < nl) buf[b][q] = cv<T2>(in[gbase + size_t(q) * nx + b]);
+      if (q < L && b < nl) r[k] = cv<T2>(in[gbase + size_t(q) * nx + b]);
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kLines * 16;
+      const int q = e / kLines, b = e - q * kLines;
+      if (q < L && b < nl) buf[b][slot[q]] = r[k];
     }
   }
   __syncthreads();
 
   // ---- gather y_{g^{-a}} (a = t + 16 n2) with the pre-processing ----
-  const int off = NEU ? 0 : -1;   // array index of node q is q + off
   T2 v[16];
   T2 y0sum = mk2<R>(0, 0), c1sum = mk2<R>(0, 0);
   T2 xa = mk2<R>(0, 0), xb = mk2<R>(0, 0);  // x_0 and x_M (cosine sums)
   if (NEU) {
-    xa = buf[g][0];
-    xb = buf[g][M];
+    xa = buf[g][256];
+    xb = buf[g][257];
     if (!INV) {
       xa = scl<R>(xa, R(0.5));
       xb = scl<R>(xb, R(0.5));
@@ -165,21 +192,20 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   }
 #pragma unroll
   for (int n2 = 0; n2 < 16; ++n2) {
-    const int q = tab.perm_in[t + 16 * n2];
-    const T2 xq = buf[g][q + off], xr = buf[g][M - q + off];
+    const int a = t + 16 * n2;
+    const T2 xq = buf[g][a], xr = buf[g][(a + 128) & 255];
     const T2 s = add<R>(xq, xr), d = sub<R>(xq, xr);
-    const R sn = R(tab.sin_q[q]);
+    const R sn = R(tab.sin_a[a]);
     T2 y;
     if (NEU) {
       y = add<R>(s, scl<R>(d, sn));
-      c1sum = add<R>(c1sum, scl<R>(d, R(0.5) * R(tab.cos_q[q])));
+      c1sum = add<R>(c1sum, scl<R>(d, R(0.5) * R(tab.cos_a[a])));
     } else {
       y = add<R>(scl<R>(s, sn), d);
     }
     y0sum = add<R>(y0sum, y);
     v[n2] = y;
   }
-  // group sums over the 16 threads of the line
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) {
     y0sum.x += __shfl_xor(y0sum.x, o, 16);
@@ -223,47 +249,35 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   if (t == 0) buf[g][0] = y0sum;
   __syncthreads();
 
-  // ---- post-processing: j = 0..128, 9 consecutive j per thread ----
-  const int jb = 9 * t, je = min(jb + 9, kHalf + 1);
-  T2 pre = mk2<R>(0, 0);                   // local sums of the odd-output increments
-  T2 inc[9];
-#pragma unroll
-  for (int u = 0; u < 9; ++u) {
-    const int j = jb + u;
-    inc[u] = mk2<R>(0, 0);
-    if (j < je && j >= 1) {
-      const T2 Yj = buf[g][j], Ym = buf[g][M - j];
-      inc[u] = NEU ? scl<R>(sub<R>(Yj, Ym), R(0.5)) : scl<R>(add<R>(Yj, Ym), R(0.5));
-      pre = add<R>(pre, inc[u]);
-    }
-  }
-  // exclusive scan of the per-thread totals across the 16 threads
-  T2 scan = pre;
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    const R px = __shfl_up(scan.x, o, 16), py = __shfl_up(scan.y, o, 16);
-    if (t >= o) { scan.x += px; scan.y += py; }
-  }
-  T2 run = sub<R>(scan, pre);
+  // ---- post-processing: j = t + 16 u (u = 0..8, j <= 128), running sums of
+  // the odd-output increments by a 16-lane scan per round ----
   T2 ev[9], od[9];
+  T2 carry = mk2<R>(0, 0);
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
-    const int j = jb + u;
-    run = add<R>(run, inc[u]);
-    if (j < je) {
-      const T2 Yj = buf[g][j == 0 ? 0 : j], Ym = buf[g][j == 0 ? 0 : M - j];
-      if (NEU) {
-        // C_{2j} and C_{2j+1}
-        const T2 A = (j == 0) ? Yj : scl<R>(add<R>(Yj, Ym), R(0.5));
-        ev[u] = add<R>(add<R>(xa, xb), scl<R>(A, R(0.5)));
-        // C'_{2j+1} = C'_1 - i * run
-        od[u] = add<R>(sub<R>(xa, xb), add<R>(c1sum, mk2<R>(run.y, -run.x)));
-      } else {
-        // S_{2j} (j >= 1) and S_{2j+1} (j <= 127)
-        const T2 D = sub<R>(Yj, Ym);
-        ev[u] = mk2<R>(-R(0.25) * D.y, R(0.25) * D.x);
-        od[u] = add<R>(scl<R>(y0sum, R(0.5)), run);
-      }
+    const int j = t + 16 * u;
+    const bool ok = j <= kHalf;
+    const int jj = ok ? j : 0;
+    const T2 Yj = buf[g][jj], Ym = buf[g][jj == 0 ? 0 : M - jj];
+    T2 inc = mk2<R>(0, 0);
+    if (ok && j >= 1) inc = NEU ? scl<R>(sub<R>(Yj, Ym), R(0.5)) : scl<R>(add<R>(Yj, Ym), R(0.5));
+    T2 sc = inc;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const R px = __shfl_up(sc.x, o, 16), py = __shfl_up(sc.y, o, 16);
+      if (t >= o) { sc.x += px; sc.y += py; }
+    }
+    const T2 run = add<R>(carry, sc);     // sum over 1 <= i <= j
+    carry.x += __shfl(sc.x, 15, 16);
+    carry.y += __shfl(sc.y, 15, 16);
+    if (NEU) {
+      const T2 A = (j == 0) ? Yj : scl<R>(add<R>(Yj, Ym), R(0.5));
+      ev[u] = add<R>(add<R>(xa, xb), scl<R>(A, R(0.5)));                      // C_{2j}
+      od[u] = add<R>(sub<R>(xa, xb), add<R>(c1sum, mk2<R>(run.y, -run.x)));  // C_{2j+1}
+    } else {
+      const T2 D = sub<R>(Yj, Ym);
+      ev[u] = mk2<R>(-R(0.25) * D.y, R(0.25) * D.x);                          // S_{2j}
+      od[u] = add<R>(scl<R>(y0sum, R(0.5)), run);                              // S_{2j+1}
     }
   }
   __syncthreads();
@@ -271,31 +285,37 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   const R fs = INV ? R(1) : R(2) / R(M);
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
-    const int j = jb + u;
-    if (j >= je) continue;
+    const int j = t + 16 * u;
+    if (j > kHalf) continue;
     if (NEU) {
       const int me = 2 * j, mo = 2 * j + 1;              // m = 0..M
       R se = fs, so = fs;
-      if (!INV && (me == 0 || me == M)) se *= R(0.5);
+      if (!INV && me == 0) se *= R(0.5);
       if (!INV && mo == M) so *= R(0.5);
       buf[g][me] = scl<R>(ev[u], se);
       if (mo <= M) buf[g][mo] = scl<R>(od[u], so);
     } else {
-      if (j >= 1) buf[g][2 * j - 1] = scl<R>(ev[u], fs);     // m = 2j -> index 2j - 1
+      if (j >= 1) buf[g][2 * j - 1] = scl<R>(ev[u], fs);           // m = 2j -> index 2j - 1
       if (2 * j + 1 <= M - 2) buf[g][2 * j] = scl<R>(od[u], fs);   // m = 2j + 1
     }
   }
   __syncthreads();
   // ---- store (coalesced) ----
   if (AXIS == 0) {
-    for (int e = tid; e < nl * L; e += kLines * 16) {
-      const int b = e / L, q = e - b * L;
-      out[gbase + e] = cv<Tout>(buf[b][q]);
-    }
+#pragma unroll
+    for (int b = 0; b < kLines; ++b)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int p = tid + k * kLines * 16;
+        if (b < nl && p < L) out[gbase + size_t(b) * L + p] = cv<Tout>(buf[b][p]);
+      }
   } else {
-    for (int e = tid; e < kLines * L; e += kLines * 16) {
+    constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * kLines * 16;
       const int q = e / kLines, b = e - q * kLines;
-      if (b < nl) out[gbase + size_t(q) * nx + b] = cv<Tout>(buf[b][q]);
+      if (q < L && b < nl) out[gbase + size_t(q) * nx + b] = cv<Tout>(buf[b][q]);
     }
   }
 }
