@@ -1,21 +1,26 @@
 """Benchmark: seconds to a 1e-8 relative residual on the 256^3 mixed-face
-Helmholtz problem (sixth-order compact scheme, 7-point FFT preconditioner),
-plain FP64 GMRES(30) on one MI355X.
+Helmholtz problem (sixth-order compact scheme, 7-point FFT preconditioner) on
+one MI355X: the mixed-precision solve (complex64 preconditioner, FP64
+operator, residuals and Arnoldi; flexible GMRES(30)) against the plain FP64
+solve on the same GPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dns-256]
+                    [--method mixed-fgmres|mixed-sks|fp64-gmres|fp64-sks|fp64-fgmres]
 
-One step is one complete solve (all hot-path stages: right-hand side resident
-in HBM, GMRES Arnoldi steps with preconditioner and operator applications,
-modified Gram-Schmidt, cycle updates and true-residual checks).  Warm-up
-solves are untimed; then K solves are timed between two device
-synchronisations.  Rank 0 prints one JSON line with:
-  value / ms_per_step  - seconds / milliseconds per solve (lower is better),
-  roofline             - the kernel with the largest share of the solve time,
-                         its algorithmic HBM bytes per launch over its average
-                         launch duration (HIP events on the solve's stream),
-  cpu_baseline         - the FP64 CPU oracle on a bounded sample of the same
-                         solve, scaled to a whole solve.
-Secondary figures (SKS, per-kernel bandwidths) ride along in "extra".
+One step is one complete solve from U = 0 (right-hand side resident in HBM;
+every Arnoldi or SKS step with its preconditioner and operator applications,
+the orthogonalisation, the cycle updates and the true-residual checks).
+Warm-up solves are untimed; then K solves are timed between two device
+synchronisations.  The process prints one JSON line:
+  value / ms_per_step  seconds / milliseconds per solve of --method,
+  roofline             the kernel class with the largest share of that solve's
+                       time: its algorithmic HBM bytes per launch over its
+                       average launch duration (HIP events on the solve's
+                       stream, recorded by the library),
+  cpu_baseline         the FP64 CPU oracle's GMRES(30) on a bounded sample of
+                       the same problem, scaled to a whole solve,
+  extra                the other methods (plain FP64 GMRES and SKS, mixed SKS)
+                       timed once each, and the per-kernel breakdown.
 """
 from __future__ import annotations
 
@@ -30,23 +35,56 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1212_1397_amd", "csrc")
+METHODS = {
+    "mixed-fgmres": ("mixed", "fgmres"),
+    "mixed-sks": ("mixed", "sks"),
+    "fp64-gmres": ("fp64", "gmres"),
+    "fp64-fgmres": ("fp64", "fgmres"),
+    "fp64-sks": ("fp64", "sks"),
+}
+BW_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs_dots",
+              "mgs_update", "axpy")
 
 
-def algorithmic_bytes(plan, cls: str, n_unknowns: int, elem: int = 16) -> float:
-    """Bytes one launch of a kernel class must move at minimum (per unknown x N).
+def csrc_digest() -> str:
+    """sha256 over the library sources (names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
 
-    stencil: read x, write y (2 vectors); stencil_resid: read x and F, write r
-    (3); each transform pass and the z solve: read and write one vector (2).
-    """
-    per = {"stencil": 2, "stencil_resid": 3, "xform_x": 2, "xform_y": 2, "tridiag_z": 2}[cls]
-    return float(per * elem * n_unknowns)
+
+def measured_traffic(workload: str, method: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or
+    None when there is none or the library sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"counters_{workload}_{method}.md")
+    if not os.path.exists(path):
+        return None
+    rows, digest = {}, None
+    for line in open(path):
+        if line.startswith("csrc_sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("| ") and not line.startswith("| kernel"):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 6 and cells[0] and not set(cells[0]) <= set("-"):
+                try:
+                    rows[cells[0]] = float(cells[5])
+                except ValueError:
+                    pass
+    if digest != csrc_digest():
+        return None
+    return rows.get(kernel)
 
 
-def run_cpu_baseline(w, gpu_iters: int):
+def run_cpu_baseline(w, iters: int):
     """Oracle GMRES on the same problem, stopped after two Arnoldi steps, scaled
-    to the GPU's iteration count (the oracle's per-step cost is uniform)."""
-    import numpy as np
-
+    to a whole solve of `iters` steps (the oracle's per-step cost is uniform)."""
     import oracle
     from oracle.functions import gaussian_sources
     from paper_1212_1397_amd.workloads import gaussian_sources as wl_sources
@@ -58,11 +96,12 @@ def run_cpu_baseline(w, gpu_iters: int):
     _, info = oracle.solve(prob, F, "gmres", restart=w.restart, tol=w.tol, maxit=2)
     dt = time.perf_counter() - t0
     per_iter = dt / max(info.iters, 1)
-    return {"value": per_iter * gpu_iters, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle GMRES({w.restart}) on the full {w.name} grid stopped after "
-                      f"{info.iters} Arnoldi steps (incl. initial and cycle-end residuals): "
-                      f"{dt:.1f} s, scaled to {gpu_iters} steps; numpy/scipy single-threaded",
-            "sample_seconds": dt}
+    return {"value": round(per_iter * iters, 2), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle GMRES({w.restart}) on the full {w.name} grid stopped after "
+                      f"{info.iters} Arnoldi steps (including the initial and cycle-end residuals): "
+                      f"{dt:.1f} s, scaled to the {iters} steps of a full FP64 GMRES solve; "
+                      f"numpy/scipy on one host thread",
+            "sample_seconds": round(dt, 2)}
 
 
 def main():
@@ -71,9 +110,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dns-256")
-    ap.add_argument("--method", default="gmres", choices=["gmres", "sks", "fgmres"])
+    ap.add_argument("--method", default="mixed-fgmres", choices=sorted(METHODS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="before the timed region, copy one vector with a plain device copy "
+                         "(the reference for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -86,68 +128,96 @@ def main():
 
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    plan = h6.Plan(w.n, w.h, w.k, w.bc)
+    plans = {}
+
+    def plan_for(prec):
+        if prec not in plans:
+            plans[prec] = h6.Plan(w.n, w.h, w.k, w.bc, precision=prec)
+        return plans[prec]
+
+    prec, meth = METHODS[args.method]
+    plan = plan_for(prec)
     N = plan.dims[0] * plan.dims[1] * plan.dims[2]
     centres, amps, sigma = gaussian_sources(w)
     F = plan.rhs_gaussians(centres, amps, sigma)
     U = torch.zeros_like(F)
-    print(f"# workload {w.name}: dims {plan.dims}, N = {N}, k = {w.k}, bc = {w.bc}", file=sys.stderr,
-          flush=True)
+    if args.calibration_copy:
+        U.copy_(F)
+        torch.cuda.synchronize()
+    print(f"# workload {w.name}: dims {plan.dims}, N = {N}, k = {w.k}, faces {w.bc}; "
+          f"method {args.method}", file=sys.stderr, flush=True)
 
-    def one_solve(method):
+    def one_solve(pl, method):
         U.zero_()
-        _, info = plan.solve(F, U, method=method, restart=w.restart, tol=w.tol, maxit=500)
+        _, info = pl.solve(F, U, method=method, restart=w.restart, tol=w.tol, maxit=500)
         if info["status"] != "ok":
             raise RuntimeError(f"solve did not converge: {info}")
         return info
 
     for _ in range(args.warmup):
-        info = one_solve(args.method)
+        info = one_solve(plan, meth)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        info = one_solve(args.method)
+        info = one_solve(plan, meth)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     print(f"# timed {args.steps} solves: {dt * 1e3:.2f} ms/solve, {info['iters']} iterations, "
           f"rel resid {info['rel_resid']:.3e}", file=sys.stderr, flush=True)
 
-    # per-kernel durations from HIP events on the solve's stream (one extra solve)
+    # per-kernel durations from HIP events on the solve's stream (one more solve)
     plan.profile(True)
     for c in h6.KERNEL_CLASSES:
         plan.kernel_time(c, reset=True)
-    one_solve(args.method)
+    one_solve(plan, meth)
     torch.cuda.synchronize()
     ktimes = {c: plan.kernel_time(c) for c in h6.KERNEL_CLASSES}
     plan.profile(False)
-    total_ms = sum(ms for ms, _ in ktimes.values())
+    total_ms = sum(ms for ms, _, _ in ktimes.values())
     kernels = {}
-    for c, (ms, n) in ktimes.items():
+    for c, (ms, n, nbytes) in ktimes.items():
         if n == 0:
             continue
-        rec = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n, "share": ms / total_ms}
-        if c in ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z"):
-            b = algorithmic_bytes(plan, c, N)
-            rec["alg_bytes_per_launch"] = b
-            rec["gbs"] = b / (1e-3 * ms / n) / 1e9
-            rec["frac_hbm"] = rec["gbs"] / HBM_PEAK_GBS
+        rec = {"ms_total": round(ms, 4), "launches": n, "avg_us": round(1e3 * ms / n, 2),
+               "share": round(ms / total_ms, 4)}
+        if c in BW_CLASSES and nbytes > 0:
+            rec["alg_bytes_per_launch"] = nbytes / n
+            rec["gbs"] = round(nbytes / (1e-3 * ms) / 1e9, 1)
+            rec["frac_hbm"] = round(rec["gbs"] / HBM_PEAK_GBS, 4)
         kernels[c] = rec
     bw = {c: r for c, r in kernels.items() if "gbs" in r}
     dom = max(bw, key=lambda c: bw[c]["ms_total"])
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(bw[dom]["gbs"], 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(bw[dom]["frac_hbm"], 4),
-                "traffic": None}
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": bw[dom]["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": bw[dom]["frac_hbm"],
+                "traffic": measured_traffic(w.name, args.method, dom),
+                "alg_bytes_per_launch": bw[dom]["alg_bytes_per_launch"],
+                "avg_launch_us": bw[dom]["avg_us"]}
 
     extra = {"kernels": kernels}
-    if not args.no_extra and args.method == "gmres":
-        t1 = time.perf_counter()
-        si = one_solve("sks")
-        torch.cuda.synchronize()
-        extra["sks"] = {"s": time.perf_counter() - t1, "iters": si["iters"], "rel_resid": si["rel_resid"]}
+    fp64_iters = info["iters"] if args.method == "fp64-gmres" else None
+    if not args.no_extra:
+        others = {}
+        for name in ("fp64-gmres", "fp64-sks", "mixed-fgmres", "mixed-sks"):
+            if name == args.method:
+                continue
+            p2, m2 = METHODS[name]
+            pl = plan_for(p2)
+            one_solve(pl, m2)                     # warm-up (workspace allocation)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            i2 = one_solve(pl, m2)
+            torch.cuda.synchronize()
+            others[name] = {"s": round(time.perf_counter() - t1, 6), "iters": i2["iters"],
+                            "rel_resid": i2["rel_resid"]}
+            if name == "fp64-gmres":
+                fp64_iters = i2["iters"]
+        extra["methods"] = others
+        if "fp64-gmres" in others:
+            extra["speedup_vs_fp64_gmres"] = round(others["fp64-gmres"]["s"] / dt, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(w, info["iters"])
+        cpu = run_cpu_baseline(w, fp64_iters or info["iters"])
 
     out = {
         "metric": "s to 1e-8 resid @256^3: mixed/learned vs plain FP64 GPU; stencil+precond HBM GB/s",
@@ -160,13 +230,12 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid_unknowns": list(plan.dims), "interior_nodes": w.n,
                    "k": [w.k.real, w.k.imag], "faces": w.bc, "sources": w.nsrc,
-                   "method": f"{args.method}({w.restart})" if args.method != "sks" else "sks",
-                   "precision": "fp64", "tol": w.tol, "iterations": info["iters"],
-                   "rel_resid": info["rel_resid"]},
+                   "method": args.method, "restart": w.restart if meth != "sks" else None,
+                   "tol": w.tol, "iterations": info["iters"], "rel_resid": info["rel_resid"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -121,15 +121,18 @@ h6_status helmholtz6_solve(h6_plan plan, const void* F, void* U, h6_solve_info* 
                            void* hip_stream);
 
 /* Per-kernel timing: when enabled, the library records HIP events around
- * every kernel it launches and accumulates their durations per kernel class.
- * helmholtz6_kernel_time reads (and with reset != 0 clears) the total
- * milliseconds and launch count of one class by name ("stencil",
- * "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm", "axpy",
- * "rhs"); it synchronises the plan's timing events.  Returns H6_ERR_ARG for
- * an unknown name. */
+ * every kernel (or fused group of kernels) it launches on the caller's stream
+ * and accumulates, per kernel class, the durations, the launch count and the
+ * algorithmic HBM bytes of the timed work (the bytes the method must move:
+ * each input vector read once, each output written once, in the storage
+ * precision of the plan).  helmholtz6_kernel_time reads (and with reset != 0
+ * clears) one class by name ("stencil", "stencil_resid", "xform_x",
+ * "xform_y", "tridiag_z", "mgs_dots", "mgs_update", "norm", "axpy", "rhs"); it
+ * synchronises the plan's timing events.  Any of ms, launches, bytes may be
+ * NULL.  Returns H6_ERR_ARG for an unknown name. */
 h6_status helmholtz6_profile(h6_plan plan, int enable);
 h6_status helmholtz6_kernel_time(h6_plan plan, const char* name, int reset, double* ms,
-                                 long long* launches);
+                                 long long* launches, double* bytes);
 
 /* Releases the plan and its workspace (NULL is accepted). */
 void helmholtz6_destroy(h6_plan plan);

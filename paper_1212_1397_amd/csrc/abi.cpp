@@ -11,7 +11,8 @@
 namespace h6 {
 
 const char* const kKernelClassNames[KC_COUNT] = {
-    "stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm", "axpy", "rhs"};
+    "stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs_dots", "mgs_update",
+    "norm", "axpy", "rhs"};
 
 namespace {
 
@@ -381,7 +382,7 @@ void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a) {
   (void)hipEventRecord(*a, s);
 }
 
-void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a) {
+void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a, double bytes) {
   if (!P->timing.enabled || !a) return;
   hipEvent_t b;
   if (P->timing.pool.empty()) {
@@ -391,7 +392,7 @@ void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a) {
     P->timing.pool.pop_back();
   }
   (void)hipEventRecord(b, s);
-  P->timing.pending.push_back({a, b, cls});
+  P->timing.pending.push_back({a, b, cls, bytes});
 }
 
 }  // namespace h6
@@ -484,7 +485,7 @@ h6_status helmholtz6_profile(h6_plan P, int enable) {
 }
 
 h6_status helmholtz6_kernel_time(h6_plan P, const char* name, int reset, double* ms,
-                                 long long* launches) {
+                                 long long* launches, double* bytes) {
   if (!P || !name) return H6_ERR_ARG;
   int cls = -1;
   for (int i = 0; i < KC_COUNT; ++i)
@@ -495,6 +496,7 @@ h6_status helmholtz6_kernel_time(h6_plan P, const char* name, int reset, double*
     if (hipEventSynchronize(pe.b) == hipSuccess && hipEventElapsedTime(&t, pe.a, pe.b) == hipSuccess) {
       P->timing.ms[pe.cls] += t;
       P->timing.launches[pe.cls] += 1;
+      P->timing.bytes[pe.cls] += pe.bytes;
     }
     P->timing.pool.push_back(pe.a);
     P->timing.pool.push_back(pe.b);
@@ -502,9 +504,11 @@ h6_status helmholtz6_kernel_time(h6_plan P, const char* name, int reset, double*
   P->timing.pending.clear();
   if (ms) *ms = P->timing.ms[cls];
   if (launches) *launches = P->timing.launches[cls];
+  if (bytes) *bytes = P->timing.bytes[cls];
   if (reset) {
     P->timing.ms[cls] = 0.0;
     P->timing.launches[cls] = 0;
+    P->timing.bytes[cls] = 0.0;
   }
   return H6_OK;
 }

@@ -36,7 +36,8 @@ enum KernelClass {
   KC_XFORM_X,
   KC_XFORM_Y,
   KC_TRIDIAG,
-  KC_MGS,
+  KC_MGS_DOTS,
+  KC_MGS_UPDATE,
   KC_NORM,
   KC_AXPY,
   KC_RHS,
@@ -59,8 +60,9 @@ struct Timing {
   bool enabled = false;
   double ms[KC_COUNT] = {0};
   long long launches[KC_COUNT] = {0};
+  double bytes[KC_COUNT] = {0};     // algorithmic HBM bytes of the timed launches
   std::vector<hipEvent_t> pool;     // recycled events
-  struct Pending { hipEvent_t a, b; int cls; };
+  struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<Pending> pending;
 };
 
@@ -91,7 +93,7 @@ struct h6_plan_s {
 
   // Krylov workspace (allocated on first solve, grown as needed)
   double2* V = nullptr;   int V_cols = 0;      // (m+1) basis vectors
-  void* Z = nullptr;      int Z_cols = 0;      // FGMRES preconditioned vectors
+  void* Z = nullptr;      int Z_cols = 0;      // FGMRES preconditioned vectors (complex64 in mixed plans)
   double2* r = nullptr;                        // residual / scratch vector
   double2* t = nullptr;                        // scratch vector
   double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
@@ -107,6 +109,7 @@ namespace h6 {
 constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
 constexpr int kMaxPartials = 1 << 20;
 constexpr int kScal = 4096;        // device scalar slots (double2)
+constexpr int kGramMax = 16;       // Gram row entries formed by launch_update_gram
 constexpr int kZSegs = 32;         // segments per z line in the partitioned z solver
 constexpr int kMaxZ = kZSegs * 17; // largest n'z of the partitioned z solver
 
@@ -114,25 +117,32 @@ constexpr int kMaxZ = kZSegs * 17; // largest n'z of the partitioned z solver
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
                           double* partials, int* nparts, hipStream_t s);
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s);
+// mixed plans only: z = A_p^{-1} r stored in complex64
+hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s);
+// y = A x for a complex64 x (FP64 arithmetic)
+hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s);
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
 
 // Krylov helpers (double2 vectors of length P->N); reductions end in device doubles
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s);
 hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
-// out[4i..4i+3] = (<q_i, w>, <q_i, qn>) for i < m, q_i = Q + i n
-hipError_t launch_block_dots(const double2* Q, int m, const double2* w, const double2* qn, size_t n,
-                             double* partials, double* out, hipStream_t s);
-// w -= sum_{i<m} c_i q_i; out[0] = |w|^2
-hipError_t launch_update_norm(double2* w, const double2* Q, const double2* c, int m, size_t n,
+// out[2i..2i+1] = <q_i, w> for i < m, q_i = Q + i n
+hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n, double* partials,
+                             double* out, hipStream_t s);
+// w -= sum_{i<m} c_i q_i; out[0] = |w|^2, out[1+2i..2+2i] = <q_i, w> for i < min(m, kGramMax)
+hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
                               double* partials, double* out, hipStream_t s);
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
                              int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
+hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y, int m, size_t n,
+                                 int accumulate, hipStream_t s);
 hipError_t launch_add(double2* U, const double2* z, size_t n, hipStream_t s);   // U += z
 
 // timing helpers
 void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a);
-void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a);
+// bytes: the algorithmic HBM traffic of the work between begin and end
+void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a, double bytes);
 
 // solver
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s);

@@ -276,8 +276,8 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
   }
 }
 
-template <typename R>
-hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
+template <typename R, typename Tout>
+hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s) {
   using T2 = typename C2<R>::T;
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   T2* w0 = static_cast<T2*>(P->w_pc[0]);
@@ -290,6 +290,7 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
   const dim3 gx((nlines_x + kXLines - 1) / kXLines), gy((nx + kYCols - 1) / kYCols, nz);
   hipEvent_t ev;
 
+  const double Nd = double(P->N);
   auto xform_x = [&](bool inv, auto* src, auto* dst) {
     timing_begin(P, KC_XFORM_X, s, &ev);
     if (X.fast)
@@ -299,7 +300,7 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
                                          std::remove_pointer_t<decltype(dst)>, R>),
                          gx, dim3(256), shx, s, src, dst, nlines_x, X.L, X.M, X.neumann, inv ? 1 : 0,
                          P->d_trig_x);
-    timing_end(P, KC_XFORM_X, s, ev);
+    timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst)));
   };
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
     timing_begin(P, KC_XFORM_Y, s, &ev);
@@ -308,7 +309,7 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
     else
       hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, src, dst, nx, Y.L, Y.M,
                          Y.neumann, inv ? 1 : 0, P->d_trig_y);
-    timing_end(P, KC_XFORM_Y, s, ev);
+    timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
   xform_x(false, r, w0);
   xform_y(false, w0, w1);
@@ -327,7 +328,7 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
       hipLaunchKernelGGL((tridiag_z_kernel<R, 17>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
                          P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
   }
-  timing_end(P, KC_TRIDIAG, s, ev);
+  timing_end(P, KC_TRIDIAG, s, ev, Nd * 2 * sizeof(T2));
   xform_y(true, w0, w1);
   xform_x(true, static_cast<const T2*>(w1), z);
   return hipGetLastError();
@@ -336,8 +337,13 @@ hipError_t pinv_impl(h6_plan P, const double2* r, double2* z, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s) {
-  if (P->p.precision == H6_MIXED) return pinv_impl<float>(P, r, z, s);
-  return pinv_impl<double>(P, r, z, s);
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, z, s);
+  return pinv_impl<double, double2>(P, r, z, s);
+}
+
+hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s) {
+  if (P->p.precision != H6_MIXED) return hipErrorInvalidValue;
+  return pinv_impl<float, float2>(P, r, z, s);
 }
 
 }  // namespace h6

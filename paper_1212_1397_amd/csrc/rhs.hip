@@ -170,7 +170,7 @@ hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* 
   timing_begin(P, KC_RHS, s, &ev);
   const size_t nb = (P->N + 255) / 256;
   hipLaunchKernelGGL(rhs_kernel, dim3(unsigned(nb)), dim3(256), 0, s, a, F);
-  timing_end(P, KC_RHS, s, ev);
+  timing_end(P, KC_RHS, s, ev, double(P->N) * sizeof(double2));
   return hipGetLastError();
 }
 

@@ -6,15 +6,18 @@
 // kept unnormalised on the device (q~_i = nu_i q_i with nu_i known on the
 // host), so no scaling pass is needed.  Step j:
 //   z~ = A_p^{-1} q~_j,  w~ = A z~                      (w = w~ / nu_j)
-//   one pass:  s~_i = <q~_i, w~>,  l~_i = <q~_i, q~_j>,  i <= j
-//   host:      s_i = s~_i / (nu_i nu_j),  G_{j,i} = conj(l~_i) / (nu_i nu_j),
-//              h_i = s_i - sum_{l<i} G_{i,l} h_l   (the MGS coefficients)
-//   one pass:  w~ -= sum_i (nu_j h_i / nu_i) q~_i, |w~|^2 -> nu_{j+1}
+//   one pass:  s~_i = <q~_i, w~>,  i <= j
+//   host:      s_i = s~_i / (nu_i nu_j),
+//              h_i = s_i - sum_{l<i} G_{i,l} h_l   (the MGS coefficients),
+//              G_{i,l} = <q_i, q_l> (l < i) from earlier steps
+//   one pass:  w~ -= sum_i (nu_j h_i / nu_i) q~_i; |w~|^2 -> nu_{j+1} and the
+//              Gram row l~_i = <q~_i, w~>, G_{j+1,i} = conj(l~_i) / (nu_i nu_{j+1})
 //   H(0..j, j) = h,  H(j+1, j) = nu_{j+1} / nu_j,
 // followed by the complex Givens update of the least-squares problem on the
 // host (FP64).  The cycle's stopping test uses the least-squares residual;
 // convergence is declared on the true residual ||F - A U|| / ||F||,
 // recomputed at every restart.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -24,10 +27,11 @@ namespace h6 {
 namespace {
 
 // device scalar layout (in doubles from P->d_scal) and pinned host mirror
-constexpr int kDots = 0;        // 4 (m + 1) doubles of block dot results
-constexpr int kNorm = 1100;     // one norm
+constexpr int kDots = 0;        // 2 (m + 1) doubles of block dot results
+constexpr int kNorm = 1100;     // one norm (update pass: norm + 2 kGramMax Gram entries)
 constexpr int kCoef = 1200;     // 2 (m + 1) doubles: update coefficients (double2)
 constexpr int kY = 2000;        // 2 m doubles: least-squares coefficients (double2)
+constexpr int kGram2 = 3000;    // Gram entries beyond kGramMax (2 m doubles)
 
 struct Ctx {
   h6_plan P;
@@ -39,12 +43,13 @@ struct Ctx {
 
 h6_status ensure(h6_plan P, int method, int m) {
   const size_t vb = P->N * sizeof(double2);
-  auto grow = [&](void** ptr, int* cols, int want) -> hipError_t {
+  const size_t zb = P->N * (P->p.precision == H6_MIXED ? sizeof(float2) : sizeof(double2));
+  auto grow = [&](void** ptr, int* cols, int want, size_t bytes) -> hipError_t {
     if (*cols >= want) return hipSuccess;
     (void)hipFree(*ptr);
     *ptr = nullptr;
     *cols = 0;
-    hipError_t e = hipMalloc(ptr, vb * size_t(want));
+    hipError_t e = hipMalloc(ptr, bytes * size_t(want));
     if (e == hipSuccess) *cols = want;
     return e;
   };
@@ -52,8 +57,8 @@ h6_status ensure(h6_plan P, int method, int m) {
   if (!P->r) e = hipMalloc(reinterpret_cast<void**>(&P->r), vb);
   if (e == hipSuccess && !P->t) e = hipMalloc(reinterpret_cast<void**>(&P->t), vb);
   if (e == hipSuccess && method != H6_SKS)
-    e = grow(reinterpret_cast<void**>(&P->V), &P->V_cols, m + 1);
-  if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m);
+    e = grow(reinterpret_cast<void**>(&P->V), &P->V_cols, m + 1, vb);
+  if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m, zb);
   if (e != hipSuccess) {
     P->last_error = std::string("workspace allocation failed: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
@@ -74,7 +79,7 @@ h6_status norm2(Ctx& c, const double2* v, double* out) {
   hipEvent_t ev;
   timing_begin(P, KC_NORM, c.s, &ev);
   H6_TRY_HIP(launch_norm2(v, c.N, P->partials, c.dev + kNorm, c.s));
-  timing_end(P, KC_NORM, c.s, ev);
+  timing_end(P, KC_NORM, c.s, ev, double(c.N) * sizeof(double2));
   h6_status st = fetch(c, kNorm, 1);
   *out = c.host[kNorm];
   return st;
@@ -120,6 +125,7 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   h6_plan P = c.P;
   const int m = info->restart;
   const bool flex = info->method == H6_FGMRES;
+  const bool mixed = P->p.precision == H6_MIXED;   // implies flex (checked at the ABI)
   const size_t N = c.N;
   int nh = 0;
   double beta2 = 0.0;
@@ -146,35 +152,52 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
     for (int j = 0; j < m; ++j) {
       double2* qj = P->V + size_t(j) * N;
       double2* w = P->V + size_t(j + 1) * N;
-      double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
-      H6_TRY_HIP(launch_pinv(P, qj, z, c.s));
-      H6_TRY_HIP(launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s));
+      if (mixed) {
+        float2* z = static_cast<float2*>(P->Z) + size_t(j) * N;
+        H6_TRY_HIP(launch_pinv_f32out(P, qj, z, c.s));
+        H6_TRY_HIP(launch_stencil_f32in(P, z, w, c.s));
+      } else {
+        double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
+        H6_TRY_HIP(launch_pinv(P, qj, z, c.s));
+        H6_TRY_HIP(launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s));
+      }
       info->iters += 1;
       hipEvent_t ev;
-      timing_begin(P, KC_MGS, c.s, &ev);
-      H6_TRY_HIP(launch_block_dots(P->V, j + 1, w, qj, N, P->partials, c.dev + kDots, c.s));
-      timing_end(P, KC_MGS, c.s, ev);
-      st = fetch(c, kDots, 4 * (j + 1));
+      timing_begin(P, KC_MGS_DOTS, c.s, &ev);
+      H6_TRY_HIP(launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s));
+      // Gram entries of q_j beyond the kGramMax formed by the last update pass
+      if (j > kGramMax)
+        H6_TRY_HIP(launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, qj, N, P->partials,
+                                     c.dev + kGram2, c.s));
+      timing_end(P, KC_MGS_DOTS, c.s, ev,
+                 double(N) * sizeof(double2) * ((j + 2) + (j > kGramMax ? j - kGramMax + 1 : 0)));
+      st = fetch(c, kDots, 2 * (j + 1));
+      if (st == H6_OK && j > kGramMax) st = fetch(c, kGram2, 2 * (j - kGramMax));
       if (st != H6_OK) return st;
-      // MGS coefficients from the inner products and the Gram row of q_j
-      for (int i = 0; i < j; ++i) {
-        const cplx l(c.host[kDots + 4 * i + 2], c.host[kDots + 4 * i + 3]);
+      for (int i = kGramMax; i < j; ++i) {
+        const cplx l(c.host[kGram2 + 2 * (i - kGramMax)], c.host[kGram2 + 2 * (i - kGramMax) + 1]);
         Gij(j, i) = std::conj(l) / (nu[i] * nu[j]);
       }
+      // MGS coefficients from the inner products and the Gram matrix
       for (int i = 0; i <= j; ++i) {
-        cplx h = cplx(c.host[kDots + 4 * i], c.host[kDots + 4 * i + 1]) / (nu[i] * nu[j]);
+        cplx h = cplx(c.host[kDots + 2 * i], c.host[kDots + 2 * i + 1]) / (nu[i] * nu[j]);
         for (int l = 0; l < i; ++l) h -= Gij(i, l) * hcol[l];
         hcol[i] = h;
         coef[i] = nu[j] * h / nu[i];
       }
       st = upload_coefs(c, kCoef, coef, j + 1);
       if (st != H6_OK) return st;
-      timing_begin(P, KC_MGS, c.s, &ev);
-      H6_TRY_HIP(launch_update_norm(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s));
-      timing_end(P, KC_MGS, c.s, ev);
-      st = fetch(c, kNorm, 1);
+      timing_begin(P, KC_MGS_UPDATE, c.s, &ev);
+      H6_TRY_HIP(launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s));
+      timing_end(P, KC_MGS_UPDATE, c.s, ev, double(N) * sizeof(double2) * (j + 3));
+      const int ng = std::min(j + 1, kGramMax);
+      st = fetch(c, kNorm, 1 + 2 * ng);
       if (st != H6_OK) return st;
       nu[j + 1] = std::sqrt(std::max(c.host[kNorm], 0.0));
+      for (int i = 0; i < ng; ++i) {
+        const cplx l(c.host[kNorm + 1 + 2 * i], c.host[kNorm + 2 + 2 * i]);
+        Gij(j + 1, i) = std::conj(l) / (nu[i] * nu[j + 1]);
+      }
       const double hn = nu[j + 1] / nu[j];
       for (int i = 0; i <= j; ++i) Hij(i, j) = hcol[i];
       // previous rotations on column j
@@ -211,16 +234,20 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
     hipEvent_t ev;
     if (flex) {
       timing_begin(P, KC_AXPY, c.s, &ev);
-      H6_TRY_HIP(launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, jdone, N, 1, c.s));
-      timing_end(P, KC_AXPY, c.s, ev);
+      if (mixed)
+        H6_TRY_HIP(launch_multi_axpy_f32(U, static_cast<float2*>(P->Z), dy, jdone, N, 1, c.s));
+      else
+        H6_TRY_HIP(launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, jdone, N, 1, c.s));
+      timing_end(P, KC_AXPY, c.s, ev,
+                 double(N) * (jdone * (mixed ? sizeof(float2) : sizeof(double2)) + 2 * sizeof(double2)));
     } else {
       timing_begin(P, KC_AXPY, c.s, &ev);
       H6_TRY_HIP(launch_multi_axpy(P->t, P->V, dy, jdone, N, 0, c.s));
-      timing_end(P, KC_AXPY, c.s, ev);
+      timing_end(P, KC_AXPY, c.s, ev, double(N) * sizeof(double2) * (jdone + 1));
       H6_TRY_HIP(launch_pinv(P, P->t, P->r, c.s));
       timing_begin(P, KC_AXPY, c.s, &ev);
       H6_TRY_HIP(launch_add(U, P->r, N, c.s));
-      timing_end(P, KC_AXPY, c.s, ev);
+      timing_end(P, KC_AXPY, c.s, ev, double(N) * sizeof(double2) * 3);
     }
     st = residual(c, F, U, P->V, &beta2);
     if (st != H6_OK) return st;
@@ -247,7 +274,7 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
     hipEvent_t ev;
     timing_begin(P, KC_AXPY, c.s, &ev);
     H6_TRY_HIP(launch_add(U, P->t, c.N, c.s));
-    timing_end(P, KC_AXPY, c.s, ev);
+    timing_end(P, KC_AXPY, c.s, ev, double(c.N) * sizeof(double2) * 3);
     st = residual(c, F, U, P->r, &r2);
     if (st != H6_OK) return st;
     info->iters += 1;

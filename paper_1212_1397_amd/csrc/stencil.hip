@@ -51,9 +51,9 @@ __device__ __forceinline__ void apply_w(double2& acc, const W9& w, const S3& s) 
 
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-template <bool RESID>
+template <bool RESID, typename Tin>
 __global__ __launch_bounds__(kThreads) void stencil_kernel(
-    const double2* __restrict__ x, double2* __restrict__ y, const double2* __restrict__ F,
+    const Tin* __restrict__ x, double2* __restrict__ y, const double2* __restrict__ F,
     double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
     int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg) {
   __shared__ double2 tile[2][kLY][kLX];
@@ -95,7 +95,10 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
       v[i] = make_double2(0.0, 0.0);
-      if (p >= 0 && p < nz && src_off[i] >= 0) v[i] = x[size_t(p) * plane + src_off[i]];
+      if (p >= 0 && p < nz && src_off[i] >= 0) {
+        const Tin t = x[size_t(p) * plane + src_off[i]];
+        v[i] = make_double2(double(t.x), double(t.y));
+      }
     }
   };
   auto store_plane = [&](int b, const double2 (&v)[kLoads]) {
@@ -174,8 +177,9 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 
 }  // namespace
 
-hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
-                          double* partials, int* nparts, hipStream_t s) {
+template <typename Tin>
+hipError_t stencil_impl(h6_plan P, const Tin* x, double2* y, const double2* F, double* partials,
+                        int* nparts, hipStream_t s) {
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
   const int nwg = ntx * nty * ntz;
@@ -184,16 +188,26 @@ hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2
   hipEvent_t ev;
   timing_begin(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, &ev);
   if (resid)
-    hipLaunchKernelGGL(stencil_kernel<true>, dim3(nwg), dim3(kThreads), 0, s, x, y, F, partials,
+    hipLaunchKernelGGL((stencil_kernel<true, Tin>), dim3(nwg), dim3(kThreads), 0, s, x, y, F, partials,
                        P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
                        P->zhi_closure, ntx, nty, nwg);
   else
-    hipLaunchKernelGGL(stencil_kernel<false>, dim3(nwg), dim3(kThreads), 0, s, x, y, nullptr,
+    hipLaunchKernelGGL((stencil_kernel<false, Tin>), dim3(nwg), dim3(kThreads), 0, s, x, y, nullptr,
                        nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
                        P->zlo_closure, P->zhi_closure, ntx, nty, nwg);
-  timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev);
+  timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev,
+             double(P->N) * (sizeof(Tin) + sizeof(double2) * (resid ? 2 : 1)));
   if (nparts) *nparts = nwg;
   return hipGetLastError();
+}
+
+hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
+                          double* partials, int* nparts, hipStream_t s) {
+  return stencil_impl(P, x, y, F, partials, nparts, s);
+}
+
+hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s) {
+  return stencil_impl(P, x, y, static_cast<const double2*>(nullptr), nullptr, nullptr, s);
 }
 
 }  // namespace h6

@@ -362,6 +362,8 @@ template hipError_t launch_rader_x<float, double2, float2>(bool, bool, const dou
                                                            int, const RaderTables&, hipStream_t);
 template hipError_t launch_rader_x<float, float2, double2>(bool, bool, const float2*, double2*, int,
                                                            int, const RaderTables&, hipStream_t);
+template hipError_t launch_rader_x<float, float2, float2>(bool, bool, const float2*, float2*, int,
+                                                          int, const RaderTables&, hipStream_t);
 template hipError_t launch_rader_y<double, double2>(bool, bool, const double2*, double2*, int, int,
                                                     int, const RaderTables&, hipStream_t);
 template hipError_t launch_rader_y<float, float2>(bool, bool, const float2*, float2*, int, int, int,

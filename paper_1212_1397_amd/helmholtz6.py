@@ -21,8 +21,8 @@ H6_ERR_ARG, H6_ERR_UNSUPPORTED_BC, H6_ERR_ALLOC, H6_ERR_HIP, H6_ERR_SINGULAR = -
 BC_CODES = {"D": 0, "N": 1, "S": 2}
 METHODS = {"gmres": 0, "fgmres": 1, "sks": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs", "norm",
-                  "axpy", "rhs")
+KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs_dots",
+                  "mgs_update", "norm", "axpy", "rhs")
 
 EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
@@ -56,7 +56,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_solve.argtypes = [vp, vp, vp, ctypes.POINTER(H6SolveInfo), vp]
     lib.helmholtz6_profile.argtypes = [vp, ip]
     lib.helmholtz6_kernel_time.argtypes = [vp, ctypes.c_char_p, ip, ctypes.POINTER(ctypes.c_double),
-                                           ctypes.POINTER(ctypes.c_longlong)]
+                                           ctypes.POINTER(ctypes.c_longlong),
+                                           ctypes.POINTER(ctypes.c_double)]
     lib.helmholtz6_destroy.argtypes = [vp]
     lib.helmholtz6_destroy.restype = None
     lib.helmholtz6_status_string.argtypes = [ip]
@@ -171,11 +172,13 @@ class Plan:
         self._check(_lib.helmholtz6_profile(self._plan, int(enable)))
 
     def kernel_time(self, name: str, reset: bool = False):
+        """(total ms, launches, algorithmic bytes) of one kernel class since the last reset."""
         ms = ctypes.c_double()
         n = ctypes.c_longlong()
+        b = ctypes.c_double()
         self._check(_lib.helmholtz6_kernel_time(self._plan, name.encode(), int(reset), ctypes.byref(ms),
-                                                ctypes.byref(n)))
-        return ms.value, n.value
+                                                ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def close(self):
         if getattr(self, "_plan", None) and self._plan.value:
