@@ -205,8 +205,17 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
   std::vector<int> slot_d(M - 1), slot_n(M + 1);
   for (int p = 0; p < M - 1; ++p) slot_d[p] = slot_of_q[p + 1];
   for (int p = 0; p <= M; ++p) slot_n[p] = slot_of_q[p];
+  std::vector<float2> kff(P1), twf(256);
+  std::vector<float> saf(P1), caf(P1);
+  for (int k = 0; k < P1; ++k) kff[k] = make_float2(float(kf[k].x), float(kf[k].y));
+  for (int t = 0; t < 256; ++t) twf[t] = make_float2(float(tw[t].x), float(tw[t].y));
+  for (int a = 0; a < P1; ++a) {
+    saf[a] = float(sa[a]);
+    caf[a] = float(ca[a]);
+  }
   const size_t bytes = 2 * P1 * sizeof(int) + 2 * P1 * sizeof(double2) + 2 * P1 * sizeof(double) +
-                       (2 * M + 1) * sizeof(int) + 256;
+                       (2 * M + 1) * sizeof(int) + 2 * P1 * sizeof(float2) + 2 * P1 * sizeof(float) +
+                       16 * 16;
   char* mem = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&mem), bytes + 64);
   if (e != hipSuccess) return e;
@@ -228,6 +237,10 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
   ax.rader.slot_n = reinterpret_cast<const int*>(put(slot_n.data(), (M + 1) * sizeof(int)));
   ax.rader.perm_in = reinterpret_cast<const int*>(put(pin.data(), P1 * sizeof(int)));
   ax.rader.perm_out = reinterpret_cast<const int*>(put(pout.data(), P1 * sizeof(int)));
+  ax.rader.kf_f = reinterpret_cast<const float2*>(put(kff.data(), P1 * sizeof(float2)));
+  ax.rader.tw_f = reinterpret_cast<const float2*>(put(twf.data(), 256 * sizeof(float2)));
+  ax.rader.sin_f = reinterpret_cast<const float*>(put(saf.data(), P1 * sizeof(float)));
+  ax.rader.cos_f = reinterpret_cast<const float*>(put(caf.data(), P1 * sizeof(float)));
   if (off > bytes + 64) return hipErrorInvalidValue;
   e = hipMemcpyAsync(mem, host.data(), off, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
@@ -252,6 +265,8 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->t);
   (void)hipFree(P->partials);
   (void)hipFree(P->d_scal);
+  (void)hipFree(P->d_gram);
+  if (P->ev_sync) (void)hipEventDestroy(P->ev_sync);
   if (P->h_pinned) (void)hipHostFree(P->h_pinned);
   for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
   for (auto& pe : P->timing.pending) {

@@ -99,6 +99,8 @@ struct h6_plan_s {
   double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
   double2* d_scal = nullptr;                   // device scalars: reduction results, coefficients (kScal entries)
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
+  double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
+  hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
 
   h6::Timing timing;
   std::string last_error;
@@ -113,12 +115,31 @@ constexpr int kGramMax = 16;       // Gram row entries formed by launch_update_g
 constexpr int kZSegs = 32;         // segments per z line in the partitioned z solver
 constexpr int kMaxZ = kZSegs * 17; // largest n'z of the partitioned z solver
 
+// Workgroup id remap for the 8 XCDs of the chip: the hardware hands out
+// consecutive workgroup ids round-robin over the XCDs (each with its own L2);
+// the remap gives each XCD a contiguous range of logical ids, so neighbouring
+// tiles that share cache lines or halos run under the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nwg) {
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int per = nwg >> 3, rem = nwg & 7;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
 // kernel launchers (stream-ordered, no synchronisation)
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
                           double* partials, int* nparts, hipStream_t s);
-hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s);
+// Preconditioner passes: PINV_FIRST is the forward x transform of r alone,
+// PINV_REST the remaining passes (forward y, z solves, inverse y and x) on the
+// plan's workspace, so a caller can enqueue the first pass before it waits on
+// the host.  PINV_ALL = both.
+enum { PINV_FIRST = 1, PINV_REST = 2, PINV_ALL = 3 };
+hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part = PINV_ALL);
+// U += A_p^{-1} r (the update folded into the last inverse transform)
+hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s,
+                           int part = PINV_ALL);
 // mixed plans only: z = A_p^{-1} r stored in complex64
-hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s);
+hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s,
+                              int part = PINV_ALL);
 // y = A x for a complex64 x (FP64 arithmetic)
 hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s);
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
@@ -133,11 +154,19 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
 // w -= sum_{i<m} c_i q_i; out[0] = |w|^2, out[1+2i..2+2i] = <q_i, w> for i < min(m, kGramMax)
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
                               double* partials, double* out, hipStream_t s);
+// MGS coefficients of Arnoldi step j on the device (one workgroup), from the
+// block dots <q~_i, w~> (dots, i <= j), the norm / Gram row of the last update
+// pass (nrow: |q~_j|^2, <q~_i, q~_j> for i < min(j, kGramMax)) and the extra
+// Gram entries i = kGramMax .. j-1 (gram2): stores nu_j, row j of the Gram
+// matrix G (ld gdim), the Hessenberg column h (hcol) and the update
+// coefficients c_i = nu_j h_i / nu_i (coef).
+hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
+                           double* nu, double2* G, int gdim, double2* hcol, double2* coef,
+                           hipStream_t s);
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
                              int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
 hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y, int m, size_t n,
                                  int accumulate, hipStream_t s);
-hipError_t launch_add(double2* U, const double2* z, size_t n, hipStream_t s);   // U += z
 
 // timing helpers
 void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a);

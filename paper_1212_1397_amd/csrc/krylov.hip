@@ -2,7 +2,7 @@
 //
 // GMRES orthogonalisation is modified Gram-Schmidt written in its inverse
 // compact WY form: for a new vector w and an (unnormalised) basis Q, one pass
-// forms all inner products <q_i, w>; the host turns them into the MGS
+// forms all inner products <q_i, w>; a one-wave kernel turns them into the MGS
 // coefficients with the Gram matrix of the basis (a small triangular solve);
 // one more pass applies w -= sum_i c_i q_i and, while the basis streams by,
 // forms |w|^2 and the Gram row <q_i, w> of the new basis vector.  This moves
@@ -11,8 +11,10 @@
 // arithmetic.
 //
 // Reductions are deterministic: a fixed grid (one full wave of resident
-// blocks) writes one partial per block and component in grid-stride order,
-// and a second kernel sums each component's partials in a fixed tree order.
+// blocks) writes one partial per block and component in
+// grid-stride order, and a second kernel sums each component's partials in a
+// fixed tree order.  Load loops use compile-time vector counts, so every load
+// of an element is issued before the first one is waited on.
 #include "h6_internal.h"
 
 namespace h6 {
@@ -56,69 +58,133 @@ __global__ __launch_bounds__(kThreads) void norm2_kernel(const double2* __restri
   block_store<1>(v, partials, 0, gridDim.x);
 }
 
-// For basis vectors q_{i0 .. i0+cnt-1} (stride n from Q): partials of
-// <q_i, w> (components 2 i, 2 i + 1 = re, im).
-template <int CH>
+// For basis vectors q_{i0 .. i0+CNT-1} (stride n from Q): partials of
+// <q_i, w> (components 2 i, 2 i + 1 = re, im).  CNT is a compile-time count so
+// that all CNT + 1 loads of an element are issued back to back, unconditionally.
+template <int CNT>
 __global__ __launch_bounds__(kThreads) void block_dots_kernel(const double2* __restrict__ Q, int i0,
-                                                              int cnt, const double2* __restrict__ w,
+                                                              const double2* __restrict__ w,
                                                               size_t n, double* __restrict__ partials) {
-  double acc[2 * CH];
+  double acc[2 * CNT];
 #pragma unroll
-  for (int c = 0; c < 2 * CH; ++c) acc[c] = 0.0;
+  for (int c = 0; c < 2 * CNT; ++c) acc[c] = 0.0;
+  const double2* __restrict__ Qb = Q + size_t(i0) * n;
   for (size_t k = blockIdx.x * size_t(kThreads) + threadIdx.x; k < n; k += size_t(gridDim.x) * kThreads) {
     const double2 x = w[k];
+    double2 q[CNT];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      if (i < cnt) {
-        const double2 q = Q[size_t(i0 + i) * n + k];
-        acc[2 * i] = fma(q.x, x.x, fma(q.y, x.y, acc[2 * i]));
-        acc[2 * i + 1] = fma(q.x, x.y, fma(-q.y, x.x, acc[2 * i + 1]));
-      }
+    for (int i = 0; i < CNT; ++i) q[i] = Qb[size_t(i) * n + k];
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      acc[2 * i] = fma(q[i].x, x.x, fma(q[i].y, x.y, acc[2 * i]));
+      acc[2 * i + 1] = fma(q[i].x, x.y, fma(-q[i].y, x.x, acc[2 * i + 1]));
     }
   }
-  block_store<2 * CH>(acc, partials, 2 * i0, gridDim.x);
+  block_store<2 * CNT>(acc, partials, 2 * i0, gridDim.x);
 }
 
 // w -= sum_{i < m} c_i q_i, then partials of |w|^2 (component 0) and of
-// <q_i, w> for i < min(m, CH) (components 1 + 2 i, 2 + 2 i): the Gram row of
-// the new basis vector w, formed while the basis is streamed for the update.
-template <int CH>
+// <q_i, w> for i < MG = min(m, kGramMax) (components 1 + 2 i, 2 + 2 i): the
+// Gram row of the new basis vector w, formed while the basis is streamed for
+// the update.  Vectors beyond MG (m > kGramMax) are applied four at a time
+// (loads past m re-read q_{m-1} with a zero coefficient).
+template <int MG>
 __global__ __launch_bounds__(kThreads) void update_gram_kernel(double2* __restrict__ w,
                                                                const double2* __restrict__ Q,
                                                                const double2* __restrict__ c, int m,
                                                                size_t n, double* __restrict__ partials) {
-  double acc[1 + 2 * CH];
+  double acc[1 + 2 * MG];
 #pragma unroll
-  for (int i = 0; i < 1 + 2 * CH; ++i) acc[i] = 0.0;
-  const int mg = m < CH ? m : CH;
+  for (int i = 0; i < 1 + 2 * MG; ++i) acc[i] = 0.0;
+  double2 cf[MG];
+#pragma unroll
+  for (int i = 0; i < MG; ++i) cf[i] = c[i];
   for (size_t k = blockIdx.x * size_t(kThreads) + threadIdx.x; k < n; k += size_t(gridDim.x) * kThreads) {
     double2 x = w[k];
-    double2 q[CH];
+    double2 q[MG];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      if (i < mg) {
-        q[i] = Q[size_t(i) * n + k];
-        const double2 a = c[i];
-        x.x -= a.x * q[i].x - a.y * q[i].y;
-        x.y -= a.x * q[i].y + a.y * q[i].x;
-      }
+    for (int i = 0; i < MG; ++i) q[i] = Q[size_t(i) * n + k];
+#pragma unroll
+    for (int i = 0; i < MG; ++i) {
+      x.x -= cf[i].x * q[i].x - cf[i].y * q[i].y;
+      x.y -= cf[i].x * q[i].y + cf[i].y * q[i].x;
     }
-    for (int i = CH; i < m; ++i) {
-      const double2 a = c[i], qq = Q[size_t(i) * n + k];
-      x.x -= a.x * qq.x - a.y * qq.y;
-      x.y -= a.x * qq.y + a.y * qq.x;
+    for (int i = MG; i < m; i += 4) {
+      double2 qq[4], a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ii = i + u < m ? i + u : m - 1;
+        qq[u] = Q[size_t(ii) * n + k];
+        a[u] = i + u < m ? c[i + u] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x.x -= a[u].x * qq[u].x - a[u].y * qq[u].y;
+        x.y -= a[u].x * qq[u].y + a[u].y * qq[u].x;
+      }
     }
     w[k] = x;
     acc[0] = fma(x.x, x.x, fma(x.y, x.y, acc[0]));
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      if (i < mg) {
-        acc[1 + 2 * i] = fma(q[i].x, x.x, fma(q[i].y, x.y, acc[1 + 2 * i]));
-        acc[2 + 2 * i] = fma(q[i].x, x.y, fma(-q[i].y, x.x, acc[2 + 2 * i]));
-      }
+    for (int i = 0; i < MG; ++i) {
+      acc[1 + 2 * i] = fma(q[i].x, x.x, fma(q[i].y, x.y, acc[1 + 2 * i]));
+      acc[2 + 2 * i] = fma(q[i].x, x.y, fma(-q[i].y, x.x, acc[2 + 2 * i]));
     }
   }
-  block_store<1 + 2 * CH>(acc, partials, 0, gridDim.x);
+  block_store<1 + 2 * MG>(acc, partials, 0, gridDim.x);
+}
+
+// MGS coefficients of Arnoldi step j (one wave):
+//   nu_j = |q~_j|,  G_{j,i} = conj(<q~_i, q~_j>) / (nu_i nu_j)  (i < j),
+//   h_i = <q~_i, w~> / (nu_i nu_j) - sum_{l<i} G_{i,l} h_l,  c_i = nu_j h_i / nu_i.
+// The triangular recurrence runs over i; each inner sum is split over the
+// lanes and reduced in a fixed order.
+constexpr int kCoefMax = 257;
+__global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __restrict__ dots,
+                                                      const double* __restrict__ nrow,
+                                                      const double* __restrict__ gram2,
+                                                      double* __restrict__ nu, double2* __restrict__ G,
+                                                      int gdim, double2* __restrict__ hcol,
+                                                      double2* __restrict__ coef) {
+  __shared__ double2 h[kCoefMax];
+  const int t = threadIdx.x;
+  const double nuj = sqrt(fmax(nrow[0], 0.0));
+  if (t == 0) nu[j] = nuj;
+  for (int i = t; i < j; i += 64) {
+    double lx, ly;
+    if (i < kGramMax) {
+      lx = nrow[1 + 2 * i];
+      ly = nrow[2 + 2 * i];
+    } else {
+      lx = gram2[2 * (i - kGramMax)];
+      ly = gram2[2 * (i - kGramMax) + 1];
+    }
+    const double d = nu[i] * nuj;
+    G[size_t(j) * gdim + i] = make_double2(lx / d, -ly / d);
+  }
+  __syncthreads();
+  for (int i = 0; i <= j; ++i) {
+    double ax = 0.0, ay = 0.0;
+    for (int l = t; l < i; l += 64) {
+      const double2 g = G[size_t(i) * gdim + l], hl = h[l];
+      ax += g.x * hl.x - g.y * hl.y;
+      ay += g.x * hl.y + g.y * hl.x;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      ax += __shfl_xor(ax, o, 64);
+      ay += __shfl_xor(ay, o, 64);
+    }
+    if (t == 0) {
+      const double nui = i == j ? nuj : nu[i];
+      const double d = nui * nuj;
+      const double2 hv = make_double2(dots[2 * i] / d - ax, dots[2 * i + 1] / d - ay);
+      h[i] = hv;
+      hcol[i] = hv;
+      const double f = nuj / nui;
+      coef[i] = make_double2(f * hv.x, f * hv.y);
+    }
+    __syncthreads();
+  }
 }
 
 // out[c] = sum_b partials[c * nblocks + b], one block per component
@@ -137,30 +203,30 @@ __global__ __launch_bounds__(kThreads) void reduce_cols_kernel(const double* __r
   if (threadIdx.x == 0) out[blockIdx.x] = s[0];
 }
 
-// out (+)= sum_i y_i V_i, V_i = V + i * n (FP64 arithmetic)
+// out (+)= sum_i y_i V_i, V_i = V + i * n (FP64 arithmetic).  Vectors are
+// taken eight at a time with all eight loads issued together (loads past m
+// re-read V_{m-1} with a zero coefficient).
 template <typename TV>
 __global__ __launch_bounds__(kThreads) void multi_axpy_kernel(double2* __restrict__ out,
                                                               const TV* __restrict__ V,
                                                               const double2* __restrict__ y, int m,
                                                               size_t n, int accumulate) {
+  constexpr int kU = 8;
   for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
     double2 acc = accumulate ? out[i] : make_double2(0.0, 0.0);
-    for (int j = 0; j < m; ++j) {
-      const double2 c = y[j];
-      const TV vv = V[size_t(j) * n + i];
-      const double2 v = make_double2(double(vv.x), double(vv.y));
-      acc.x += c.x * v.x - c.y * v.y;
-      acc.y += c.x * v.y + c.y * v.x;
+    for (int j = 0; j < m; j += kU) {
+      TV vv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) vv[u] = V[size_t(j + u < m ? j + u : m - 1) * n + i];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const double2 c = j + u < m ? y[j + u] : make_double2(0.0, 0.0);
+        const double2 v = make_double2(double(vv[u].x), double(vv[u].y));
+        acc.x += c.x * v.x - c.y * v.y;
+        acc.y += c.x * v.y + c.y * v.x;
+      }
     }
     out[i] = acc;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void add_kernel(double2* __restrict__ U,
-                                                       const double2* __restrict__ z, size_t n) {
-  for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
-    const double2 a = U[i], b = z[i];
-    U[i] = make_double2(a.x + b.x, a.y + b.y);
   }
 }
 
@@ -174,6 +240,15 @@ constexpr int kGramChunk = kGramMax;
 
 }  // namespace
 
+hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
+                           double* nu, double2* G, int gdim, double2* hcol, double2* coef,
+                           hipStream_t s) {
+  if (j < 0 || j >= kCoefMax || j >= gdim) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mgs_coef_kernel, dim3(1), dim3(64), 0, s, j, dots, nrow, gram2, nu, G, gdim,
+                     hcol, coef);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s) {
   hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, n, partials);
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
@@ -185,29 +260,45 @@ hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hi
   return hipGetLastError();
 }
 
+// Grid of the reductions: one full wave of resident blocks of the widest
+// block_dots instance (no tail), at most 2048 (the partials capacity: 514
+// components x 2048 blocks).  The same grid serves every instance: more
+// blocks did not help the narrow ones.
 int reduction_blocks() {
   static int blocks = 0;
   if (!blocks) {
     int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, block_dots_kernel<kDotChunk>, kThreads, 0) !=
-            hipSuccess || cus <= 0 || per <= 0)
-      blocks = kRedBlocks;
-    else
-      blocks = cus * per;      // one full wave of resident blocks, no tail
-    if (blocks > kRedBlocks * 2) blocks = kRedBlocks * 2;   // partials capacity: 514 x 2048
+    blocks = kRedBlocks;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, block_dots_kernel<kDotChunk>, kThreads, 0) ==
+            hipSuccess &&
+        cus > 0 && per > 0)
+      blocks = cus * per;
+    if (blocks > kRedBlocks * 2) blocks = kRedBlocks * 2;
   }
   return blocks;
 }
 
+// compile-time chunk counts 1..16
+#define H6_COUNTS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n, double* partials,
                              double* out, hipStream_t s) {
+  // one grid size for all chunks (the partials of all 2m components are
+  // reduced together)
   const int nb = reduction_blocks();
   for (int i0 = 0; i0 < m; i0 += kDotChunk) {
     const int cnt = m - i0 < kDotChunk ? m - i0 : kDotChunk;
-    hipLaunchKernelGGL(block_dots_kernel<kDotChunk>, dim3(nb), dim3(kThreads), 0, s, Q, i0, cnt, w, n,
-                       partials);
+    switch (cnt) {
+#define H6_DOTS(C)                                                                                \
+  case C:                                                                                         \
+    hipLaunchKernelGGL(block_dots_kernel<C>, dim3(nb), dim3(kThreads), 0, s, Q, i0, w, n, partials); \
+    break;
+      H6_COUNTS(H6_DOTS)
+#undef H6_DOTS
+      default: return hipErrorInvalidValue;
+    }
   }
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(2 * m), dim3(kThreads), 0, s, partials, nb, out);
   return hipGetLastError();
@@ -216,9 +307,17 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
                               double* partials, double* out, hipStream_t s) {
   const int nb = reduction_blocks();
-  hipLaunchKernelGGL(update_gram_kernel<kGramChunk>, dim3(nb), dim3(kThreads), 0, s, w, Q, c, m, n,
-                     partials);
   const int mg = m < kGramChunk ? m : kGramChunk;
+  if (mg < 1) return hipErrorInvalidValue;
+  switch (mg) {
+#define H6_UPD(C)                                                                                  \
+  case C:                                                                                          \
+    hipLaunchKernelGGL(update_gram_kernel<C>, dim3(nb), dim3(kThreads), 0, s, w, Q, c, m, n, partials); \
+    break;
+    H6_COUNTS(H6_UPD)
+#undef H6_UPD
+    default: return hipErrorInvalidValue;
+  }
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out);
   return hipGetLastError();
 }
@@ -234,11 +333,6 @@ hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y
                                  int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(multi_axpy_kernel<float2>, dim3(grid_for(n)), dim3(kThreads), 0, s, out, V, y, m,
                      n, accumulate);
-  return hipGetLastError();
-}
-
-hipError_t launch_add(double2* U, const double2* z, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(add_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, U, z, n);
   return hipGetLastError();
 }
 

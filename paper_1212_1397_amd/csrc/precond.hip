@@ -90,7 +90,7 @@ template <typename Tin, typename Tout, typename R>
 __global__ __launch_bounds__(256) void xform_x_kernel(const Tin* __restrict__ in,
                                                       Tout* __restrict__ out, int nlines, int L,
                                                       int M, int neumann, int inverse,
-                                                      const double* __restrict__ trig) {
+                                                      const double* __restrict__ trig, int acc) {
   using T2 = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   R* sinT = reinterpret_cast<R*>(smem_raw);
@@ -107,7 +107,13 @@ __global__ __launch_bounds__(256) void xform_x_kernel(const Tin* __restrict__ in
   __syncthreads();
   for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
     const int b = e / L, m = e - b * L;
-    out[base + e] = cvt<Tout>(dense_out<R>(buf + b * L, 1, L, M, neumann, inverse, m, sinT, cosT));
+    Tout v = cvt<Tout>(dense_out<R>(buf + b * L, 1, L, M, neumann, inverse, m, sinT, cosT));
+    if (acc) {                    // out += result
+      const Tout o = out[base + e];
+      v.x += o.x;
+      v.y += o.y;
+    }
+    out[base + e] = v;
   }
 }
 
@@ -200,9 +206,13 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
     const double* __restrict__ lx, const double* __restrict__ ly, double kap_re, double kap_im,
     int nx, int ny, int nz) {
   using T2 = typename C2<R>::T;
+  constexpr int kThr = kTriLines * kSegs;
+  constexpr int kTabPer = (3 * kMaxZ + kThr - 1) / kThr;
   __shared__ T2 sh[2][kSegs][kTriLines];
-  const int lane = threadIdx.x % kTriLines;
-  const int seg = threadIdx.x / kTriLines;
+  __shared__ T2 tz[kTabPer * kThr];  // sub-, main and super-diagonal of T_z (main without the shift)
+  const int tid = threadIdx.x;
+  const int lane = tid % kTriLines;
+  const int seg = tid / kTriLines;
   const int nmodes = nx * ny;
   const int mode = blockIdx.x * kTriLines + lane;
   const bool active = mode < nmodes;
@@ -211,22 +221,33 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
   const size_t stride = size_t(nx) * ny;
   const int S = (nz + kSegs - 1) / kSegs;
   const int r0 = min(seg * S, nz), cnt = min(S, nz - r0);
-  const T2 shift = mk<R>(R(kap_re + lx[i] + ly[j]), R(kap_im));
   const T2 one = mk<R>(1, 0), zero = mk<R>(0, 0);
 
+  // All global reads are issued up front and unconditionally (clamped
+  // indices): first the matrix (it is written to LDS first, so waiting for it
+  // leaves the vector loads in flight), then the start value of c', the
+  // transverse eigenvalues and this thread's rows of the vector.
+  double2 tv[kTabPer];
+#pragma unroll
+  for (int k = 0; k < kTabPer; ++k) tv[k] = tri[min(tid + k * kThr, 3 * nz - 1)];
+  const T2 cst = cstart[size_t(seg) * nmodes + mc];
+  const double lxi = lx[i], lyj = ly[j];
   T2 d[kSmax], ip[kSmax];     // right-hand side, then d'; inverse pivots 1/m_i
 #pragma unroll
-  for (int u = 0; u < kSmax; ++u)
-    d[u] = (u < cnt && active) ? in[mode + size_t(r0 + u) * stride] : zero;
+  for (int u = 0; u < kSmax; ++u) d[u] = in[mc + size_t(min(r0 + u, nz - 1)) * stride];
+#pragma unroll
+  for (int k = 0; k < kTabPer; ++k) tz[tid + k * kThr] = cvt<T2>(tv[k]);   // entries past 3 n'z unused
+  __syncthreads();
+  const T2 shift = mk<R>(R(kap_re + lxi + lyj), R(kap_im));
 
   // local pass: c' from the stored start value, inverse pivots, and the
   // affine map d'_{last} = A d'_{r0-1} + B
-  T2 cprev = cstart[size_t(seg) * nmodes + mc], A = one, B = zero;
+  T2 cprev = cst, A = one, B = zero;
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
       const int r = r0 + u;
-      const T2 a = cvt<T2>(tri[r]), b = cadd<R>(cvt<T2>(tri[nz + r]), shift), c = cvt<T2>(tri[2 * nz + r]);
+      const T2 a = tz[r], b = cadd<R>(tz[nz + r], shift), c = tz[2 * nz + r];
       ip[u] = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
       const T2 al = cmulr<R>(mk<R>(-a.x, -a.y), ip[u]);
       A = cmulr<R>(al, A);
@@ -245,7 +266,7 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
-      const T2 a = cvt<T2>(tri[r0 + u]);
+      const T2 a = tz[r0 + u];
       d[u] = cmulr<R>(csub<R>(d[u], cmulr<R>(a, dprev)), ip[u]);
       dprev = d[u];
     }
@@ -254,7 +275,7 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      const T2 c = cvt<T2>(tri[2 * nz + r0 + u]);
+      const T2 c = tz[2 * nz + r0 + u];
       const T2 ncp = cmulr<R>(mk<R>(-c.x, -c.y), ip[u]);      // -c'_u
       D = cadd<R>(d[u], cmulr<R>(ncp, D));
       C = cmulr<R>(ncp, C);
@@ -269,15 +290,16 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      const T2 c = cvt<T2>(tri[2 * nz + r0 + u]);
+      const T2 c = tz[2 * nz + r0 + u];
       x = csub<R>(d[u], cmulr<R>(cmulr<R>(c, ip[u]), x));
       if (active) out[mode + size_t(r0 + u) * stride] = x;
     }
   }
 }
 
+// z = A_p^{-1} r, or z += A_p^{-1} r with acc != 0 (folded into the last pass)
 template <typename R, typename Tout>
-hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s) {
+hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s, int part, int acc = 0) {
   using T2 = typename C2<R>::T;
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   T2* w0 = static_cast<T2*>(P->w_pc[0]);
@@ -291,16 +313,16 @@ hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s) {
   hipEvent_t ev;
 
   const double Nd = double(P->N);
-  auto xform_x = [&](bool inv, auto* src, auto* dst) {
+  auto xform_x = [&](bool inv, auto* src, auto* dst, int accumulate) {
     timing_begin(P, KC_XFORM_X, s, &ev);
     if (X.fast)
-      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s);
+      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate);
     else
       hipLaunchKernelGGL((xform_x_kernel<std::remove_cv_t<std::remove_pointer_t<decltype(src)>>,
                                          std::remove_pointer_t<decltype(dst)>, R>),
                          gx, dim3(256), shx, s, src, dst, nlines_x, X.L, X.M, X.neumann, inv ? 1 : 0,
-                         P->d_trig_x);
-    timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst)));
+                         P->d_trig_x, accumulate);
+    timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst) * (accumulate ? 2 : 1)));
   };
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
     timing_begin(P, KC_XFORM_Y, s, &ev);
@@ -311,7 +333,8 @@ hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s) {
                          Y.neumann, inv ? 1 : 0, P->d_trig_y);
     timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
-  xform_x(false, r, w0);
+  if (part & PINV_FIRST) xform_x(false, r, w0, 0);
+  if (!(part & PINV_REST)) return hipGetLastError();
   xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
   {
@@ -330,20 +353,25 @@ hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s) {
   }
   timing_end(P, KC_TRIDIAG, s, ev, Nd * 2 * sizeof(T2));
   xform_y(true, w0, w1);
-  xform_x(true, static_cast<const T2*>(w1), z);
+  xform_x(true, static_cast<const T2*>(w1), z, acc);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s) {
-  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, z, s);
-  return pinv_impl<double, double2>(P, r, z, s);
+hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part) {
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, z, s, part);
+  return pinv_impl<double, double2>(P, r, z, s, part);
 }
 
-hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s) {
+hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s, int part) {
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, U, s, part, 1);
+  return pinv_impl<double, double2>(P, r, U, s, part, 1);
+}
+
+hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s, int part) {
   if (P->p.precision != H6_MIXED) return hipErrorInvalidValue;
-  return pinv_impl<float, float2>(P, r, z, s);
+  return pinv_impl<float, float2>(P, r, z, s, part);
 }
 
 }  // namespace h6

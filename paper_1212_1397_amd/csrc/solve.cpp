@@ -3,20 +3,22 @@
 // (Section 2, Algorithm 1) in correction form.
 //
 // Arnoldi: modified Gram-Schmidt in inverse compact WY form.  The basis is
-// kept unnormalised on the device (q~_i = nu_i q_i with nu_i known on the
-// host), so no scaling pass is needed.  Step j:
+// kept unnormalised on the device (q~_i = nu_i q_i), so no scaling pass is
+// needed.  Step j:
 //   z~ = A_p^{-1} q~_j,  w~ = A z~                      (w = w~ / nu_j)
 //   one pass:  s~_i = <q~_i, w~>,  i <= j
-//   host:      s_i = s~_i / (nu_i nu_j),
-//              h_i = s_i - sum_{l<i} G_{i,l} h_l   (the MGS coefficients),
-//              G_{i,l} = <q_i, q_l> (l < i) from earlier steps
-//   one pass:  w~ -= sum_i (nu_j h_i / nu_i) q~_i; |w~|^2 -> nu_{j+1} and the
-//              Gram row l~_i = <q~_i, w~>, G_{j+1,i} = conj(l~_i) / (nu_i nu_{j+1})
+//   device:    nu_j, row j of the Gram matrix G_{i,l} = <q_i, q_l>, and
+//              h_i = s~_i / (nu_i nu_j) - sum_{l<i} G_{i,l} h_l   (the MGS
+//              coefficients; one small kernel, no host round trip)
+//   one pass:  w~ -= sum_i (nu_j h_i / nu_i) q~_i; |w~|^2 and the Gram row
+//              <q~_i, w~> of the next basis vector
 //   H(0..j, j) = h,  H(j+1, j) = nu_{j+1} / nu_j,
 // followed by the complex Givens update of the least-squares problem on the
-// host (FP64).  The cycle's stopping test uses the least-squares residual;
-// convergence is declared on the true residual ||F - A U|| / ||F||,
-// recomputed at every restart.
+// host (FP64).  The host waits once per step, for h and |w~|^2; the first
+// preconditioner pass of the next step is enqueued before that wait, so the
+// device stays busy while the host decides whether to go on.  The cycle's
+// stopping test uses the least-squares residual; convergence is declared on
+// the true residual ||F - A U|| / ||F||, recomputed at every restart.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -32,6 +34,8 @@ constexpr int kNorm = 1100;     // one norm (update pass: norm + 2 kGramMax Gram
 constexpr int kCoef = 1200;     // 2 (m + 1) doubles: update coefficients (double2)
 constexpr int kY = 2000;        // 2 m doubles: least-squares coefficients (double2)
 constexpr int kGram2 = 3000;    // Gram entries beyond kGramMax (2 m doubles)
+constexpr int kNu = 3600;       // m + 1 doubles: basis norms nu_i
+constexpr int kHcol = 4000;     // 2 (m + 1) doubles: Hessenberg column of the current step
 
 struct Ctx {
   h6_plan P;
@@ -54,10 +58,19 @@ h6_status ensure(h6_plan P, int method, int m) {
     return e;
   };
   hipError_t e = hipSuccess;
-  if (!P->r) e = hipMalloc(reinterpret_cast<void**>(&P->r), vb);
+  if (!P->ev_sync) e = hipEventCreateWithFlags(&P->ev_sync, hipEventDisableTiming);
+  if (e == hipSuccess && !P->r) e = hipMalloc(reinterpret_cast<void**>(&P->r), vb);
   if (e == hipSuccess && !P->t) e = hipMalloc(reinterpret_cast<void**>(&P->t), vb);
-  if (e == hipSuccess && method != H6_SKS)
+  if (e == hipSuccess && method != H6_SKS) {
     e = grow(reinterpret_cast<void**>(&P->V), &P->V_cols, m + 1, vb);
+    if (e == hipSuccess && P->gram_dim < m + 1) {
+      (void)hipFree(P->d_gram);
+      P->d_gram = nullptr;
+      P->gram_dim = 0;
+      e = hipMalloc(reinterpret_cast<void**>(&P->d_gram), sizeof(double2) * size_t(m + 1) * (m + 1));
+      if (e == hipSuccess) P->gram_dim = m + 1;
+    }
+  }
   if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m, zb);
   if (e != hipSuccess) {
     P->last_error = std::string("workspace allocation failed: ") + hipGetErrorString(e);
@@ -66,11 +79,22 @@ h6_status ensure(h6_plan P, int method, int m) {
   return H6_OK;
 }
 
-h6_status fetch(Ctx& c, int off, int count) {
+// copy `count` doubles at `off` back to the pinned mirror; wait() blocks until
+// they (and only the work enqueued before them) are done
+h6_status fetch_async(Ctx& c, int off, int count) {
   h6_plan P = c.P;
   H6_TRY_HIP(hipMemcpyAsync(c.host + off, c.dev + off, sizeof(double) * count, hipMemcpyDeviceToHost, c.s));
-  H6_TRY_HIP(hipStreamSynchronize(c.s));
+  H6_TRY_HIP(hipEventRecord(P->ev_sync, c.s));
   return H6_OK;
+}
+h6_status wait(Ctx& c) {
+  h6_plan P = c.P;
+  H6_TRY_HIP(hipEventSynchronize(P->ev_sync));
+  return H6_OK;
+}
+h6_status fetch(Ctx& c, int off, int count) {
+  h6_status st = fetch_async(c, off, count);
+  return st == H6_OK ? wait(c) : st;
 }
 
 // |v|^2 on the host (synchronises)
@@ -85,15 +109,14 @@ h6_status norm2(Ctx& c, const double2* v, double* out) {
   return st;
 }
 
-// r = F - A U and |r|^2 on the host (synchronises)
-h6_status residual(Ctx& c, const double2* F, const double2* U, double2* r, double* out) {
+// r = F - A U with |r|^2 into the device slot kNorm and on its way to the host
+// (fetch_async: call wait() before reading c.host[kNorm])
+h6_status residual_async(Ctx& c, const double2* F, const double2* U, double2* r) {
   h6_plan P = c.P;
   int nparts = 0;
   H6_TRY_HIP(launch_stencil(P, U, r, F, P->partials, &nparts, c.s));
   H6_TRY_HIP(launch_reduce_sum(P->partials, nparts, c.dev + kNorm, c.s));
-  h6_status st = fetch(c, kNorm, 1);
-  *out = c.host[kNorm];
-  return st;
+  return fetch_async(c, kNorm, 1);
 }
 
 void record(h6_solve_info* info, int& nh, double v) {
@@ -128,16 +151,23 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   const bool mixed = P->p.precision == H6_MIXED;   // implies flex (checked at the ABI)
   const size_t N = c.N;
   int nh = 0;
-  double beta2 = 0.0;
   // the residual goes straight into the first basis slot (unnormalised)
-  h6_status st = residual(c, F, U, P->V, &beta2);
+  h6_status st = residual_async(c, F, U, P->V);
+  if (st == H6_OK) st = wait(c);
   if (st != H6_OK) return st;
-  std::vector<cplx> H(size_t(m + 1) * m), g(m + 1), sn(m), G(size_t(m + 1) * (m + 1)), hcol(m + 1),
-      coef(m + 1);
+  double beta2 = c.host[kNorm];
+  std::vector<cplx> H(size_t(m + 1) * m), g(m + 1), sn(m);
   std::vector<double> cs(m), nu(m + 1);
   auto Hij = [&](int i, int j) -> cplx& { return H[size_t(i) * m + j]; };
-  auto Gij = [&](int i, int j) -> cplx& { return G[size_t(i) * (m + 1) + j]; };
   const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
+  double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
+  // preconditioner passes of step j (z_j = A_p^{-1} q~_j)
+  auto pinv = [&](int j, int part) -> hipError_t {
+    const double2* qj = P->V + size_t(j) * N;
+    if (mixed) return launch_pinv_f32out(P, qj, static_cast<float2*>(P->Z) + size_t(j) * N, c.s, part);
+    double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
+    return launch_pinv(P, qj, z, c.s, part);
+  };
   info->iters = 0;
   while (true) {
     const double beta = std::sqrt(beta2);
@@ -149,57 +179,43 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
     std::fill(g.begin(), g.end(), cplx(0.0));
     g[0] = beta;
     int jdone = 0;
+    bool first_done = false;          // first preconditioner pass of step j already enqueued
     for (int j = 0; j < m; ++j) {
-      double2* qj = P->V + size_t(j) * N;
       double2* w = P->V + size_t(j + 1) * N;
-      if (mixed) {
-        float2* z = static_cast<float2*>(P->Z) + size_t(j) * N;
-        H6_TRY_HIP(launch_pinv_f32out(P, qj, z, c.s));
-        H6_TRY_HIP(launch_stencil_f32in(P, z, w, c.s));
-      } else {
-        double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
-        H6_TRY_HIP(launch_pinv(P, qj, z, c.s));
-        H6_TRY_HIP(launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s));
-      }
+      H6_TRY_HIP(pinv(j, first_done ? PINV_REST : PINV_ALL));
+      if (mixed)
+        H6_TRY_HIP(launch_stencil_f32in(P, static_cast<float2*>(P->Z) + size_t(j) * N, w, c.s));
+      else
+        H6_TRY_HIP(launch_stencil(P, flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t, w,
+                                  nullptr, nullptr, nullptr, c.s));
       info->iters += 1;
       hipEvent_t ev;
       timing_begin(P, KC_MGS_DOTS, c.s, &ev);
       H6_TRY_HIP(launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s));
       // Gram entries of q_j beyond the kGramMax formed by the last update pass
       if (j > kGramMax)
-        H6_TRY_HIP(launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, qj, N, P->partials,
-                                     c.dev + kGram2, c.s));
+        H6_TRY_HIP(launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, P->V + size_t(j) * N,
+                                     N, P->partials, c.dev + kGram2, c.s));
       timing_end(P, KC_MGS_DOTS, c.s, ev,
                  double(N) * sizeof(double2) * ((j + 2) + (j > kGramMax ? j - kGramMax + 1 : 0)));
-      st = fetch(c, kDots, 2 * (j + 1));
-      if (st == H6_OK && j > kGramMax) st = fetch(c, kGram2, 2 * (j - kGramMax));
-      if (st != H6_OK) return st;
-      for (int i = kGramMax; i < j; ++i) {
-        const cplx l(c.host[kGram2 + 2 * (i - kGramMax)], c.host[kGram2 + 2 * (i - kGramMax) + 1]);
-        Gij(j, i) = std::conj(l) / (nu[i] * nu[j]);
-      }
-      // MGS coefficients from the inner products and the Gram matrix
-      for (int i = 0; i <= j; ++i) {
-        cplx h = cplx(c.host[kDots + 2 * i], c.host[kDots + 2 * i + 1]) / (nu[i] * nu[j]);
-        for (int l = 0; l < i; ++l) h -= Gij(i, l) * hcol[l];
-        hcol[i] = h;
-        coef[i] = nu[j] * h / nu[i];
-      }
-      st = upload_coefs(c, kCoef, coef, j + 1);
-      if (st != H6_OK) return st;
+      H6_TRY_HIP(launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu,
+                                 P->d_gram, P->gram_dim, dhcol, reinterpret_cast<double2*>(c.dev + kCoef),
+                                 c.s));
       timing_begin(P, KC_MGS_UPDATE, c.s, &ev);
       H6_TRY_HIP(launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s));
       timing_end(P, KC_MGS_UPDATE, c.s, ev, double(N) * sizeof(double2) * (j + 3));
-      const int ng = std::min(j + 1, kGramMax);
-      st = fetch(c, kNorm, 1 + 2 * ng);
+      // h and |w~|^2 to the host; meanwhile the device starts on step j + 1
+      H6_TRY_HIP(hipMemcpyAsync(c.host + kHcol, c.dev + kHcol, sizeof(double) * 2 * (j + 1),
+                                hipMemcpyDeviceToHost, c.s));
+      st = fetch_async(c, kNorm, 1);
+      if (st != H6_OK) return st;
+      first_done = j + 1 < m && info->iters < info->maxit;
+      if (first_done) H6_TRY_HIP(pinv(j + 1, PINV_FIRST));
+      st = wait(c);
       if (st != H6_OK) return st;
       nu[j + 1] = std::sqrt(std::max(c.host[kNorm], 0.0));
-      for (int i = 0; i < ng; ++i) {
-        const cplx l(c.host[kNorm + 1 + 2 * i], c.host[kNorm + 2 + 2 * i]);
-        Gij(j + 1, i) = std::conj(l) / (nu[i] * nu[j + 1]);
-      }
+      for (int i = 0; i <= j; ++i) Hij(i, j) = cplx(c.host[kHcol + 2 * i], c.host[kHcol + 2 * i + 1]);
       const double hn = nu[j + 1] / nu[j];
-      for (int i = 0; i <= j; ++i) Hij(i, j) = hcol[i];
       // previous rotations on column j
       for (int i = 0; i < j; ++i) {
         const cplx t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
@@ -244,41 +260,42 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
       timing_begin(P, KC_AXPY, c.s, &ev);
       H6_TRY_HIP(launch_multi_axpy(P->t, P->V, dy, jdone, N, 0, c.s));
       timing_end(P, KC_AXPY, c.s, ev, double(N) * sizeof(double2) * (jdone + 1));
-      H6_TRY_HIP(launch_pinv(P, P->t, P->r, c.s));
-      timing_begin(P, KC_AXPY, c.s, &ev);
-      H6_TRY_HIP(launch_add(U, P->r, N, c.s));
-      timing_end(P, KC_AXPY, c.s, ev, double(N) * sizeof(double2) * 3);
+      H6_TRY_HIP(launch_pinv_acc(P, P->t, U, c.s));
     }
-    st = residual(c, F, U, P->V, &beta2);
+    st = residual_async(c, F, U, P->V);
+    if (st == H6_OK) st = wait(c);
     if (st != H6_OK) return st;
+    beta2 = c.host[kNorm];
   }
 }
 
-// SKS, Algorithm 1, in correction form: U += A_p^{-1} r, r = F - A U.
+// SKS, Algorithm 1, in correction form: U += A_p^{-1} r (the update is made
+// by the last inverse transform pass), r = F - A U.  The first
+// preconditioner pass of r is enqueued before the host waits for |r|, so the
+// device stays busy during the convergence test.
 h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
   h6_plan P = c.P;
   int nh = 0;
-  double r2 = 0.0;
-  h6_status st = residual(c, F, U, P->r, &r2);
+  h6_status st = residual_async(c, F, U, P->r);
   if (st != H6_OK) return st;
   info->iters = 0;
   while (true) {
-    info->rel_resid = std::sqrt(r2) / normF;
+    const bool more = info->iters < info->maxit;
+    if (more) H6_TRY_HIP(launch_pinv_acc(P, P->r, U, c.s, PINV_FIRST));
+    st = wait(c);
+    if (st != H6_OK) return st;
+    info->rel_resid = std::sqrt(c.host[kNorm]) / normF;
+    if (info->iters > 0) record(info, nh, info->rel_resid);
     if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
     if (!std::isfinite(info->rel_resid) || (info->iters > 0 && info->rel_resid > 1e4)) {
       info->history_len = nh;
       return H6_DIVERGED;
     }
-    if (info->iters >= info->maxit) { info->history_len = nh; return H6_NOT_CONVERGED; }
-    H6_TRY_HIP(launch_pinv(P, P->r, P->t, c.s));
-    hipEvent_t ev;
-    timing_begin(P, KC_AXPY, c.s, &ev);
-    H6_TRY_HIP(launch_add(U, P->t, c.N, c.s));
-    timing_end(P, KC_AXPY, c.s, ev, double(c.N) * sizeof(double2) * 3);
-    st = residual(c, F, U, P->r, &r2);
+    if (!more) { info->history_len = nh; return H6_NOT_CONVERGED; }
+    H6_TRY_HIP(launch_pinv_acc(P, P->r, U, c.s, PINV_REST));
+    st = residual_async(c, F, U, P->r);
     if (st != H6_OK) return st;
     info->iters += 1;
-    record(info, nh, std::sqrt(r2) / normF);
   }
 }
 

@@ -26,12 +26,6 @@ constexpr int kLX = kTX + 2, kLY = kTY + 2;
 constexpr int kThreads = 256;
 constexpr int kLoads = (kLX * kLY + kThreads - 1) / kThreads;   // 3
 
-__device__ __forceinline__ int xcd_remap(int bid, int nwg) {
-  const int xcd = bid & 7, idx = bid >> 3;
-  const int per = nwg >> 3, rem = nwg & 7;
-  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
 struct S3 {
   double2 c, e, k;
 };
@@ -91,21 +85,35 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
     src_off[i] = off;
   }
 
-  auto load_plane = [&](int p, double2 (&v)[kLoads]) {
+  // A plane in flight: raw input values (converted to complex128 only when
+  // written to LDS) and a mask of the valid ones.  The loads are unconditional
+  // (invalid ones read element 0 of the plane and are masked at the LDS
+  // write), so the code is straight-line and waiting for one plane's loads
+  // does not wait for the loads issued after them.
+  struct Plane {
+    Tin v[kLoads];
+    unsigned ok;
+  };
+  // planes outside [z0 - 1, z1] or outside the grid are masked; their loads
+  // re-read the last plane of the chunk (already in cache)
+  const int zlast = min(z1, nz - 1);
+  auto load_plane = [&](int p, Plane& pl) {
+    const bool okp = p >= 0 && p < nz && p <= z1;
+    const Tin* xp = x + size_t(okp ? p : zlast) * plane;
+    pl.ok = 0;
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
-      v[i] = make_double2(0.0, 0.0);
-      if (p >= 0 && p < nz && src_off[i] >= 0) {
-        const Tin t = x[size_t(p) * plane + src_off[i]];
-        v[i] = make_double2(double(t.x), double(t.y));
-      }
+      pl.v[i] = xp[src_off[i] >= 0 ? src_off[i] : 0];
+      if (okp && src_off[i] >= 0) pl.ok |= 1u << i;
     }
   };
-  auto store_plane = [&](int b, const double2 (&v)[kLoads]) {
+  auto store_plane = [&](int b, const Plane& pl) {
 #pragma unroll
     for (int i = 0; i < kLoads; ++i) {
       const int e = tid + i * kThreads;
-      if (e < kLX * kLY) (&tile[b][0][0])[e] = v[i];
+      const bool ok = (pl.ok >> i) & 1u;
+      if (e < kLX * kLY)
+        (&tile[b][0][0])[e] = make_double2(ok ? double(pl.v[i].x) : 0.0, ok ? double(pl.v[i].y) : 0.0);
     }
   };
 
@@ -116,16 +124,19 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
   for (int s = 0; s < 2; ++s) acc_a[s] = acc_b[s] = make_double2(0.0, 0.0);
   double nrm = 0.0;
 
-  double2 v[kLoads];
-  load_plane(z0 - 1, v);
-  store_plane(0, v);
+  // planes stream through two register sets (loads issued two planes ahead)
+  // into the double-buffered LDS tile
+  Plane va, vb;
+  const int nplanes = z1 - z0 + 2;
+  load_plane(z0 - 1, va);
+  store_plane(0, va);
+  load_plane(z0, vb);                     // plane of iteration 1 (nplanes >= 3)
   __syncthreads();
 
-  const int nplanes = z1 - z0 + 2;
-  for (int it = 0; it < nplanes; ++it) {
+  auto step = [&](int it, Plane& cur, Plane& nxt) {
+    // LDS buffer (it & 1) holds plane p; nxt holds plane p + 1; cur is free
     const int p = z0 - 1 + it;
-    const bool more = it + 1 < nplanes;
-    if (more) load_plane(p + 1, v);
+    load_plane(p + 2, cur);   // unconditional (masked past the chunk): straight-line waits
     const int b = it & 1;
     // row types of the three rows this plane feeds (uniform across the block)
     const W9 w_prev = W->w[row_type(p - 1)][2];
@@ -159,8 +170,12 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
       acc_b[s] = make_double2(0.0, 0.0);
       apply_w(acc_b[s], w_next, S);
     }
-    if (more) store_plane(b ^ 1, v);
+    if (it + 1 < nplanes) store_plane(b ^ 1, nxt);
     __syncthreads();
+  };
+  for (int it = 0; it < nplanes; it += 2) {
+    step(it, va, vb);
+    if (it + 1 < nplanes) step(it + 1, vb, va);
   }
 
   if (RESID) {

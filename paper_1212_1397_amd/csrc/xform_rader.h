@@ -15,13 +15,18 @@ struct RaderTables {
   const double* cos_a;     // cos(pi g^{-a} / M), a = 0..M-2
   const int* slot_d;       // LDS slot of array index p of a sine-basis line (node q = p + 1)
   const int* slot_n;       // LDS slot of array index p of a cosine-basis line (node q = p)
+  const float2* kf_f;      // kf, tw256, sin_a, cos_a rounded to single precision (complex64 path)
+  const float2* tw_f;
+  const float* sin_f;
+  const float* cos_f;
 };
 
 constexpr int kRaderM = 257;
 
+// accumulate != 0 (inverse transforms with a complex128 output only): out += result
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s);
+                          const RaderTables& tab, hipStream_t s, int accumulate = 0);
 template <typename R, typename T>
 hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
                           const RaderTables& tab, hipStream_t s);

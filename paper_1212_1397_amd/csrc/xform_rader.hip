@@ -126,10 +126,33 @@ constexpr int kHalf = 128;         // (M - 1) / 2
 // gather of (x_q, x_{M-q}) pairs reads consecutive slots; the 16 x 16
 // transposes use a row stride of 17; Y is scattered to natural order and the
 // outputs are written back in natural order for a coalesced store.
+// table entries in the compute precision
+template <typename R>
+__device__ __forceinline__ typename V2<R>::T tab_tw(const RaderTables& tab, int i) {
+  if constexpr (sizeof(R) == 4) return tab.tw_f[i];
+  else return tab.tw256[i];
+}
+template <typename R>
+__device__ __forceinline__ typename V2<R>::T tab_kf(const RaderTables& tab, int i) {
+  if constexpr (sizeof(R) == 4) return tab.kf_f[i];
+  else return tab.kf[i];
+}
+template <typename R>
+__device__ __forceinline__ R tab_sin(const RaderTables& tab, int i) {
+  if constexpr (sizeof(R) == 4) return tab.sin_f[i];
+  else return tab.sin_a[i];
+}
+template <typename R>
+__device__ __forceinline__ R tab_cos(const RaderTables& tab, int i) {
+  if constexpr (sizeof(R) == 4) return tab.cos_f[i];
+  else return tab.cos_a[i];
+}
+
 template <typename R, int AXIS, bool NEU, bool INV, typename Tin, typename Tout>
 __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __restrict__ in,
                                                                Tout* __restrict__ out, int nlines,
-                                                               int nx, int L, RaderTables tab) {
+                                                               int nx, int L, RaderTables tab,
+                                                               int acc) {
   __shared__ T2 buf[kLines][kStride];
   constexpr int M = 257;
   const int tid = threadIdx.x;
@@ -139,10 +162,23 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   // thread are issued before any LDS write (coalesced, many loads in flight) ----
   int nl;
   size_t gbase;
-  const int line0 = blockIdx.x * kLines;
+  // along y, a workgroup's columns share 128-byte lines with its neighbours':
+  // neighbouring column groups are kept on one XCD
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (AXIS == 1) {
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    bx = lid % gridDim.x;
+    by = lid / gridDim.x;
+  }
+  const int line0 = bx * kLines;
   if (AXIS == 0) {
     nl = min(kLines, nlines - line0);
     gbase = size_t(line0) * L;
+    // LDS slots first, unconditionally (clamped), so that no slot lookup is
+    // waited on between the data loads and their LDS writes
+    int sl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sl[k] = slot[min(tid + k * kLines * 16, L - 1)];
     T2 r[kLines][3];
 #pragma unroll
     for (int b = 0; b < kLines; ++b)
@@ -156,12 +192,15 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int p = tid + k * kLines * 16;
-        if (b < nl && p < L) buf[b][slot[p]] = r[b][k];
+        if (b < nl && p < L) buf[b][sl[k]] = r[b][k];
       }
   } else {
     nl = min(kLines, nx - line0);                   // x columns i0 .. i0 + nl - 1
-    gbase = size_t(blockIdx.y) * nx * L + line0;
+    gbase = size_t(by) * nx * L + line0;
     constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
+    int sl[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) sl[k] = slot[min((tid + k * kLines * 16) / kLines, L - 1)];
     T2 r[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -173,7 +212,7 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
     for (int k = 0; k < kPer; ++k) {
       const int e = tid + k * kLines * 16;
       const int q = e / kLines, b = e - q * kLines;
-      if (q < L && b < nl) buf[b][slot[q]] = r[k];
+      if (q < L && b < nl) buf[b][sl[k]] = r[k];
     }
   }
   __syncthreads();
@@ -195,11 +234,11 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
     const int a = t + 16 * n2;
     const T2 xq = buf[g][a], xr = buf[g][(a + 128) & 255];
     const T2 s = add<R>(xq, xr), d = sub<R>(xq, xr);
-    const R sn = R(tab.sin_a[a]);
+    const R sn = tab_sin<R>(tab, a);
     T2 y;
     if (NEU) {
       y = add<R>(s, scl<R>(d, sn));
-      c1sum = add<R>(c1sum, scl<R>(d, R(0.5) * R(tab.cos_a[a])));
+      c1sum = add<R>(c1sum, scl<R>(d, R(0.5) * tab_cos<R>(tab, a)));
     } else {
       y = add<R>(scl<R>(s, sn), d);
     }
@@ -221,7 +260,7 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   fft16<R, false>(v);                      // over n2 -> v[k2]
 #pragma unroll
   for (int k2 = 0; k2 < 16; ++k2) {
-    const T2 w = cv<T2>(tab.tw256[(t * k2) & 255]);
+    const T2 w = tab_tw<R>(tab, (t * k2) & 255);
     buf[g][17 * t + k2] = mul<R>(v[k2], w);
   }
   __syncthreads();
@@ -231,12 +270,12 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   // pointwise product with the kernel spectrum (1/256 folded in), then
   // inverse FFT_256 back to the natural index
 #pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) v[k1] = mul<R>(v[k1], cv<T2>(tab.kf[16 * k1 + t]));
+  for (int k1 = 0; k1 < 16; ++k1) v[k1] = mul<R>(v[k1], tab_kf<R>(tab, 16 * k1 + t));
   fft16<R, true>(v);                       // over k1 -> Z[n1][k2] in v[n1]
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) {
-    const double2 w = tab.tw256[(n1 * t) & 255];
-    buf[g][17 * n1 + t] = mul<R>(v[n1], mk2<R>(R(w.x), -R(w.y)));
+    const T2 w = tab_tw<R>(tab, (n1 * t) & 255);
+    buf[g][17 * n1 + t] = mul<R>(v[n1], mk2<R>(w.x, -w.y));
   }
   __syncthreads();
 #pragma unroll
@@ -300,15 +339,39 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
     }
   }
   __syncthreads();
-  // ---- store (coalesced) ----
+  // ---- store (coalesced); with acc, out += result (all reads issued first) ----
   if (AXIS == 0) {
+    if (acc) {
+      Tout o[kLines][3];
 #pragma unroll
-    for (int b = 0; b < kLines; ++b)
+      for (int b = 0; b < kLines; ++b)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int p = tid + k * kLines * 16;
-        if (b < nl && p < L) out[gbase + size_t(b) * L + p] = cv<Tout>(buf[b][p]);
-      }
+        for (int k = 0; k < 3; ++k) {
+          const int p = tid + k * kLines * 16;
+          if (b < nl && p < L) o[b][k] = out[gbase + size_t(b) * L + p];
+        }
+#pragma unroll
+      for (int b = 0; b < kLines; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int p = tid + k * kLines * 16;
+          if (b < nl && p < L) {
+            const Tout v = cv<Tout>(buf[b][p]);
+            Tout u;
+            u.x = o[b][k].x + v.x;
+            u.y = o[b][k].y + v.y;
+            out[gbase + size_t(b) * L + p] = u;
+          }
+        }
+    } else {
+#pragma unroll
+      for (int b = 0; b < kLines; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int p = tid + k * kLines * 16;
+          if (b < nl && p < L) out[gbase + size_t(b) * L + p] = cv<Tout>(buf[b][p]);
+        }
+    }
   } else {
     constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
 #pragma unroll
@@ -324,25 +387,25 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
 
 template <typename R, int AXIS, bool NEU, typename Tin, typename Tout>
 void launch_one(bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
-                const RaderTables& tab, hipStream_t s) {
+                const RaderTables& tab, hipStream_t s, int acc = 0) {
   const dim3 grid = AXIS == 0 ? dim3((nlines + kLines - 1) / kLines) : dim3((nx + kLines - 1) / kLines, nz);
   if (inv)
     hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, true, Tin, Tout>), grid, dim3(kLines * 16), 0,
-                       s, in, out, nlines, nx, L, tab);
+                       s, in, out, nlines, nx, L, tab, acc);
   else
     hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, false, Tin, Tout>), grid, dim3(kLines * 16), 0,
-                       s, in, out, nlines, nx, L, tab);
+                       s, in, out, nlines, nx, L, tab, 0);
 }
 
 }  // namespace
 
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s) {
+                          const RaderTables& tab, hipStream_t s, int accumulate) {
   if (neumann)
-    launch_one<R, 0, true>(inverse, in, out, nlines, 0, L, 0, tab, s);
+    launch_one<R, 0, true>(inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
   else
-    launch_one<R, 0, false>(inverse, in, out, nlines, 0, L, 0, tab, s);
+    launch_one<R, 0, false>(inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
   return hipGetLastError();
 }
 
@@ -357,13 +420,13 @@ hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int n
 }
 
 template hipError_t launch_rader_x<double, double2, double2>(bool, bool, const double2*, double2*,
-                                                             int, int, const RaderTables&, hipStream_t);
+                                                             int, int, const RaderTables&, hipStream_t, int);
 template hipError_t launch_rader_x<float, double2, float2>(bool, bool, const double2*, float2*, int,
-                                                           int, const RaderTables&, hipStream_t);
+                                                           int, const RaderTables&, hipStream_t, int);
 template hipError_t launch_rader_x<float, float2, double2>(bool, bool, const float2*, double2*, int,
-                                                           int, const RaderTables&, hipStream_t);
+                                                           int, const RaderTables&, hipStream_t, int);
 template hipError_t launch_rader_x<float, float2, float2>(bool, bool, const float2*, float2*, int,
-                                                          int, const RaderTables&, hipStream_t);
+                                                          int, const RaderTables&, hipStream_t, int);
 template hipError_t launch_rader_y<double, double2>(bool, bool, const double2*, double2*, int, int,
                                                     int, const RaderTables&, hipStream_t);
 template hipError_t launch_rader_y<float, float2>(bool, bool, const float2*, float2*, int, int, int,
