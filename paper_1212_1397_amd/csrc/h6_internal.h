@@ -137,11 +137,18 @@ hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, i
 // U += A_p^{-1} r (the update folded into the last inverse transform)
 hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s,
                            int part = PINV_ALL);
+// mixed plans only: U += A_p^{-1} r for a complex64 r
+hipError_t launch_pinv_acc_f32in(h6_plan P, const float2* r, double2* U, hipStream_t s,
+                                 int part = PINV_ALL);
 // mixed plans only: z = A_p^{-1} r stored in complex64
 hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s,
                               int part = PINV_ALL);
 // y = A x for a complex64 x (FP64 arithmetic)
 hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s);
+// r = F - A U stored in complex64 (FP64 arithmetic and |r|^2 partials), for
+// callers that only hand r to a complex64 preconditioner
+hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
+                               double* partials, int* nparts, hipStream_t s);
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
 

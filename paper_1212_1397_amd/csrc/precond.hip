@@ -298,8 +298,8 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 }
 
 // z = A_p^{-1} r, or z += A_p^{-1} r with acc != 0 (folded into the last pass)
-template <typename R, typename Tout>
-hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s, int part, int acc = 0) {
+template <typename R, typename Tin, typename Tout>
+hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, int acc = 0) {
   using T2 = typename C2<R>::T;
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   T2* w0 = static_cast<T2*>(P->w_pc[0]);
@@ -360,18 +360,23 @@ hipError_t pinv_impl(h6_plan P, const double2* r, Tout* z, hipStream_t s, int pa
 }  // namespace
 
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part) {
-  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, z, s, part);
-  return pinv_impl<double, double2>(P, r, z, s, part);
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, z, s, part);
+  return pinv_impl<double, double2, double2>(P, r, z, s, part);
 }
 
 hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s, int part) {
-  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2>(P, r, U, s, part, 1);
-  return pinv_impl<double, double2>(P, r, U, s, part, 1);
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, U, s, part, 1);
+  return pinv_impl<double, double2, double2>(P, r, U, s, part, 1);
+}
+
+hipError_t launch_pinv_acc_f32in(h6_plan P, const float2* r, double2* U, hipStream_t s, int part) {
+  if (P->p.precision != H6_MIXED) return hipErrorInvalidValue;
+  return pinv_impl<float, float2, double2>(P, r, U, s, part, 1);
 }
 
 hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_t s, int part) {
   if (P->p.precision != H6_MIXED) return hipErrorInvalidValue;
-  return pinv_impl<float, float2>(P, r, z, s, part);
+  return pinv_impl<float, double2, float2>(P, r, z, s, part);
 }
 
 }  // namespace h6

@@ -272,16 +272,30 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
 // SKS, Algorithm 1, in correction form: U += A_p^{-1} r (the update is made
 // by the last inverse transform pass), r = F - A U.  The first
 // preconditioner pass of r is enqueued before the host waits for |r|, so the
-// device stays busy during the convergence test.
+// device stays busy during the convergence test.  In mixed plans r is stored
+// in complex64 by the residual kernel (its norm is taken in FP64 first): the
+// preconditioner's first pass would round it to complex64 on load anyway.
 h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
   h6_plan P = c.P;
+  const bool mixed = P->p.precision == H6_MIXED;
+  float2* r32 = reinterpret_cast<float2*>(P->r);
+  auto resid = [&]() -> h6_status {
+    if (!mixed) return residual_async(c, F, U, P->r);
+    int nparts = 0;
+    H6_TRY_HIP(launch_resid_f32out(P, U, r32, F, P->partials, &nparts, c.s));
+    H6_TRY_HIP(launch_reduce_sum(P->partials, nparts, c.dev + kNorm, c.s));
+    return fetch_async(c, kNorm, 1);
+  };
+  auto pinv = [&](int part) -> hipError_t {
+    return mixed ? launch_pinv_acc_f32in(P, r32, U, c.s, part) : launch_pinv_acc(P, P->r, U, c.s, part);
+  };
   int nh = 0;
-  h6_status st = residual_async(c, F, U, P->r);
+  h6_status st = resid();
   if (st != H6_OK) return st;
   info->iters = 0;
   while (true) {
     const bool more = info->iters < info->maxit;
-    if (more) H6_TRY_HIP(launch_pinv_acc(P, P->r, U, c.s, PINV_FIRST));
+    if (more) H6_TRY_HIP(pinv(PINV_FIRST));
     st = wait(c);
     if (st != H6_OK) return st;
     info->rel_resid = std::sqrt(c.host[kNorm]) / normF;
@@ -292,8 +306,8 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
       return H6_DIVERGED;
     }
     if (!more) { info->history_len = nh; return H6_NOT_CONVERGED; }
-    H6_TRY_HIP(launch_pinv_acc(P, P->r, U, c.s, PINV_REST));
-    st = residual_async(c, F, U, P->r);
+    H6_TRY_HIP(pinv(PINV_REST));
+    st = resid();
     if (st != H6_OK) return st;
     info->iters += 1;
   }

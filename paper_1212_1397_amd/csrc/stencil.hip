@@ -45,9 +45,9 @@ __device__ __forceinline__ void apply_w(double2& acc, const W9& w, const S3& s) 
 
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-template <bool RESID, typename Tin>
+template <bool RESID, typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void stencil_kernel(
-    const Tin* __restrict__ x, double2* __restrict__ y, const double2* __restrict__ F,
+    const Tin* __restrict__ x, Tout* __restrict__ y, const double2* __restrict__ F,
     double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
     int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg) {
   __shared__ double2 tile[2][kLY][kLX];
@@ -162,7 +162,10 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
             out = make_double2(f.x - out.x, f.y - out.y);
             nrm = fma(out.x, out.x, fma(out.y, out.y, nrm));
           }
-          y[o] = out;
+          Tout yo;
+          yo.x = out.x;           // complex64 output: rounded after the FP64 norm
+          yo.y = out.y;
+          y[o] = yo;
         }
       }
       acc_a[s] = acc_b[s];
@@ -192,8 +195,8 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 
 }  // namespace
 
-template <typename Tin>
-hipError_t stencil_impl(h6_plan P, const Tin* x, double2* y, const double2* F, double* partials,
+template <typename Tin, typename Tout>
+hipError_t stencil_impl(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
                         int* nparts, hipStream_t s) {
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
@@ -203,15 +206,15 @@ hipError_t stencil_impl(h6_plan P, const Tin* x, double2* y, const double2* F, d
   hipEvent_t ev;
   timing_begin(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, &ev);
   if (resid)
-    hipLaunchKernelGGL((stencil_kernel<true, Tin>), dim3(nwg), dim3(kThreads), 0, s, x, y, F, partials,
-                       P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
+    hipLaunchKernelGGL((stencil_kernel<true, Tin, Tout>), dim3(nwg), dim3(kThreads), 0, s, x, y, F,
+                       partials, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
                        P->zhi_closure, ntx, nty, nwg);
   else
-    hipLaunchKernelGGL((stencil_kernel<false, Tin>), dim3(nwg), dim3(kThreads), 0, s, x, y, nullptr,
-                       nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
+    hipLaunchKernelGGL((stencil_kernel<false, Tin, Tout>), dim3(nwg), dim3(kThreads), 0, s, x, y,
+                       nullptr, nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
                        P->zlo_closure, P->zhi_closure, ntx, nty, nwg);
   timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev,
-             double(P->N) * (sizeof(Tin) + sizeof(double2) * (resid ? 2 : 1)));
+             double(P->N) * (sizeof(Tin) + sizeof(Tout) + (resid ? sizeof(double2) : 0)));
   if (nparts) *nparts = nwg;
   return hipGetLastError();
 }
@@ -223,6 +226,11 @@ hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2
 
 hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s) {
   return stencil_impl(P, x, y, static_cast<const double2*>(nullptr), nullptr, nullptr, s);
+}
+
+hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
+                               double* partials, int* nparts, hipStream_t s) {
+  return stencil_impl(P, U, r, F, partials, nparts, s);
 }
 
 }  // namespace h6

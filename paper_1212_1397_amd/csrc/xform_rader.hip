@@ -288,43 +288,50 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   if (t == 0) buf[g][0] = y0sum;
   __syncthreads();
 
-  // ---- post-processing: j = t + 16 u (u = 0..8, j <= 128), running sums of
-  // the odd-output increments by a 16-lane scan per round ----
+  // ---- post-processing: thread t takes j = 9t .. 9t+8 (j <= 128).  The odd
+  // outputs need running sums of the increments over j: a serial prefix over
+  // the thread's own nine values plus one 16-lane scan of the thread totals ----
   T2 ev[9], od[9];
-  T2 carry = mk2<R>(0, 0);
+  T2 loc = mk2<R>(0, 0);
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
-    const int j = t + 16 * u;
+    const int j = 9 * t + u;
     const bool ok = j <= kHalf;
     const int jj = ok ? j : 0;
     const T2 Yj = buf[g][jj], Ym = buf[g][jj == 0 ? 0 : M - jj];
     T2 inc = mk2<R>(0, 0);
     if (ok && j >= 1) inc = NEU ? scl<R>(sub<R>(Yj, Ym), R(0.5)) : scl<R>(add<R>(Yj, Ym), R(0.5));
-    T2 sc = inc;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      const R px = __shfl_up(sc.x, o, 16), py = __shfl_up(sc.y, o, 16);
-      if (t >= o) { sc.x += px; sc.y += py; }
-    }
-    const T2 run = add<R>(carry, sc);     // sum over 1 <= i <= j
-    carry.x += __shfl(sc.x, 15, 16);
-    carry.y += __shfl(sc.y, 15, 16);
+    loc = add<R>(loc, inc);
+    od[u] = loc;                          // running sum within the thread (inclusive)
     if (NEU) {
       const T2 A = (j == 0) ? Yj : scl<R>(add<R>(Yj, Ym), R(0.5));
       ev[u] = add<R>(add<R>(xa, xb), scl<R>(A, R(0.5)));                      // C_{2j}
-      od[u] = add<R>(sub<R>(xa, xb), add<R>(c1sum, mk2<R>(run.y, -run.x)));  // C_{2j+1}
     } else {
       const T2 D = sub<R>(Yj, Ym);
       ev[u] = mk2<R>(-R(0.25) * D.y, R(0.25) * D.x);                          // S_{2j}
-      od[u] = add<R>(scl<R>(y0sum, R(0.5)), run);                              // S_{2j+1}
     }
+  }
+  T2 sc = loc;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const R px = __shfl_up(sc.x, o, 16), py = __shfl_up(sc.y, o, 16);
+    if (t >= o) { sc.x += px; sc.y += py; }
+  }
+  const T2 off = sub<R>(sc, loc);        // sum over the lanes before t
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const T2 run = add<R>(off, od[u]);   // sum over 1 <= i <= j
+    if (NEU)
+      od[u] = add<R>(sub<R>(xa, xb), add<R>(c1sum, mk2<R>(run.y, -run.x)));  // C_{2j+1}
+    else
+      od[u] = add<R>(scl<R>(y0sum, R(0.5)), run);                             // S_{2j+1}
   }
   __syncthreads();
   // scaled outputs into LDS in natural order
   const R fs = INV ? R(1) : R(2) / R(M);
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
-    const int j = t + 16 * u;
+    const int j = 9 * t + u;
     if (j > kHalf) continue;
     if (NEU) {
       const int me = 2 * j, mo = 2 * j + 1;              // m = 0..M
