@@ -1,0 +1,216 @@
+"""Correction network of the learned preconditioner, in FP64.
+
+TEST INFRASTRUCTURE ONLY: part of the FP64 CPU oracle.  Parity target for
+the GPU network (forward pass, and the weight and input gradients of its
+training step).
+
+The network is not in the paper; it is the learned correction to the
+preconditioner A_p^{-1} of eq. (3DAP) (Section 3.3) used inside flexible
+GMRES.  Definition (the one the GPU path implements):
+
+* Arrays are channels-first, (C, n'z, n'y, n'x), like the oracle's unknown
+  vectors with a leading channel axis.
+* conv(x; W, b): zero-padded 3x3x3 cross-correlation,
+    out[o, p] = b[o] + sum_{c, t} W[o, c, t] x[c, p + t],  t in {-1,0,1}^3,
+  with W of shape (Cout, Cin, 3, 3, 3) indexed (dz, dy, dx).
+* pool: 2x2x2 average, output extent ceil(n/2) per axis; entries past the
+  input's end count as zero (the divisor is always 8).
+* up: nearest-neighbour upsampling to a given extent, out[p] = in[p // 2].
+* Three levels, channels 16 / 32 / 64; ReLU after every convolution but the
+  last; skip connections by channel concatenation ([upsampled, skip]):
+      s1 = R(e1b(R(e1a(x))))                 3 -> 16 -> 16
+      s2 = R(e2b(R(e2a(pool s1))))          16 -> 32 -> 32
+      b3 = R(b3b(R(b3a(pool s2))))          32 -> 64 -> 64
+      d2 = R(d2b(R(d2a([up b3, s2]))))      96 -> 32 -> 32
+      d1 = R(d1b(R(d1a([up d2, s1]))))      48 -> 16 -> 16
+      y  = out(d1)                          16 -> 2
+* Features of a residual r: s = sqrt(mean |r|^2); x = [Re r / s, Im r / s,
+  Re(k) h]; the correction is c = s (y_0 + i y_1).  (The scaling makes the
+  map r -> c positively homogeneous of degree one.)
+* Loss of a training pair (r, target t): L = sum |c - t|^2 / sum |t|^2.
+
+Gradients are written out by hand (the adjoint of each step in reverse
+order); the tests pin them to central finite differences.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# (name, Cin, Cout, relu)
+LAYERS = [
+    ("e1a", 3, 16, True), ("e1b", 16, 16, True),
+    ("e2a", 16, 32, True), ("e2b", 32, 32, True),
+    ("b3a", 32, 64, True), ("b3b", 64, 64, True),
+    ("d2a", 96, 32, True), ("d2b", 32, 32, True),
+    ("d1a", 48, 16, True), ("d1b", 16, 16, True),
+    ("out", 16, 2, False),
+]
+
+
+def _taps():
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                yield dz, dy, dx
+
+
+def conv(x, W, b):
+    """Zero-padded 3x3x3 cross-correlation with bias."""
+    C, Z, Y, X = x.shape
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    out = np.empty((W.shape[0], Z, Y, X))
+    out[...] = b[:, None, None, None]
+    for dz, dy, dx in _taps():
+        out += np.einsum("oc,czyx->ozyx", W[:, :, dz, dy, dx], xp[:, dz:dz + Z, dy:dy + Y, dx:dx + X])
+    return out
+
+
+def conv_backward(x, W, dout):
+    """Gradients of conv: (dx, dW, db) for the upstream gradient dout."""
+    C, Z, Y, X = x.shape
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    dxp = np.zeros_like(xp)
+    dW = np.empty_like(W)
+    for dz, dy, dx in _taps():
+        sl = (slice(None), slice(dz, dz + Z), slice(dy, dy + Y), slice(dx, dx + X))
+        dW[:, :, dz, dy, dx] = np.einsum("ozyx,czyx->oc", dout, xp[sl])
+        dxp[sl] += np.einsum("oc,ozyx->czyx", W[:, :, dz, dy, dx], dout)
+    return dxp[:, 1:-1, 1:-1, 1:-1], dW, dout.sum(axis=(1, 2, 3))
+
+
+def pooled_shape(shape):
+    return tuple((n + 1) // 2 for n in shape)
+
+
+def pool(x):
+    C, Z, Y, X = x.shape
+    Zo, Yo, Xo = pooled_shape((Z, Y, X))
+    xp = np.zeros((C, 2 * Zo, 2 * Yo, 2 * Xo))
+    xp[:, :Z, :Y, :X] = x
+    return xp.reshape(C, Zo, 2, Yo, 2, Xo, 2).sum(axis=(2, 4, 6)) / 8.0
+
+
+def pool_backward(dout, shape):
+    C = dout.shape[0]
+    Z, Y, X = shape
+    d = np.repeat(np.repeat(np.repeat(dout, 2, axis=1), 2, axis=2), 2, axis=3) / 8.0
+    return d[:, :Z, :Y, :X].copy()
+
+
+def up(x, shape):
+    Z, Y, X = shape
+    return x[:, np.arange(Z) // 2][:, :, np.arange(Y) // 2][:, :, :, np.arange(X) // 2]
+
+
+def up_backward(dout, shape):
+    C, Z, Y, X = dout.shape
+    Zi, Yi, Xi = shape
+    d = np.zeros((C, 2 * Zi, 2 * Yi, 2 * Xi))
+    d[:, :Z, :Y, :X] = dout
+    return d.reshape(C, Zi, 2, Yi, 2, Xi, 2).sum(axis=(2, 4, 6))
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def features(r, k, h):
+    """Network input of a complex residual r (n'z, n'y, n'x) and its scale s."""
+    s = float(np.sqrt(np.mean(np.abs(r) ** 2)))
+    x = np.empty((3,) + r.shape)
+    x[0] = r.real / s
+    x[1] = r.imag / s
+    x[2] = complex(k).real * h
+    return x, s
+
+
+def forward(params, x):
+    """Network output y (2, ...) and the saved activations for backward."""
+    cache = {"x": x}
+
+    def layer(name, inp):
+        W, b = params[name]
+        z = conv(inp, W, b)
+        cache[name] = (inp, z)
+        return z
+
+    n1 = x.shape[1:]
+    n2 = pooled_shape(n1)
+    a = relu(layer("e1a", x))
+    s1 = relu(layer("e1b", a))
+    a = relu(layer("e2a", pool(s1)))
+    s2 = relu(layer("e2b", a))
+    a = relu(layer("b3a", pool(s2)))
+    b3 = relu(layer("b3b", a))
+    a = relu(layer("d2a", np.concatenate([up(b3, n2), s2])))
+    d2 = relu(layer("d2b", a))
+    a = relu(layer("d1a", np.concatenate([up(d2, n1), s1])))
+    d1 = relu(layer("d1b", a))
+    y = layer("out", d1)
+    cache["shapes"] = (n1, n2, pooled_shape(n2))
+    return y, cache
+
+
+def backward(params, cache, dy):
+    """Parameter gradients {name: (dW, db)} and the input gradient, for dL/dy."""
+    grads = {}
+    n1, n2, n3 = cache["shapes"]
+
+    def back(name, dz):
+        inp, z = cache[name]
+        if dict((l[0], l[3]) for l in LAYERS)[name]:
+            dz = dz * (z > 0.0)
+        dinp, dW, db = conv_backward(inp, params[name][0], dz)
+        grads[name] = (dW, db)
+        return dinp
+
+    d = back("out", dy)
+    d = back("d1b", d)
+    d = back("d1a", d)                    # 48 channels: [up d2 (32), s1 (16)]
+    ds1 = d[32:]
+    d = back("d2b", up_backward(d[:32], n2))
+    d = back("d2a", d)                    # 96 channels: [up b3 (64), s2 (32)]
+    ds2 = d[64:]
+    d = back("b3b", up_backward(d[:64], n3))
+    d = back("b3a", d)
+    d = back("e2b", ds2 + pool_backward(d, n2))
+    d = back("e2a", d)
+    d = back("e1b", ds1 + pool_backward(d, n1))
+    dx = back("e1a", d)
+    return grads, dx
+
+
+def correction(params, r, k, h):
+    """c = s (y_0 + i y_1) for the residual r."""
+    x, s = features(r, k, h)
+    y, _ = forward(params, x)
+    return s * (y[0] + 1j * y[1])
+
+
+def loss_and_grads(params, r, k, h, target):
+    """Relative squared error of the correction and its parameter gradients."""
+    x, s = features(r, k, h)
+    y, cache = forward(params, x)
+    c = s * (y[0] + 1j * y[1])
+    den = float(np.sum(np.abs(target) ** 2))
+    diff = c - target
+    L = float(np.sum(np.abs(diff) ** 2)) / den
+    dy = np.stack([2.0 * s * diff.real, 2.0 * s * diff.imag]) / den
+    grads, _ = backward(params, cache, dy)
+    return L, grads
+
+
+def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba) of every weight and bias, in place."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for name, (dW, db) in grads.items():
+        for idx, g in ((0, dW), (1, db)):
+            key = (name, idx)
+            m, v = state.get(key, (np.zeros_like(g), np.zeros_like(g)))
+            m = beta1 * m + (1 - beta1) * g
+            v = beta2 * v + (1 - beta2) * g * g
+            state[key] = (m, v)
+            mhat = m / (1 - beta1 ** t)
+            vhat = v / (1 - beta2 ** t)
+            params[name][idx][...] -= lr * mhat / (np.sqrt(vhat) + eps)

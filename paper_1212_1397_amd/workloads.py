@@ -72,3 +72,18 @@ def random_sources(nsrc: int, seed: int, h: float, lo: float = 0.25, hi: float =
     centres = rng.uniform(lo, hi, size=(nsrc, 3))
     amps = rng.standard_normal(nsrc) + 1j * rng.standard_normal(nsrc)
     return centres, amps, 4.0 * h
+
+
+def init_net_params(layers, seed: int):
+    """He-normal initial weights of the correction network: for each
+    (name, Cin, Cout) in `layers`, W ~ N(0, 2 / (27 Cin)) of shape
+    (Cout, Cin, 3, 3, 3) and b = 0; the last layer's weights are scaled by
+    1e-2 so that the initial correction is small.  Returns {name: (W, b)}."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for i, (name, cin, cout) in enumerate(layers):
+        W = rng.standard_normal((cout, cin, 3, 3, 3)) * np.sqrt(2.0 / (27 * cin))
+        if i == len(layers) - 1:
+            W *= 1e-2
+        out[name] = (W, np.zeros(cout))
+    return out
