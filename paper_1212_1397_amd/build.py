@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libhelmholtz6.so")
 ARCH = os.environ.get("H6_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "solve.cpp", "stencil.hip", "precond.hip", "xform_rader.hip", "krylov.hip",
-           "rhs.hip"]
+           "rhs.hip", "unet.hip"]
 
 # Packed FP32 instructions are disabled for every device pass.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

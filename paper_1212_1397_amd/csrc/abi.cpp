@@ -7,6 +7,7 @@
 #include <new>
 
 #include "h6_internal.h"
+#include "h6net.h"
 
 namespace h6 {
 
@@ -542,6 +543,22 @@ const char* helmholtz6_status_string(h6_status s) {
     case H6_ERR_SINGULAR: return "preconditioner singular (k^2 on the 7-point spectrum)";
   }
   return "unknown status";
+}
+
+h6_status helmholtz6_attach_net(h6_plan P, h6_net net) {
+  if (!P) return H6_ERR_ARG;
+  if (net && !net_matches(net, P->dims)) {
+    P->last_error = "network grid does not match the plan's dims";
+    return H6_ERR_ARG;
+  }
+  P->net = net;
+  return H6_OK;
+}
+
+h6_status helmholtz6_learned_steps(h6_plan P, int* steps) {
+  if (!P || !steps) return H6_ERR_ARG;
+  *steps = P->learned_steps;
+  return H6_OK;
 }
 
 const char* helmholtz6_last_error(h6_plan P) {

@@ -101,6 +101,8 @@ struct h6_plan_s {
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
   double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
+  struct h6_net_s* net = nullptr;              // learned correction for FGMRES (not owned)
+  int learned_steps = 0;                       // steps of the last solve that used it
 
   h6::Timing timing;
   std::string last_error;
@@ -170,6 +172,13 @@ hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, in
 hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
                            double* nu, double2* G, int gdim, double2* hcol, double2* coef,
                            hipStream_t s);
+// out = |a - b|^2 (device double)
+hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
+                             hipStream_t s);
+// learned correction (unet.hip): z += c(q), z complex64 when z_f32
+hipError_t net_apply_add(struct h6_net_s* net, const double2* q, double kh, void* z, bool z_f32,
+                         hipStream_t s);
+bool net_matches(struct h6_net_s* net, const int dims[3]);
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
                              int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
 hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y, int m, size_t n,

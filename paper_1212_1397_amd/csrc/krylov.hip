@@ -58,6 +58,19 @@ __global__ __launch_bounds__(kThreads) void norm2_kernel(const double2* __restri
   block_store<1>(v, partials, 0, gridDim.x);
 }
 
+// |a - b|^2 partials (component 0)
+__global__ __launch_bounds__(kThreads) void diff_norm2_kernel(const double2* __restrict__ a,
+                                                              const double2* __restrict__ b, size_t n,
+                                                              double* __restrict__ partials) {
+  double v[1] = {0.0};
+  for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+    const double2 x = a[i], y = b[i];
+    const double dx = x.x - y.x, dy = x.y - y.y;
+    v[0] = fma(dx, dx, fma(dy, dy, v[0]));
+  }
+  block_store<1>(v, partials, 0, gridDim.x);
+}
+
 // For basis vectors q_{i0 .. i0+CNT-1} (stride n from Q): partials of
 // <q_i, w> (components 2 i, 2 i + 1 = re, im).  CNT is a compile-time count so
 // that all CNT + 1 loads of an element are issued back to back, unconditionally.
@@ -251,6 +264,13 @@ hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const 
 
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s) {
   hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, n, partials);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(diff_norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, b, n, partials);
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
   return hipGetLastError();
 }

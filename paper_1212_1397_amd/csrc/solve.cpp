@@ -36,6 +36,7 @@ constexpr int kY = 2000;        // 2 m doubles: least-squares coefficients (doub
 constexpr int kGram2 = 3000;    // Gram entries beyond kGramMax (2 m doubles)
 constexpr int kNu = 3600;       // m + 1 doubles: basis norms nu_i
 constexpr int kHcol = 4000;     // 2 (m + 1) doubles: Hessenberg column of the current step
+constexpr int kJudge = 4600;    // 2 doubles: |q - A z|^2 without / with the learned correction
 
 struct Ctx {
   h6_plan P;
@@ -161,6 +162,8 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   auto Hij = [&](int i, int j) -> cplx& { return H[size_t(i) * m + j]; };
   const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
   double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
+  const double kh = P->k.real() * P->p.h;      // feature of the learned correction
+  P->learned_steps = 0;
   // preconditioner passes of step j (z_j = A_p^{-1} q~_j)
   auto pinv = [&](int j, int part) -> hipError_t {
     const double2* qj = P->V + size_t(j) * N;
@@ -180,14 +183,39 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
     g[0] = beta;
     int jdone = 0;
     bool first_done = false;          // first preconditioner pass of step j already enqueued
+    bool use_net = false;             // this cycle applies the learned correction
     for (int j = 0; j < m; ++j) {
       double2* w = P->V + size_t(j + 1) * N;
+      const double2* qj = P->V + size_t(j) * N;
+      void* zj = flex ? (mixed ? static_cast<void*>(static_cast<float2*>(P->Z) + size_t(j) * N)
+                               : static_cast<void*>(static_cast<double2*>(P->Z) + size_t(j) * N))
+                      : static_cast<void*>(P->t);
+      auto apply_A_z = [&](const void* z, double2* out) -> hipError_t {
+        if (mixed) return launch_stencil_f32in(P, static_cast<const float2*>(z), out, c.s);
+        return launch_stencil(P, static_cast<const double2*>(z), out, nullptr, nullptr, nullptr, c.s);
+      };
       H6_TRY_HIP(pinv(j, first_done ? PINV_REST : PINV_ALL));
-      if (mixed)
-        H6_TRY_HIP(launch_stencil_f32in(P, static_cast<float2*>(P->Z) + size_t(j) * N, w, c.s));
-      else
-        H6_TRY_HIP(launch_stencil(P, flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t, w,
-                                  nullptr, nullptr, nullptr, c.s));
+      if (j == 0 && flex && P->net) {
+        // judge of the correction for this cycle: ||q - A z|| with and without it
+        const size_t zb = N * (mixed ? sizeof(float2) : sizeof(double2));
+        H6_TRY_HIP(apply_A_z(zj, w));
+        H6_TRY_HIP(launch_diff_norm2(qj, w, N, P->partials, c.dev + kJudge, c.s));
+        H6_TRY_HIP(hipMemcpyAsync(P->t, zj, zb, hipMemcpyDeviceToDevice, c.s));
+        H6_TRY_HIP(net_apply_add(P->net, qj, kh, P->t, mixed, c.s));
+        H6_TRY_HIP(apply_A_z(P->t, P->r));
+        H6_TRY_HIP(launch_diff_norm2(qj, P->r, N, P->partials, c.dev + kJudge + 1, c.s));
+        st = fetch(c, kJudge, 2);
+        if (st != H6_OK) return st;
+        use_net = c.host[kJudge + 1] <= c.host[kJudge];
+        if (use_net) {
+          H6_TRY_HIP(hipMemcpyAsync(zj, P->t, zb, hipMemcpyDeviceToDevice, c.s));
+          H6_TRY_HIP(hipMemcpyAsync(w, P->r, N * sizeof(double2), hipMemcpyDeviceToDevice, c.s));
+        }
+      } else {
+        if (use_net) H6_TRY_HIP(net_apply_add(P->net, qj, kh, zj, mixed, c.s));
+        H6_TRY_HIP(apply_A_z(zj, w));
+      }
+      if (use_net) P->learned_steps += 1;
       info->iters += 1;
       hipEvent_t ev;
       timing_begin(P, KC_MGS_DOTS, c.s, &ev);

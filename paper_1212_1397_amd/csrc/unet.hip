@@ -1,0 +1,716 @@
+// Learned correction network (see include/h6net.h for the definition):
+// BF16 activations and weights, FP32 accumulation on the matrix cores.
+//
+// Convolutions are implicit GEMMs with v_mfma_f32_16x16x16bf16_1k:
+//   forward / input gradient: rows = 16 voxels (flattened x-fastest index),
+//     columns = output channels, k = (tap, input channel);
+//   weight gradient: rows = output channels, columns = input channels,
+//     k = voxels, one tap per workgroup, deterministic two-stage reduction.
+// Operand lane layout of the instruction (lane l, element e = 0..3):
+//   A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16], D[4 (l / 16) + e][l % 16].
+// Activations are channels-last: element (v, c) of a view at p[v * cs + coff + c],
+// so the skip concatenations are two producers writing channel ranges of one
+// buffer.  The input-gradient convolution is the forward kernel with the
+// taps mirrored and the channel roles swapped (a repacked weight copy).
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "h6_internal.h"
+#include "h6net.h"
+
+namespace h6 {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;
+
+__device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float(unsigned(v) << 16); }
+__device__ __forceinline__ bf16 f2bf(float f) {      // round to nearest even (finite inputs)
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16(u >> 16);
+}
+
+struct Grid3 {
+  int X, Y, Z;
+  __host__ __device__ long long P() const { return (long long)X * Y * Z; }
+};
+Grid3 half(Grid3 g) { return Grid3{(g.X + 1) / 2, (g.Y + 1) / 2, (g.Z + 1) / 2}; }
+
+struct View {           // channels-last BF16 view
+  bf16* p;
+  int cs, coff;
+};
+
+constexpr int kConvWaves = 4;
+
+// out[v][co] = act(b[co] + sum_{tap, ci} W[tap][co][ci] in[v + tap][ci]), CIN and
+// COUTP multiples of 16; writes co < cout (BF16 view, or FP32 [v][2] when f32out).
+template <int CIN, int COUTP>
+__global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(View in, const bf16* __restrict__ W,
+                                                               const float* __restrict__ bias, View out,
+                                                               float* __restrict__ out32, int cout,
+                                                               int relu, Grid3 g) {
+  constexpr int NT = COUTP / 16;
+  const int l = threadIdx.x & 63;
+  const long long tile = (long long)blockIdx.x * kConvWaves + (threadIdx.x >> 6);
+  const long long P = g.P();
+  if (tile * 16 >= P) return;                 // no barriers in this kernel
+  const int i = l & 15, kq = l >> 4;
+  const long long v = tile * 16 + i;
+  const bool vok = v < P;
+  const int x = int(v % g.X), y = int((v / g.X) % g.Y), z = int(v / ((long long)g.X * g.Y));
+  f4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int tap = 0; tap < 27; ++tap) {
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const bool ok = vok && x + dx >= 0 && x + dx < g.X && y + dy >= 0 && y + dy < g.Y && z + dz >= 0 &&
+                    z + dz < g.Z;
+    const long long nv = ok ? v + dx + (long long)g.X * (dy + (long long)g.Y * dz) : 0;
+    const bf16* src = in.p + nv * in.cs + in.coff + 4 * kq;
+    const bf16* wt = W + ((size_t)tap * COUTP + i) * CIN + 4 * kq;
+#pragma unroll
+    for (int kc = 0; kc < CIN / 16; ++kc) {
+      s4 a = *reinterpret_cast<const s4*>(src + 16 * kc);
+      if (!ok) a = s4{0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const s4 b = *reinterpret_cast<const s4*>(wt + (size_t)t * 16 * CIN + 16 * kc);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + i;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long long vo = tile * 16 + 4 * kq + e;
+      if (vo >= P || co >= cout) continue;
+      float val = acc[t][e] + (bias ? bias[co] : 0.f);
+      if (relu) val = fmaxf(val, 0.f);
+      if (out32)
+        out32[vo * 2 + co] = val;
+      else
+        out.p[vo * out.cs + out.coff + co] = f2bf(val);
+    }
+  }
+}
+
+constexpr int kWgTile = 64;      // voxels per weight-gradient tile
+constexpr int kWgStride = 68;    // LDS row stride (bf16) of the transposed tiles
+
+// Partial weight gradients of one tap over a strided set of voxel tiles:
+//   part[g][tap][co][ci] = sum_v dz[v][co] x[v + tap][ci]
+// and (centre tap) the bias partials bpart[g][co] = sum_v dz[v][co].
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(256) void wgrad_kernel(View dz, View xin, float* __restrict__ part,
+                                                    float* __restrict__ bpart, Grid3 g) {
+  __shared__ __attribute__((aligned(16))) bf16 dzT[COUTP * kWgStride];
+  __shared__ __attribute__((aligned(16))) bf16 xT[CINP * kWgStride];
+  constexpr int NA = COUTP / 16, NB = CINP / 16, NPAIR = NA * NB;
+  constexpr int PW = (NPAIR + 3) / 4;        // pairs per wave
+  const int tap = blockIdx.x, gi = blockIdx.y, G = gridDim.y;
+  const int dzt = tap / 9 - 1, dyt = (tap / 3) % 3 - 1, dxt = tap % 3 - 1;
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, i = l & 15, kq = l >> 4;
+  const long long P = g.P();
+  const long long ntiles = (P + kWgTile - 1) / kWgTile;
+  f4 acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  for (long long tl = gi; tl < ntiles; tl += G) {
+    const long long v0 = tl * kWgTile;
+    // stage dz (transposed) and the tap-shifted input (transposed, zero outside)
+    for (int idx = tid; idx < kWgTile * (COUTP / 4); idx += 256) {
+      const int vv = idx / (COUTP / 4), cq = idx % (COUTP / 4);
+      const long long v = v0 + vv;
+      s4 a = s4{0, 0, 0, 0};
+      if (v < P) a = *reinterpret_cast<const s4*>(dz.p + v * dz.cs + dz.coff + 4 * cq);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dzT[(4 * cq + e) * kWgStride + vv] = bf16(a[e]);
+    }
+    for (int idx = tid; idx < kWgTile * (CINP / 4); idx += 256) {
+      const int vv = idx / (CINP / 4), cq = idx % (CINP / 4);
+      const long long v = v0 + vv;
+      s4 a = s4{0, 0, 0, 0};
+      if (v < P) {
+        const int x = int(v % g.X), y = int((v / g.X) % g.Y), z = int(v / ((long long)g.X * g.Y));
+        if (x + dxt >= 0 && x + dxt < g.X && y + dyt >= 0 && y + dyt < g.Y && z + dzt >= 0 && z + dzt < g.Z) {
+          const long long nv = v + dxt + (long long)g.X * (dyt + (long long)g.Y * dzt);
+          a = *reinterpret_cast<const s4*>(xin.p + nv * xin.cs + xin.coff + 4 * cq);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xT[(4 * cq + e) * kWgStride + vv] = bf16(a[e]);
+    }
+    __syncthreads();
+    if (tap == 13 && tid < COUTP)
+      for (int vv = 0; vv < kWgTile; ++vv) bsum += bf2f(dzT[tid * kWgStride + vv]);
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int pr = wave + 4 * q;
+      if (pr < NPAIR) {
+        const int ta = pr / NB, tb = pr % NB;
+#pragma unroll
+        for (int kc = 0; kc < kWgTile / 16; ++kc) {
+          const s4 a = *reinterpret_cast<const s4*>(&dzT[(ta * 16 + i) * kWgStride + kc * 16 + 4 * kq]);
+          const s4 b = *reinterpret_cast<const s4*>(&xT[(tb * 16 + i) * kWgStride + kc * 16 + 4 * kq]);
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* dst = part + ((size_t)gi * 27 + tap) * COUTP * CINP;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int pr = wave + 4 * q;
+    if (pr < NPAIR) {
+      const int ta = pr / NB, tb = pr % NB;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[(ta * 16 + 4 * kq + e) * CINP + tb * 16 + i] = acc[q][e];
+    }
+  }
+  if (tap == 13 && tid < COUTP) bpart[(size_t)gi * COUTP + tid] = bsum;
+}
+
+// grad (parameter layout) of one layer from the partials, summed over the
+// G workgroup rows in order.
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, const float* __restrict__ bpart,
+                                    int G, int cin, int cout, int cinp, int coutp, float* __restrict__ gw,
+                                    float* __restrict__ gb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nw = cout * cin * 27;
+  if (idx < nw) {
+    const int tap = idx % 27, ci = (idx / 27) % cin, co = idx / (27 * cin);
+    float s = 0.f;
+    for (int q = 0; q < G; ++q) s += part[(((size_t)q * 27 + tap) * coutp + co) * cinp + ci];
+    gw[idx] = s;
+  } else if (idx < nw + cout) {
+    const int co = idx - nw;
+    float s = 0.f;
+    for (int q = 0; q < G; ++q) s += bpart[(size_t)q * coutp + co];
+    gb[co] = s;
+  }
+}
+
+// BF16 weight copies of one layer from the FP32 master (parameter layout):
+// fwd[tap][co][ci] (co < coutp, ci < cinp, zero padded) for the forward pass,
+// bwd[tap'][ci][co] = W[co][ci][26 - tap'] for the input gradient.
+__global__ void pack_kernel(const float* __restrict__ w, int cin, int cout, int cinp, int coutp,
+                            bf16* __restrict__ fwd, bf16* __restrict__ bwd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 27 * coutp * cinp) return;
+  const int ci = idx % cinp, co = (idx / cinp) % coutp, tap = idx / (cinp * coutp);
+  const float val = (ci < cin && co < cout) ? w[((size_t)co * cin + ci) * 27 + tap] : 0.f;
+  fwd[idx] = f2bf(val);
+  bwd[((size_t)(26 - tap) * cinp + ci) * coutp + co] = f2bf(val);
+}
+
+// network input: (Re r / s, Im r / s, kh, 0 ...) with s^2 = mean |r|^2 (16 channels)
+__global__ void features_kernel(const double2* __restrict__ r, const double* __restrict__ nrm2,
+                                long long P, float kh, bf16* __restrict__ x) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double ms = *nrm2 / double(P);
+  const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+  const double2 a = r[v];
+  bf16* d = x + v * 16;
+  d[0] = f2bf(float(a.x * inv));
+  d[1] = f2bf(float(a.y * inv));
+  d[2] = f2bf(ms > 0.0 ? kh : 0.f);
+}
+
+// 2x2x2 average pool (extent ceil(n/2), divisor 8) of C channels
+__global__ void pool_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= go.P() * C) return;
+  const int c = int(idx % C);
+  const long long vo = idx / C;
+  const int x = int(vo % go.X), y = int((vo / go.X) % go.Y), z = int(vo / ((long long)go.X * go.Y));
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int d = 0; d < 2; ++d) {
+        const int xi = 2 * x + d, yi = 2 * y + b, zi = 2 * z + a;
+        if (xi < gi.X && yi < gi.Y && zi < gi.Z)
+          s += bf2f(in.p[(xi + (long long)gi.X * (yi + (long long)gi.Y * zi)) * in.cs + in.coff + c]);
+      }
+  out.p[vo * out.cs + out.coff + c] = f2bf(s * 0.125f);
+}
+
+// gradient of the pool, added to din: din[v] += dout[v / 2] / 8
+__global__ void pool_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= gi.P() * C) return;
+  const int c = int(idx % C);
+  const long long v = idx / C;
+  const int x = int(v % gi.X), y = int((v / gi.X) % gi.Y), z = int(v / ((long long)gi.X * gi.Y));
+  const long long vo = (x / 2) + (long long)go.X * ((y / 2) + (long long)go.Y * (z / 2));
+  bf16* d = din.p + v * din.cs + din.coff + c;
+  *d = f2bf(bf2f(*d) + 0.125f * bf2f(dout.p[vo * dout.cs + dout.coff + c]));
+}
+
+// nearest-neighbour upsampling: out[v] = in[v / 2]
+__global__ void up_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= go.P() * C) return;
+  const int c = int(idx % C);
+  const long long v = idx / C;
+  const int x = int(v % go.X), y = int((v / go.X) % go.Y), z = int(v / ((long long)go.X * go.Y));
+  const long long vi = (x / 2) + (long long)gi.X * ((y / 2) + (long long)gi.Y * (z / 2));
+  out.p[v * out.cs + out.coff + c] = in.p[vi * in.cs + in.coff + c];
+}
+
+// gradient of the upsampling: din[v] = sum of dout over the children of v
+__global__ void up_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= gi.P() * C) return;
+  const int c = int(idx % C);
+  const long long v = idx / C;
+  const int x = int(v % gi.X), y = int((v / gi.X) % gi.Y), z = int(v / ((long long)gi.X * gi.Y));
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int d = 0; d < 2; ++d) {
+        const int xo = 2 * x + d, yo = 2 * y + b, zo = 2 * z + a;
+        if (xo < go.X && yo < go.Y && zo < go.Z)
+          s += bf2f(dout.p[(xo + (long long)go.X * (yo + (long long)go.Y * zo)) * dout.cs + dout.coff + c]);
+      }
+  din.p[v * din.cs + din.coff + c] = f2bf(s);
+}
+
+// ReLU gradient: g *= (a > 0)
+__global__ void relu_back_kernel(View gv, View av, long long P, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= P * C) return;
+  const int c = int(idx % C);
+  const long long v = idx / C;
+  if (!(bf2f(av.p[v * av.cs + av.coff + c]) > 0.f)) gv.p[v * gv.cs + gv.coff + c] = 0;
+}
+
+// correction c = s (y0 + i y1): mode 0 writes complex128, 1 adds to complex128,
+// 2 adds to complex64
+__global__ void output_kernel(const float* __restrict__ y, const double* __restrict__ nrm2, long long P,
+                              void* dst, int mode) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double s = sqrt(*nrm2 / double(P));
+  const double cx = s * y[2 * v], cy = s * y[2 * v + 1];
+  if (mode == 0) {
+    static_cast<double2*>(dst)[v] = make_double2(cx, cy);
+  } else if (mode == 1) {
+    double2* d = static_cast<double2*>(dst) + v;
+    *d = make_double2(d->x + cx, d->y + cy);
+  } else {
+    float2* d = static_cast<float2*>(dst) + v;
+    *d = make_float2(float(d->x + cx), float(d->y + cy));
+  }
+}
+
+// loss numerator partials and the output gradient dY = 2 s (c - t) / den
+// (BF16, channels 0, 1 of a 16-channel buffer)
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y,
+                                                   const double* __restrict__ nrm2,
+                                                   const double* __restrict__ den,
+                                                   const double2* __restrict__ t, long long P,
+                                                   bf16* __restrict__ dy, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const double s = sqrt(*nrm2 / double(P));
+  const double dn = *den;
+  const double f = dn > 0.0 ? 2.0 * s / dn : 0.0;
+  for (long long v = blockIdx.x * 256LL + threadIdx.x; v < P; v += (long long)gridDim.x * 256) {
+    const double2 tv = t[v];
+    const double ex = s * y[2 * v] - tv.x, ey = s * y[2 * v + 1] - tv.y;
+    acc += ex * ex + ey * ey;
+    dy[v * 16] = f2bf(float(f * ex));
+    dy[v * 16 + 1] = f2bf(float(f * ey));
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, long long n, float lr, float c1, float c2) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+struct LayerDef {
+  int cin, cout, relu;
+};
+constexpr LayerDef kLayers[11] = {{3, 16, 1},  {16, 16, 1}, {16, 32, 1}, {32, 32, 1},
+                                  {32, 64, 1}, {64, 64, 1}, {96, 32, 1}, {32, 32, 1},
+                                  {48, 16, 1}, {16, 16, 1}, {16, 2, 0}};
+enum { E1A, E1B, E2A, E2B, B3A, B3B, D2A, D2B, D1A, D1B, OUT, NL };
+
+int r16(int c) { return (c + 15) / 16 * 16; }
+
+long long param_count() {
+  long long n = 0;
+  for (const auto& L : kLayers) n += (long long)L.cout * L.cin * 27 + L.cout;
+  return n;
+}
+
+constexpr int kWgGroups = 64;     // workgroup rows of the weight-gradient reduction
+
+}  // namespace
+}  // namespace h6
+
+struct h6_net_s {
+  h6::Grid3 g1{}, g2{}, g3{};
+  long long np = 0;
+  // parameters
+  float* w32 = nullptr;     // master (parameter layout)
+  float* grad = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  long long off[h6::NL] = {};          // weight offset of each layer in the parameter array
+  h6::bf16* wf[h6::NL] = {};           // packed BF16 forward weights
+  h6::bf16* wb[h6::NL] = {};           // packed BF16 input-gradient weights
+  int adam_t = 0;
+  // activations (channels-last BF16)
+  h6::bf16 *X0 = nullptr, *T1 = nullptr, *C1 = nullptr, *T1b = nullptr, *D1 = nullptr;
+  h6::bf16 *Pl1 = nullptr, *T2 = nullptr, *C2 = nullptr, *T2b = nullptr, *D2 = nullptr;
+  h6::bf16 *Pl2 = nullptr, *T3 = nullptr, *B3 = nullptr;
+  float* Y = nullptr;
+  // gradients (allocated for training)
+  h6::bf16 *dY = nullptr, *dD1 = nullptr, *dT1b = nullptr, *dC1 = nullptr, *dT1 = nullptr;
+  h6::bf16 *dD2 = nullptr, *dT2b = nullptr, *dC2 = nullptr, *dT2 = nullptr, *dPl1 = nullptr;
+  h6::bf16 *dB3 = nullptr, *dT3 = nullptr, *dPl2 = nullptr;
+  float* part = nullptr;
+  float* bpart = nullptr;
+  // scalars: [0] |r|^2, [1] |t|^2, [2] loss numerator
+  double* d_scal = nullptr;
+  double* partials = nullptr;
+  double* h_scal = nullptr;     // pinned
+  std::vector<void*> allocs;
+};
+
+namespace h6 {
+namespace {
+
+template <typename T>
+hipError_t dalloc(h6_net N, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T) + 64);
+  if (e != hipSuccess) return e;
+  N->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return hipMemset(q, 0, count * sizeof(T) + 64);
+}
+
+unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+#define H6_CONV_CASES(X) \
+  X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(16, 48) X(32, 96) X(64, 32) X(32, 16)
+
+hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
+                int cout, int relu, Grid3 g, hipStream_t s) {
+  const unsigned grid = unsigned((g.P() + 16 * kConvWaves - 1) / (16 * kConvWaves));
+#define H6_CONV(CI, CO)                                                                             \
+  if (cinp == CI && coutp == CO) {                                                                  \
+    hipLaunchKernelGGL((conv_kernel<CI, CO>), dim3(grid), dim3(64 * kConvWaves), 0, s, in, W, bias, \
+                       out, out32, cout, relu, g);                                                  \
+    return hipGetLastError();                                                                       \
+  }
+  H6_CONV_CASES(H6_CONV)
+#undef H6_CONV
+  return hipErrorInvalidValue;
+}
+
+#define H6_WGRAD_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16)
+
+hipError_t wgrad(View dz, View xin, int cinp, int coutp, float* part, float* bpart, Grid3 g,
+                 hipStream_t s) {
+#define H6_WG(CI, CO)                                                                              \
+  if (cinp == CI && coutp == CO) {                                                                 \
+    hipLaunchKernelGGL((wgrad_kernel<CI, CO>), dim3(27, kWgGroups), dim3(256), 0, s, dz, xin, part, \
+                       bpart, g);                                                                  \
+    return hipGetLastError();                                                                      \
+  }
+  H6_WGRAD_CASES(H6_WG)
+#undef H6_WG
+  return hipErrorInvalidValue;
+}
+
+View vw(bf16* p, int cs, int coff = 0) { return View{p, cs, coff}; }
+
+// one layer: out = act(conv(in)) with the layer's packed weights
+hipError_t layer_fwd(h6_net N, int L, View in, View out, float* out32, Grid3 g, hipStream_t s) {
+  const LayerDef& d = kLayers[L];
+  return conv(in, r16(d.cin), N->wf[L], r16(d.cout), N->w32 + N->off[L] + (long long)d.cout * d.cin * 27,
+              out, out32, d.cout, d.relu, g, s);
+}
+
+hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s) {
+  const Grid3 g1 = N->g1, g2 = N->g2, g3 = N->g3;
+  hipError_t e = launch_norm2(r, size_t(g1.P()), N->partials, N->d_scal, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(features_kernel, dim3(nblk(g1.P())), dim3(256), 0, s, r, N->d_scal, g1.P(),
+                     float(kh), N->X0);
+#define TRY(x) if ((e = (x)) != hipSuccess) return e
+  TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s));
+  TRY(layer_fwd(N, E1B, vw(N->T1, 16), vw(N->C1, 48, 32), nullptr, g1, s));
+  hipLaunchKernelGGL(pool_kernel, dim3(nblk(g2.P() * 16)), dim3(256), 0, s, vw(N->C1, 48, 32), g1,
+                     vw(N->Pl1, 16), g2, 16);
+  TRY(layer_fwd(N, E2A, vw(N->Pl1, 16), vw(N->T2, 32), nullptr, g2, s));
+  TRY(layer_fwd(N, E2B, vw(N->T2, 32), vw(N->C2, 96, 64), nullptr, g2, s));
+  hipLaunchKernelGGL(pool_kernel, dim3(nblk(g3.P() * 32)), dim3(256), 0, s, vw(N->C2, 96, 64), g2,
+                     vw(N->Pl2, 32), g3, 32);
+  TRY(layer_fwd(N, B3A, vw(N->Pl2, 32), vw(N->T3, 64), nullptr, g3, s));
+  TRY(layer_fwd(N, B3B, vw(N->T3, 64), vw(N->B3, 64), nullptr, g3, s));
+  hipLaunchKernelGGL(up_kernel, dim3(nblk(g2.P() * 64)), dim3(256), 0, s, vw(N->B3, 64), g3,
+                     vw(N->C2, 96, 0), g2, 64);
+  TRY(layer_fwd(N, D2A, vw(N->C2, 96), vw(N->T2b, 32), nullptr, g2, s));
+  TRY(layer_fwd(N, D2B, vw(N->T2b, 32), vw(N->D2, 32), nullptr, g2, s));
+  hipLaunchKernelGGL(up_kernel, dim3(nblk(g1.P() * 32)), dim3(256), 0, s, vw(N->D2, 32), g2,
+                     vw(N->C1, 48, 0), g1, 32);
+  TRY(layer_fwd(N, D1A, vw(N->C1, 48), vw(N->T1b, 16), nullptr, g1, s));
+  TRY(layer_fwd(N, D1B, vw(N->T1b, 16), vw(N->D1, 16), nullptr, g1, s));
+  TRY(layer_fwd(N, OUT, vw(N->D1, 16), View{nullptr, 0, 0}, N->Y, g1, s));
+#undef TRY
+  return hipGetLastError();
+}
+
+// backward of one layer given the gradient gout of its (post-activation)
+// output act: masks gout by the ReLU, accumulates the weight gradients and
+// (gin.p != nullptr) writes the input gradient
+hipError_t layer_bwd(h6_net N, int L, View act, View gout, View xin, View gin, Grid3 g, hipStream_t s) {
+  const LayerDef& d = kLayers[L];
+  const int cinp = r16(d.cin), coutp = r16(d.cout);
+  hipError_t e;
+  if (d.relu)
+    hipLaunchKernelGGL(relu_back_kernel, dim3(nblk(g.P() * d.cout)), dim3(256), 0, s, gout, act, g.P(),
+                       d.cout);
+  if ((e = wgrad(gout, xin, cinp, coutp, N->part, N->bpart, g, s)) != hipSuccess) return e;
+  const long long nw = (long long)d.cout * d.cin * 27;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nblk(nw + d.cout)), dim3(256), 0, s, N->part, N->bpart,
+                     kWgGroups, d.cin, d.cout, cinp, coutp, N->grad + N->off[L], N->grad + N->off[L] + nw);
+  if (gin.p)
+    return conv(gout, coutp, N->wb[L], cinp, nullptr, gin, nullptr, cinp, 0, g, s);
+  return hipGetLastError();
+}
+
+hipError_t backward(h6_net N, hipStream_t s) {
+  const Grid3 g1 = N->g1, g2 = N->g2, g3 = N->g3;
+  hipError_t e;
+#define TRY(x) if ((e = (x)) != hipSuccess) return e
+  TRY(layer_bwd(N, OUT, View{nullptr, 0, 0}, vw(N->dY, 16), vw(N->D1, 16), vw(N->dD1, 16), g1, s));
+  TRY(layer_bwd(N, D1B, vw(N->D1, 16), vw(N->dD1, 16), vw(N->T1b, 16), vw(N->dT1b, 16), g1, s));
+  TRY(layer_bwd(N, D1A, vw(N->T1b, 16), vw(N->dT1b, 16), vw(N->C1, 48), vw(N->dC1, 48), g1, s));
+  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g2.P() * 32)), dim3(256), 0, s, vw(N->dC1, 48, 0), g1,
+                     vw(N->dD2, 32), g2, 32);
+  TRY(layer_bwd(N, D2B, vw(N->D2, 32), vw(N->dD2, 32), vw(N->T2b, 32), vw(N->dT2b, 32), g2, s));
+  TRY(layer_bwd(N, D2A, vw(N->T2b, 32), vw(N->dT2b, 32), vw(N->C2, 96), vw(N->dC2, 96), g2, s));
+  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g3.P() * 64)), dim3(256), 0, s, vw(N->dC2, 96, 0), g2,
+                     vw(N->dB3, 64), g3, 64);
+  TRY(layer_bwd(N, B3B, vw(N->B3, 64), vw(N->dB3, 64), vw(N->T3, 64), vw(N->dT3, 64), g3, s));
+  TRY(layer_bwd(N, B3A, vw(N->T3, 64), vw(N->dT3, 64), vw(N->Pl2, 32), vw(N->dPl2, 32), g3, s));
+  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g2.P() * 32)), dim3(256), 0, s, vw(N->dPl2, 32), g3,
+                     vw(N->dC2, 96, 64), g2, 32);
+  TRY(layer_bwd(N, E2B, vw(N->C2, 96, 64), vw(N->dC2, 96, 64), vw(N->T2, 32), vw(N->dT2, 32), g2, s));
+  TRY(layer_bwd(N, E2A, vw(N->T2, 32), vw(N->dT2, 32), vw(N->Pl1, 16), vw(N->dPl1, 16), g2, s));
+  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g1.P() * 16)), dim3(256), 0, s, vw(N->dPl1, 16), g2,
+                     vw(N->dC1, 48, 32), g1, 16);
+  TRY(layer_bwd(N, E1B, vw(N->C1, 48, 32), vw(N->dC1, 48, 32), vw(N->T1, 16), vw(N->dT1, 16), g1, s));
+  TRY(layer_bwd(N, E1A, vw(N->T1, 16), vw(N->dT1, 16), vw(N->X0, 16), View{nullptr, 0, 0}, g1, s));
+#undef TRY
+  return hipGetLastError();
+}
+
+hipError_t pack_all(h6_net N, hipStream_t s) {
+  for (int L = 0; L < NL; ++L) {
+    const LayerDef& d = kLayers[L];
+    const int n = 27 * r16(d.cout) * r16(d.cin);
+    hipLaunchKernelGGL(pack_kernel, dim3(nblk(n)), dim3(256), 0, s, N->w32 + N->off[L], d.cin, d.cout,
+                       r16(d.cin), r16(d.cout), N->wf[L], N->wb[L]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t alloc_training(h6_net N) {
+  if (N->dY) return hipSuccess;
+  const long long p1 = N->g1.P(), p2 = N->g2.P(), p3 = N->g3.P();
+  hipError_t e = hipSuccess;
+  auto A = [&](bf16** p, long long n) { if (e == hipSuccess) e = dalloc(N, p, size_t(n)); };
+  A(&N->dY, p1 * 16); A(&N->dD1, p1 * 16); A(&N->dT1b, p1 * 16); A(&N->dC1, p1 * 48); A(&N->dT1, p1 * 16);
+  A(&N->dD2, p2 * 32); A(&N->dT2b, p2 * 32); A(&N->dC2, p2 * 96); A(&N->dT2, p2 * 32); A(&N->dPl1, p2 * 16);
+  A(&N->dB3, p3 * 64); A(&N->dT3, p3 * 64); A(&N->dPl2, p3 * 32);
+  if (e == hipSuccess) e = dalloc(N, &N->part, size_t(kWgGroups) * 27 * 96 * 64);
+  if (e == hipSuccess) e = dalloc(N, &N->bpart, size_t(kWgGroups) * 64);
+  if (e == hipSuccess) e = dalloc(N, &N->m, size_t(N->np));
+  if (e == hipSuccess) e = dalloc(N, &N->v, size_t(N->np));
+  return e;
+}
+
+// loss of the current forward output against t; gradients into N->grad
+hipError_t loss_backward(h6_net N, const double2* t, hipStream_t s) {
+  const long long P = N->g1.P();
+  hipError_t e = launch_norm2(t, size_t(P), N->partials, N->d_scal + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(loss_kernel, dim3(kRedBlocks), dim3(256), 0, s, N->Y, N->d_scal, N->d_scal + 1, t, P,
+                     N->dY, N->partials);
+  if ((e = launch_reduce_sum(N->partials, kRedBlocks, N->d_scal + 2, s)) != hipSuccess) return e;
+  return backward(N, s);
+}
+
+}  // namespace
+}  // namespace h6
+
+using namespace h6;
+
+extern "C" {
+
+long long h6net_param_count(void) { return param_count(); }
+
+h6_status h6net_create(const int dims[3], void* hip_stream, h6_net* out) {
+  if (!out) return H6_ERR_ARG;
+  *out = nullptr;
+  if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return H6_ERR_ARG;
+  h6_net N = new (std::nothrow) h6_net_s();
+  if (!N) return H6_ERR_ALLOC;
+  N->g1 = Grid3{dims[0], dims[1], dims[2]};
+  N->g2 = half(N->g1);
+  N->g3 = half(N->g2);
+  N->np = param_count();
+  long long o = 0;
+  for (int L = 0; L < NL; ++L) {
+    N->off[L] = o;
+    o += (long long)kLayers[L].cout * kLayers[L].cin * 27 + kLayers[L].cout;
+  }
+  const long long p1 = N->g1.P(), p2 = N->g2.P(), p3 = N->g3.P();
+  hipError_t e = hipSuccess;
+  auto B = [&](bf16** p, long long n) { if (e == hipSuccess) e = dalloc(N, p, size_t(n)); };
+  B(&N->X0, p1 * 16); B(&N->T1, p1 * 16); B(&N->C1, p1 * 48); B(&N->T1b, p1 * 16); B(&N->D1, p1 * 16);
+  B(&N->Pl1, p2 * 16); B(&N->T2, p2 * 32); B(&N->C2, p2 * 96); B(&N->T2b, p2 * 32); B(&N->D2, p2 * 32);
+  B(&N->Pl2, p3 * 32); B(&N->T3, p3 * 64); B(&N->B3, p3 * 64);
+  if (e == hipSuccess) e = dalloc(N, &N->Y, size_t(p1) * 2);
+  if (e == hipSuccess) e = dalloc(N, &N->w32, size_t(N->np));
+  if (e == hipSuccess) e = dalloc(N, &N->grad, size_t(N->np));
+  for (int L = 0; L < NL && e == hipSuccess; ++L) {
+    const size_t n = size_t(27) * r16(kLayers[L].cout) * r16(kLayers[L].cin);
+    e = dalloc(N, &N->wf[L], n);
+    if (e == hipSuccess) e = dalloc(N, &N->wb[L], n);
+  }
+  if (e == hipSuccess) e = dalloc(N, &N->d_scal, 8);
+  if (e == hipSuccess) e = dalloc(N, &N->partials, size_t(kRedBlocks));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&N->h_scal), 8 * sizeof(double));
+  if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) {
+    h6net_destroy(N);
+    return e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
+  }
+  *out = N;
+  return H6_OK;
+}
+
+h6_status h6net_set_params(h6_net N, const float* params, long long count, void* hip_stream) {
+  if (!N || !params || count != N->np) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(N->w32, params, size_t(count) * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess ||
+      pack_all(N, s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (N->m && (hipMemsetAsync(N->m, 0, size_t(N->np) * 4, s) != hipSuccess ||
+               hipMemsetAsync(N->v, 0, size_t(N->np) * 4, s) != hipSuccess))
+    return H6_ERR_HIP;
+  N->adam_t = 0;
+  return hipStreamSynchronize(s) == hipSuccess ? H6_OK : H6_ERR_HIP;
+}
+
+h6_status h6net_get_params(h6_net N, float* params, long long count, void* hip_stream) {
+  if (!N || !params || count != N->np) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(params, N->w32, size_t(count) * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return H6_ERR_HIP;
+  return H6_OK;
+}
+
+h6_status h6net_forward(h6_net N, const void* r, double kh, void* c, void* hip_stream) {
+  if (!N || !r || !c || r == c) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess) return H6_ERR_HIP;
+  hipLaunchKernelGGL(output_kernel, dim3(nblk(N->g1.P())), dim3(256), 0, s, N->Y, N->d_scal, N->g1.P(), c, 0);
+  return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
+}
+
+h6_status h6net_gradients(h6_net N, const void* r, double kh, const void* t, float* grads, double* loss,
+                          void* hip_stream) {
+  if (!N || !r || !t) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (alloc_training(N) != hipSuccess) return H6_ERR_ALLOC;
+  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess ||
+      loss_backward(N, static_cast<const double2*>(t), s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (hipMemcpyAsync(N->h_scal, N->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (grads && hipMemcpyAsync(grads, N->grad, size_t(N->np) * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return H6_ERR_HIP;
+  if (loss) *loss = N->h_scal[1] > 0.0 ? N->h_scal[2] / N->h_scal[1] : 0.0;
+  return H6_OK;
+}
+
+h6_status h6net_train_step(h6_net N, const void* r, double kh, const void* t, float lr, double* loss,
+                           void* hip_stream) {
+  if (!N || !r || !t) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (alloc_training(N) != hipSuccess) return H6_ERR_ALLOC;
+  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess ||
+      loss_backward(N, static_cast<const double2*>(t), s) != hipSuccess)
+    return H6_ERR_HIP;
+  N->adam_t += 1;
+  const float c1 = float(1.0 / (1.0 - std::pow(0.9, N->adam_t)));
+  const float c2 = float(1.0 / (1.0 - std::pow(0.999, N->adam_t)));
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(N->np)), dim3(256), 0, s, N->w32, N->grad, N->m, N->v, N->np,
+                     lr, c1, c2);
+  if (pack_all(N, s) != hipSuccess) return H6_ERR_HIP;
+  if (loss) {
+    if (hipMemcpyAsync(N->h_scal, N->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return H6_ERR_HIP;
+    *loss = N->h_scal[1] > 0.0 ? N->h_scal[2] / N->h_scal[1] : 0.0;
+  }
+  return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
+}
+
+void h6net_destroy(h6_net N) {
+  if (!N) return;
+  for (void* p : N->allocs) (void)hipFree(p);
+  if (N->h_scal) (void)hipHostFree(N->h_scal);
+  delete N;
+}
+
+}  // extern "C"
+
+namespace h6 {
+
+// z += correction(q) for the solver (complex64 z in mixed plans)
+hipError_t net_apply_add(h6_net N, const double2* q, double kh, void* z, bool z_f32, hipStream_t s) {
+  hipError_t e = forward(N, q, kh, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(output_kernel, dim3(nblk(N->g1.P())), dim3(256), 0, s, N->Y, N->d_scal, N->g1.P(), z,
+                     z_f32 ? 2 : 1);
+  return hipGetLastError();
+}
+
+bool net_matches(h6_net N, const int dims[3]) {
+  return N && N->g1.X == dims[0] && N->g1.Y == dims[1] && N->g1.Z == dims[2];
+}
+
+}  // namespace h6

@@ -1,4 +1,4 @@
-"""Python binding of the helmholtz6 C ABI (include/helmholtz6.h).
+"""Python binding of the helmholtz6 C ABI (include/helmholtz6.h, include/h6net.h).
 
 Argument marshalling only: every step of the computation runs in the HIP
 library.  Vectors are torch complex128 tensors on the GPU, contiguous, of
@@ -28,6 +28,13 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error")
+EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
+                "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
+                "helmholtz6_learned_steps", "h6net_destroy")
+# layers of the correction network: (name, Cin, Cout), in parameter order
+NET_LAYERS = (("e1a", 3, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32), ("b3a", 32, 64),
+              ("b3b", 64, 64), ("d2a", 96, 32), ("d2b", 32, 32), ("d1a", 48, 16), ("d1b", 16, 16),
+              ("out", 16, 2))
 
 
 class H6Params(ctypes.Structure):
@@ -67,6 +74,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
                  "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
+        getattr(lib, name).restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.h6net_param_count.argtypes = []
+    lib.h6net_param_count.restype = ctypes.c_longlong
+    lib.h6net_create.argtypes = [ctypes.POINTER(ctypes.c_int), vp, ctypes.POINTER(vp)]
+    lib.h6net_set_params.argtypes = [vp, fp, ctypes.c_longlong, vp]
+    lib.h6net_get_params.argtypes = [vp, fp, ctypes.c_longlong, vp]
+    lib.h6net_forward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
+    lib.h6net_gradients.argtypes = [vp, vp, ctypes.c_double, vp, fp, dp, vp]
+    lib.h6net_train_step.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_float, dp, vp]
+    lib.helmholtz6_attach_net.argtypes = [vp, vp]
+    lib.helmholtz6_learned_steps.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.h6net_destroy.argtypes = [vp]
+    lib.h6net_destroy.restype = None
+    for name in ("h6net_create", "h6net_set_params", "h6net_get_params", "h6net_forward",
+                 "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
+                 "helmholtz6_learned_steps"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -168,6 +193,16 @@ class Plan:
         return U, dict(status=status, iters=info.iters, rel_resid=info.rel_resid,
                        history=list(hist[:info.history_len]))
 
+    def attach_net(self, net):
+        """Use the learned correction of `net` in flexible GMRES solves (None detaches)."""
+        self._net = net
+        self._check(_lib.helmholtz6_attach_net(self._plan, net._net if net is not None else None))
+
+    def learned_steps(self) -> int:
+        n = ctypes.c_int()
+        self._check(_lib.helmholtz6_learned_steps(self._plan, ctypes.byref(n)))
+        return n.value
+
     def profile(self, enable: bool = True):
         self._check(_lib.helmholtz6_profile(self._plan, int(enable)))
 
@@ -190,6 +225,108 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The learned correction network (include/h6net.h) for grids of `dims`
+    (n'x, n'y, n'z).  Parameters are host float32 arrays in the parameter
+    layout: per layer of NET_LAYERS, W[co][ci][dz][dy][dx] then b[co]."""
+
+    def __init__(self, dims, stream=None):
+        d = (ctypes.c_int * 3)(*[int(x) for x in dims])
+        self._net = ctypes.c_void_p()
+        st = _lib.h6net_create(d, _stream_handle(stream), ctypes.byref(self._net))
+        if st != H6_OK:
+            raise H6Error(st, "h6net_create failed")
+        self.dims = tuple(int(x) for x in dims)
+        self.count = int(_lib.h6net_param_count())
+
+    @property
+    def shape(self):
+        return (self.dims[2], self.dims[1], self.dims[0])
+
+    def _check(self, st, what):
+        if st < 0:
+            raise H6Error(st, what)
+        return st
+
+    def _vec(self, t, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128
+                and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor of shape {self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, flat, stream=None):
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        if a.size != self.count:
+            raise ValueError(f"expected {self.count} parameters, got {a.size}")
+        self._check(_lib.h6net_set_params(self._net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          self.count, _stream_handle(stream)), "set_params")
+
+    def get_params(self, stream=None):
+        import numpy as np
+        a = np.empty(self.count, dtype=np.float32)
+        self._check(_lib.h6net_get_params(self._net, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          self.count, _stream_handle(stream)), "get_params")
+        return a
+
+    def forward(self, r, kh: float, out=None, stream=None):
+        out = torch.empty_like(r) if out is None else out
+        self._check(_lib.h6net_forward(self._net, self._vec(r, "r"), float(kh), self._vec(out, "out"),
+                                       _stream_handle(stream)), "forward")
+        return out
+
+    def gradients(self, r, kh: float, t, stream=None):
+        """(loss, flat float32 gradients) of the pair (r, t) without an update."""
+        import numpy as np
+        g = np.empty(self.count, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(_lib.h6net_gradients(self._net, self._vec(r, "r"), float(kh), self._vec(t, "t"),
+                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         ctypes.byref(loss), _stream_handle(stream)), "gradients")
+        return loss.value, g
+
+    def train_step(self, r, kh: float, t, lr: float, want_loss: bool = True, stream=None):
+        loss = ctypes.c_double()
+        self._check(_lib.h6net_train_step(self._net, self._vec(r, "r"), float(kh), self._vec(t, "t"),
+                                          float(lr), ctypes.byref(loss) if want_loss else None,
+                                          _stream_handle(stream)), "train_step")
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "_net", None) and self._net.value:
+            _lib.h6net_destroy(self._net)
+            self._net = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_net_params(params) -> "numpy.ndarray":
+    """Flat float32 parameter vector from {name: (W, b)} in NET_LAYERS order."""
+    import numpy as np
+    parts = []
+    for name, cin, cout in NET_LAYERS:
+        W, b = params[name]
+        parts += [np.asarray(W, dtype=np.float32).reshape(-1), np.asarray(b, dtype=np.float32).reshape(-1)]
+    return np.concatenate(parts)
+
+
+def unpack_net_params(flat) -> dict:
+    """{name: (W (Cout, Cin, 3, 3, 3), b (Cout,))} from the flat parameter vector."""
+    import numpy as np
+    out, o = {}, 0
+    for name, cin, cout in NET_LAYERS:
+        nw = cout * cin * 27
+        W = np.asarray(flat[o:o + nw]).reshape(cout, cin, 3, 3, 3)
+        b = np.asarray(flat[o + nw:o + nw + cout])
+        out[name] = (W, b)
+        o += nw + cout
+    return out
 
 
 def status_string(status: int) -> str:

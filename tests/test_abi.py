@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports every symbol of include/helmholtz6.h and
-rejects invalid plans before touching the GPU (no GPU needed)."""
+include/h6net.h and rejects invalid plans before touching the GPU (no GPU
+needed)."""
 import ctypes
 import os
 import re
@@ -9,6 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1212_1397_amd", "libhelmholtz6.so")
 HEADER = os.path.join(ROOT, "include", "helmholtz6.h")
+NET_HEADER = os.path.join(ROOT, "include", "h6net.h")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 
@@ -32,9 +34,51 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
 
 
+def net_declared_functions():
+    text = open(NET_HEADER).read()
+    return sorted(set(re.findall(r"\b((?:h6net|helmholtz6)_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
 def test_binding_lists_every_symbol():
     from paper_1212_1397_amd import helmholtz6 as h6
     assert sorted(h6.EXPORTED) == declared_functions()
+    assert sorted(h6.EXPORTED_NET) == net_declared_functions()
+
+
+def test_library_exports_every_network_symbol():
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB)
+    for n in net_declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_network_parameter_count():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    from oracle import unet
+    assert [(l[0], l[1], l[2]) for l in unet.LAYERS] == list(h6.NET_LAYERS)
+    expected = sum(co * ci * 27 + co for _, ci, co in h6.NET_LAYERS)
+    assert h6._lib.h6net_param_count() == expected
+
+
+def test_network_rejects_bad_arguments():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    out = ctypes.c_void_p()
+    bad = (ctypes.c_int * 3)(0, 4, 4)
+    assert h6._lib.h6net_create(bad, None, ctypes.byref(out)) == h6.H6_ERR_ARG
+    assert not out.value
+    assert h6._lib.h6net_forward(None, None, 0.0, None, None) == h6.H6_ERR_ARG
+    assert h6._lib.helmholtz6_attach_net(None, None) == h6.H6_ERR_ARG
+
+
+def test_pack_unpack_roundtrip():
+    import numpy as np
+    from paper_1212_1397_amd import helmholtz6 as h6
+    from paper_1212_1397_amd.workloads import init_net_params
+    p = init_net_params(h6.NET_LAYERS, 3)
+    flat = h6.pack_net_params(p)
+    q = h6.unpack_net_params(flat)
+    for name, _, _ in h6.NET_LAYERS:
+        np.testing.assert_array_equal(q[name][0], p[name][0].astype(np.float32))
 
 
 def test_status_strings():

@@ -1,0 +1,161 @@
+"""GPU parity of the learned correction network (include/h6net.h) against the
+FP64 oracle (oracle/unet.py), and its use inside flexible GMRES.
+
+Tolerances: the GPU keeps activations and weights in BF16 (8-bit
+significand, unit roundoff 2^-9) and accumulates in FP32.  The oracle gets
+the same BF16-rounded weights, so the difference comes from rounding each of
+the 11 layers' outputs (and, backward, each layer's input gradient) to BF16:
+about sqrt(11) * 2^-9 = 0.7% RMS for the forward output and twice as many
+roundings for the gradients; the tests allow 3% (output) and 3% (gradient
+blocks) in relative 2-norm when every ReLU is active (positive biases keep
+the pre-activations away from zero).  With mixed signs, a pre-activation
+within the rounding error of zero may switch its ReLU on one side only; a
+fraction p of such switches changes a gradient block by about sqrt(p) in
+relative 2-norm, so the general case is held to 15%."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet
+from paper_1212_1397_amd.workloads import init_net_params, random_field
+
+pytestmark = pytest.mark.gpu
+
+KH = 0.35
+
+
+def bf16_round(a):
+    """Round float64 values to BF16 (round to nearest even), as the device does."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def params_for_test(seed=5, out_scale=1.0, bias=None, wscale=1.0):
+    """Initial weights (seeded) with random biases, or all biases = `bias`."""
+    p = init_net_params([(l[0], l[1], l[2]) for l in unet.LAYERS], seed)
+    rng = np.random.default_rng(seed + 1)
+    for name in p:
+        W, b = p[name]
+        W = W * (out_scale if name == "out" else wscale)
+        b = 0.05 * rng.standard_normal(b.shape) if bias is None else np.full(b.shape, bias)
+        p[name] = (W, b)
+    return p
+
+
+def oracle_params(p):
+    """The weights as the device uses them (BF16); biases stay FP32 on the device."""
+    return {k: (bf16_round(W), np.asarray(b, dtype=np.float32).astype(np.float64)) for k, (W, b) in p.items()}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def h6():
+    from paper_1212_1397_amd import helmholtz6
+    return helmholtz6
+
+
+@pytest.mark.parametrize("dims", [(12, 10, 9), (17, 8, 6)])
+def test_forward_matches_oracle(h6, dims):
+    p = params_for_test(out_scale=100.0)
+    net = h6.Net(dims)
+    net.set_params(h6.pack_net_params(p))
+    shape = (dims[2], dims[1], dims[0])
+    r = random_field(shape, 3)
+    c = net.forward(torch.from_numpy(r).cuda(), KH).cpu().numpy()
+    ref = unet.correction(oracle_params(p), r, KH, 1.0)     # k h passed as k = KH, h = 1
+    print(f"dims {dims}: forward rel err {rel(c, ref):.2e}", flush=True)
+    assert rel(c, ref) < 3e-2
+
+
+def test_forward_is_homogeneous_and_zero_safe(h6):
+    dims = (10, 9, 8)
+    p = params_for_test(out_scale=100.0)
+    net = h6.Net(dims)
+    net.set_params(h6.pack_net_params(p))
+    r = torch.from_numpy(random_field((8, 9, 10), 4)).cuda()
+    c1 = net.forward(r, KH)
+    c2 = net.forward(2.0 * r, KH)
+    assert torch.equal(c2, 2.0 * c1)
+    z = net.forward(torch.zeros_like(r), KH)
+    assert torch.count_nonzero(z) == 0
+
+
+@pytest.mark.parametrize("regime", ["active", "mixed"])
+def test_gradients_match_oracle(h6, regime):
+    dims = (12, 10, 9)
+    if regime == "active":
+        p, tol = params_for_test(out_scale=100.0, bias=1.0, wscale=0.3), 3e-2
+    else:
+        p, tol = params_for_test(out_scale=100.0), 1.5e-1
+    net = h6.Net(dims)
+    net.set_params(h6.pack_net_params(p))
+    shape = (dims[2], dims[1], dims[0])
+    r = random_field(shape, 6)
+    t = 0.3 * random_field(shape, 7)
+    loss, g = net.gradients(torch.from_numpy(r).cuda(), KH, torch.from_numpy(t).cuda())
+    L_ref, grads = unet.loss_and_grads(oracle_params(p), r, KH, 1.0, t)
+    print(f"{regime}: loss gpu {loss:.6e} oracle {L_ref:.6e}", flush=True)
+    assert abs(loss - L_ref) / L_ref < 1e-2
+    gg = h6.unpack_net_params(g)
+    for name, _, _, _ in unet.LAYERS:
+        eW = rel(gg[name][0], grads[name][0])
+        eb = rel(gg[name][1], grads[name][1])
+        print(f"  {name}: dW rel err {eW:.2e}, db rel err {eb:.2e}", flush=True)
+        assert eW < tol and eb < tol, name
+
+
+def test_adam_step_and_loss_decrease(h6):
+    dims = (12, 10, 9)
+    p = params_for_test(out_scale=100.0)
+    net = h6.Net(dims)
+    flat0 = h6.pack_net_params(p)
+    net.set_params(flat0)
+    shape = (dims[2], dims[1], dims[0])
+    r = torch.from_numpy(random_field(shape, 8)).cuda()
+    t = torch.from_numpy(0.3 * random_field(shape, 9)).cuda()
+    _, g = net.gradients(r, KH, t)
+    lr = 1e-3
+    loss0 = net.train_step(r, KH, t, lr)
+    flat1 = net.get_params()
+    # first Adam step from zero moments: w - lr g / (|g| + eps) (FP32 arithmetic)
+    g32 = g.astype(np.float32)
+    expect = flat0 - np.float32(lr) * g32 / (np.abs(g32) + np.float32(1e-8))
+    np.testing.assert_allclose(flat1, expect, rtol=1e-5, atol=1e-6)
+    losses = [loss0] + [net.train_step(r, KH, t, lr) for _ in range(20)]
+    print("losses", [f"{x:.4f}" for x in losses[::5]], flush=True)
+    assert losses[-1] < 0.9 * losses[0]
+
+
+def test_learned_fgmres_converges_and_falls_back(h6):
+    from paper_1212_1397_amd.workloads import WORKLOADS, gaussian_sources
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    F = plan.rhs_gaussians(*gaussian_sources(w))
+    U0, info0 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
+    assert info0["status"] == "ok"
+    net = h6.Net(plan.dims)
+    # a zero correction passes the judge: every step uses it and the iterates
+    # are those of the plain solve, bit for bit
+    net.set_params(np.zeros(net.count, dtype=np.float32))
+    plan.attach_net(net)
+    U1, info1 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
+    print(f"plain {info0['iters']} its, zero correction {info1['iters']} its "
+          f"({plan.learned_steps()} with the correction)", flush=True)
+    assert plan.learned_steps() == info1["iters"] == info0["iters"]
+    assert torch.equal(U1, U0)
+    # a small random correction: the solve still converges to the tolerance
+    net.set_params(h6.pack_net_params(params_for_test(out_scale=1.0)))
+    U1, info1 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
+    assert info1["status"] == "ok" and info1["rel_resid"] <= w.tol
+    assert float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0)) < 1e-6
+    # a grossly wrong correction is rejected by the judge: plain iterations
+    net.set_params(h6.pack_net_params(params_for_test(out_scale=1e5)))
+    U2, info2 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
+    assert plan.learned_steps() == 0
+    assert info2["iters"] == info0["iters"] and info2["status"] == "ok"
+    plan.attach_net(None)
