@@ -11,6 +11,11 @@ TEST INFRASTRUCTURE ONLY: part of the FP64 CPU oracle.
   each cycle; inside a cycle the least-squares residual serves as estimate.
 * Flexible GMRES stores the preconditioned vectors z_j = M_j^{-1} v_j, so the
   preconditioner may change (or be inexact) from step to step.
+* Chebyshev acceleration (Section 2, Theorem 2 and its citation; Section 4):
+  the classical Chebyshev iteration for a real spectrum [alpha, beta],
+  0 < alpha, applied to the right-preconditioned system A A_p^{-1} Y = F and
+  written for U = A_p^{-1} Y; the paper takes alpha, beta from the exact
+  eigenvalues (3DEGV) of the Dirichlet problem.
 * SKS (Section 2, Algorithm 1): Y = F; repeat U = A_p^{-1} Y, r = F - A U,
   eps = ||r|| / ||F||, stop if eps <= tol, Y = Y + r.  The loop condition of
   the printed algorithm is read as "while j <= maxit and eps > tol", with
@@ -176,6 +181,51 @@ def sks_correction(A, Pinv, F, x0=None, tol=1e-10, maxit=100, diverge=1e4):
         if not np.isfinite(eps) or eps > diverge:
             info.status = "diverged"
             return U, info
+    return U, info
+
+
+def chebyshev(A, Pinv, F, alpha: float, beta: float, tol=1e-10, maxit=100, diverge=1e4):
+    """Chebyshev acceleration on A A_p^{-1} Y = F, spectrum in [alpha, beta].
+
+    With theta = (alpha + beta) / 2, delta = (beta - alpha) / 2 and
+    sigma = theta / delta, the textbook recurrence in Y reads
+      d_0 = r_0 / theta,  rho_0 = 1 / sigma,
+      Y_{k+1} = Y_k + d_k,  r_{k+1} = r_k - A A_p^{-1} d_k,
+      rho_{k+1} = 1 / (2 sigma - rho_k),
+      d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) r_{k+1};
+    with e_k = A_p^{-1} d_k it becomes, for U = A_p^{-1} Y,
+      U_{k+1} = U_k + e_k,  e_{k+1} = rho_{k+1} rho_k e_k + (2 rho_{k+1} / delta) A_p^{-1} r_{k+1}.
+    The residual r = F - A U is recomputed every iteration.  Zero initial
+    guess; iterations are counted as A A_p^{-1} applications."""
+    if not (0.0 < alpha < beta):
+        raise ValueError("Chebyshev acceleration needs 0 < alpha < beta")
+    theta, delta = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
+    sigma = theta / delta
+    normF = _norm(F.reshape(-1))
+    info = SolveInfo()
+    U = np.zeros_like(F)
+    if normF == 0.0:
+        info.status, info.rel_resid = "ok", 0.0
+        return U, info
+    r = F.copy()
+    rho = 1.0 / sigma
+    e = Pinv(r) / theta
+    for _ in range(maxit):
+        U = U + e
+        r = F - A(U)
+        eps = _norm(r.reshape(-1)) / normF
+        info.iters += 1
+        info.history.append(eps)
+        info.rel_resid = eps
+        if eps <= tol:
+            info.status = "ok"
+            return U, info
+        if not np.isfinite(eps) or eps > diverge:
+            info.status = "diverged"
+            return U, info
+        rho_next = 1.0 / (2.0 * sigma - rho)
+        e = rho_next * rho * e + (2.0 * rho_next / delta) * Pinv(r)
+        rho = rho_next
     return U, info
 
 
