@@ -8,8 +8,9 @@
  *     Section 3.2.1, eq. (3DN), and the Sommerfeld-like closure of
  *     Section 3.2.2, eq. (3DDISCS).
  *   - Preconditioner A_p: Section 3.3, eq. (3DAP).
- *   - Solvers: right-preconditioned GMRES (Section 2, eq. (AAP)) and the SKS
- *     iteration (Section 2, Algorithm 1).
+ *   - Solvers: right-preconditioned GMRES (Section 2, eq. (AAP)), the SKS
+ *     iteration (Section 2, Algorithm 1) and Chebyshev acceleration (Section 2,
+ *     Theorem 2) with the closed-form spectrum bounds of eq. (3DEGV).
  *
  * Every entry point is extern "C" and never throws.  All vectors are device
  * pointers to complex128 values stored as interleaved (re, im) doubles, x
@@ -49,7 +50,7 @@ typedef enum {
 } h6_status;
 
 typedef enum { H6_DIRICHLET = 0, H6_NEUMANN = 1, H6_SOMMERFELD = 2 } h6_bc;
-typedef enum { H6_GMRES = 0, H6_FGMRES = 1, H6_SKS = 2 } h6_method;
+typedef enum { H6_GMRES = 0, H6_FGMRES = 1, H6_SKS = 2, H6_CHEBYSHEV = 3 } h6_method;
 typedef enum { H6_FP64 = 0, H6_MIXED = 1 } h6_precision;
 
 typedef struct h6_plan_s* h6_plan;
@@ -116,9 +117,26 @@ h6_status helmholtz6_rhs_gaussians(h6_plan plan, int nsrc, const double* centres
  * preconditioning, modified Gram-Schmidt Arnoldi, Givens least squares in FP64
  * on the host, restart every info->restart steps.  SKS: Algorithm 1 written
  * in correction form U += A_p^{-1} r (identical iterates for U0 = 0).
+ * Chebyshev: the classical Chebyshev iteration on A A_p^{-1} over the exact
+ * spectrum interval of helmholtz6_spectrum_bounds, one A and one A_p^{-1}
+ * per iteration (all-Dirichlet faces, real k; diverged as for SKS).
  * Synchronises hip_stream before returning. */
 h6_status helmholtz6_solve(h6_plan plan, const void* F, void* U, h6_solve_info* info,
                            void* hip_stream);
+
+/* Exact bounds [lo, hi] of the spectrum of A A_p^{-1} for all-Dirichlet faces
+ * and real k: the smallest and largest lambda / lambda^p of eq. (3DEGV) over
+ * every sine mode of the grid (computed on the host on first use).
+ * H6_ERR_ARG for other face patterns or complex k.  Chebyshev acceleration
+ * (method H6_CHEBYSHEV) uses them and requires lo > 0 (H6_ERR_ARG otherwise:
+ * the iteration does not apply). */
+h6_status helmholtz6_spectrum_bounds(h6_plan plan, double* lo, double* hi);
+
+/* Order estimate psi of eq. (PSI) from the first two SKS residual norms on
+ * grids h and gamma h: eps = ||r_2|| / ||r_1|| on each grid,
+ * psi = (ln eps^{gamma h} - ln eps^h) / ln gamma (gamma > 1; NaN if any
+ * argument is not positive). */
+double helmholtz6_psi_order(double r1_h, double r2_h, double r1_gh, double r2_gh, double gamma);
 
 /* Per-kernel timing: when enabled, the library records HIP events around
  * every kernel (or fused group of kernels) it launches on the caller's stream

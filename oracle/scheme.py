@@ -163,11 +163,13 @@ def dirichlet_eigenvalue_p(prob: Problem, i: int, j: int, l: int) -> complex:
 def dirichlet_preconditioned_bounds(prob: Problem):
     """(min, max) over all Dirichlet sine modes of lambda / lambda^p, the
     eigenvalues 1 + d of A A_p^{-1} (eq. (3DEGV)) for real k and all-Dirichlet
-    faces.  Evaluated for every mode (i, j, l) of the grid."""
+    faces.  Evaluated for every mode (i, j, l) of the grid.  On a box with n_a
+    unknowns per axis the sine modes have s_r = sin^2(r pi / (2 (n_a + 1)))
+    (= sin^2(r pi h / 2) on the unit cube of eq. (3DEGV))."""
     if any(f != "D" for f in prob.bc) or complex(prob.k).imag != 0.0:
         raise ValueError("the closed-form spectrum needs real k and Dirichlet faces")
-    h, kap = prob.h, float(np.real(prob.kappa))
-    s = [np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2 for n in prob.n]
+    kap = float(np.real(prob.kappa))
+    s = [np.sin(np.arange(1, n + 1) * np.pi / (2.0 * (n + 1))) ** 2 for n in prob.n]
     si, sj, sl = np.meshgrid(s[0], s[1], s[2], indexing="ij", sparse=True)
     lp = -4.0 * (si + sj + sl) + kap
     lam = (lp + (8.0 / 3.0) * (1.0 + kap / 30.0) * (si * sj + si * sl + sj * sl)

@@ -1,5 +1,6 @@
 // C ABI of the helmholtz6 library: parameter validation, plan construction
 // (coefficients of Section 3.1-3.3), workspace, status strings and timing.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -415,6 +416,57 @@ void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a, double bytes) {
 
 using namespace h6;
 
+namespace h6 {
+
+// Extreme eigenvalues of A A_p^{-1} over all Dirichlet sine modes: with
+// mu_a = -4 sin^2(m pi / (2 M_a)) the eigenvalues of D_a, A = D_z G + P has
+//   lambda = mu_z (1 + a (mu_x + mu_y) + mu_x mu_y / 30) + mu_x + mu_y + a mu_x mu_y + kappa c_K
+// (a = (1 + kappa/30)/6, c_K = 1 - kappa/12 + kappa^2/360; eq. (3DEGV)) and
+// A_p has lambda^p = mu_x + mu_y + mu_z + kappa.
+h6_status spectrum_bounds(h6_plan P) {
+  if (P->spec_done) return P->spec_status;
+  P->spec_done = true;
+  P->spec_status = H6_ERR_ARG;
+  for (int f = 0; f < 6; ++f)
+    if (P->p.bc[f] != H6_DIRICHLET) {
+      P->last_error = "spectrum bounds need Dirichlet faces";
+      return P->spec_status;
+    }
+  if (P->p.k_im != 0.0) {
+    P->last_error = "spectrum bounds need a real k";
+    return P->spec_status;
+  }
+  const double kap = P->kappa.real();
+  const double a = (1.0 + kap / 30.0) / 6.0, cK = 1.0 - kap / 12.0 + kap * kap / 360.0;
+  std::vector<double> mu[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = P->dims[ax];
+    for (int m = 1; m <= n; ++m) {
+      const double s = std::sin(M_PI * m / (2.0 * (n + 1)));
+      mu[ax].push_back(-4.0 * s * s);
+    }
+  }
+  double lo = INFINITY, hi = -INFINITY;
+  for (double mz : mu[2])
+    for (double my : mu[1])
+      for (double mx : mu[0]) {
+        const double lam = mz * (1.0 + a * (mx + my) + mx * my / 30.0) + mx + my + a * mx * my + kap * cK;
+        const double r = lam / (mx + my + mz + kap);
+        lo = std::min(lo, r);
+        hi = std::max(hi, r);
+      }
+  if (!std::isfinite(lo) || !std::isfinite(hi)) {
+    P->last_error = "spectrum bounds are not finite (k^2 on the 7-point spectrum)";
+    return P->spec_status;
+  }
+  P->spec_lo = lo;
+  P->spec_hi = hi;
+  P->spec_status = H6_OK;
+  return H6_OK;
+}
+
+}  // namespace h6
+
 extern "C" {
 
 h6_status helmholtz6_setup(const h6_params* p, void* hip_stream, h6_plan* out) {
@@ -475,8 +527,9 @@ h6_status helmholtz6_solve(h6_plan P, const void* F, void* U, h6_solve_info* inf
   if (!P) return H6_ERR_ARG;
   P->last_error.clear();
   if (!F || !U || !info || F == U) { P->last_error = "bad solve arguments"; return H6_ERR_ARG; }
-  if (info->method < H6_GMRES || info->method > H6_SKS || info->maxit < 1 || !(info->tol >= 0.0) ||
-      ((info->method != H6_SKS) && (info->restart < 1 || info->restart > 256)) ||
+  const bool krylov = info->method == H6_GMRES || info->method == H6_FGMRES;
+  if (info->method < H6_GMRES || info->method > H6_CHEBYSHEV || info->maxit < 1 || !(info->tol >= 0.0) ||
+      (krylov && (info->restart < 1 || info->restart > 256)) ||
       (info->history_len < 0) || (info->history_len > 0 && !info->history)) {
     P->last_error = "bad solve info";
     return H6_ERR_ARG;
@@ -543,6 +596,20 @@ const char* helmholtz6_status_string(h6_status s) {
     case H6_ERR_SINGULAR: return "preconditioner singular (k^2 on the 7-point spectrum)";
   }
   return "unknown status";
+}
+
+h6_status helmholtz6_spectrum_bounds(h6_plan P, double* lo, double* hi) {
+  if (!P || !lo || !hi) return H6_ERR_ARG;
+  const h6_status st = spectrum_bounds(P);
+  if (st != H6_OK) return st;
+  *lo = P->spec_lo;
+  *hi = P->spec_hi;
+  return H6_OK;
+}
+
+double helmholtz6_psi_order(double r1_h, double r2_h, double r1_gh, double r2_gh, double gamma) {
+  if (!(r1_h > 0.0 && r2_h > 0.0 && r1_gh > 0.0 && r2_gh > 0.0 && gamma > 1.0)) return std::nan("");
+  return (std::log(r2_gh / r1_gh) - std::log(r2_h / r1_h)) / std::log(gamma);
 }
 
 h6_status helmholtz6_attach_net(h6_plan P, h6_net net) {

@@ -102,6 +102,9 @@ struct h6_plan_s {
   double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
   struct h6_net_s* net = nullptr;              // learned correction for FGMRES (not owned)
+  bool spec_done = false;                      // exact spectrum bounds of A A_p^{-1} (Dirichlet)
+  h6_status spec_status = H6_OK;
+  double spec_lo = 0.0, spec_hi = 0.0;
   int learned_steps = 0;                       // steps of the last solve that used it
 
   h6::Timing timing;
@@ -188,6 +191,12 @@ hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y
 void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a);
 // bytes: the algorithmic HBM traffic of the work between begin and end
 void timing_end(h6_plan P, int cls, hipStream_t s, hipEvent_t a, double bytes);
+
+// exact spectrum bounds of A A_p^{-1} (all-Dirichlet, real k), cached in the plan
+h6_status spectrum_bounds(h6_plan P);
+// e = c1 e + c2 t; U += e (Chebyshev step)
+hipError_t launch_cheb_update(double2* e, const double2* t, double2* U, double c1, double c2, size_t n,
+                              hipStream_t s);
 
 // solver
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s);

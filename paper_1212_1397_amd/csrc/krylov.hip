@@ -243,6 +243,19 @@ __global__ __launch_bounds__(kThreads) void multi_axpy_kernel(double2* __restric
   }
 }
 
+// Chebyshev step: e = c1 e + c2 t; U += e
+__global__ __launch_bounds__(kThreads) void cheb_update_kernel(double2* __restrict__ e,
+                                                               const double2* __restrict__ t,
+                                                               double2* __restrict__ U, double c1,
+                                                               double c2, size_t n) {
+  for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
+    const double2 a = e[i], b = t[i], u = U[i];
+    const double2 v = make_double2(c1 * a.x + c2 * b.x, c1 * a.y + c2 * b.y);
+    e[i] = v;
+    U[i] = make_double2(u.x + v.x, u.y + v.y);
+  }
+}
+
 int grid_for(size_t n) {
   const size_t b = (n + kThreads - 1) / kThreads;
   return int(b < size_t(kRedBlocks) ? (b > 0 ? b : 1) : kRedBlocks);
@@ -339,6 +352,12 @@ hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, in
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_update(double2* e, const double2* t, double2* U, double c1, double c2, size_t n,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(cheb_update_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, e, t, U, c1, c2, n);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Host control loops of the solvers: right-preconditioned restarted GMRES(m)
-// and flexible GMRES(m) (Section 2, eq. (AAP)), and the SKS iteration
-// (Section 2, Algorithm 1) in correction form.
+// and flexible GMRES(m) (Section 2, eq. (AAP)), the SKS iteration (Section 2,
+// Algorithm 1) in correction form, and Chebyshev acceleration (Section 2,
+// Theorem 2) over the exact spectrum interval of eq. (3DEGV).
 //
 // Arnoldi: modified Gram-Schmidt in inverse compact WY form.  The basis is
 // kept unnormalised on the device (q~_i = nu_i q_i), so no scaling pass is
@@ -62,7 +63,9 @@ h6_status ensure(h6_plan P, int method, int m) {
   if (!P->ev_sync) e = hipEventCreateWithFlags(&P->ev_sync, hipEventDisableTiming);
   if (e == hipSuccess && !P->r) e = hipMalloc(reinterpret_cast<void**>(&P->r), vb);
   if (e == hipSuccess && !P->t) e = hipMalloc(reinterpret_cast<void**>(&P->t), vb);
-  if (e == hipSuccess && method != H6_SKS) {
+  if (e == hipSuccess && method == H6_CHEBYSHEV)
+    e = grow(reinterpret_cast<void**>(&P->V), &P->V_cols, 1, vb);     // the direction e
+  if (e == hipSuccess && method != H6_SKS && method != H6_CHEBYSHEV) {
     e = grow(reinterpret_cast<void**>(&P->V), &P->V_cols, m + 1, vb);
     if (e == hipSuccess && P->gram_dim < m + 1) {
       (void)hipFree(P->d_gram);
@@ -341,6 +344,50 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
   }
 }
 
+// Chebyshev acceleration on A A_p^{-1} Y = F over the spectrum interval
+// [alpha, beta] (theta = centre, delta = half width, sigma = theta / delta),
+// written for U = A_p^{-1} Y with the direction e = A_p^{-1} d:
+//   e_0 = A_p^{-1} r_0 / theta,  U_{k+1} = U_k + e_k,  r_{k+1} = F - A U_{k+1},
+//   rho_{k+1} = 1 / (2 sigma - rho_k),  e_{k+1} = rho_{k+1} rho_k e_k + (2 rho_{k+1} / delta) A_p^{-1} r_{k+1}.
+h6_status chebyshev(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
+  h6_plan P = c.P;
+  h6_status st = spectrum_bounds(P);
+  if (st != H6_OK) return st;
+  const double alpha = P->spec_lo, beta = P->spec_hi;
+  if (!(alpha > 0.0 && beta > alpha)) {
+    P->last_error = "Chebyshev acceleration needs a positive spectrum interval (lo > 0)";
+    return H6_ERR_ARG;
+  }
+  const double theta = 0.5 * (alpha + beta), delta = 0.5 * (beta - alpha), sigma = theta / delta;
+  double2* e = P->V;
+  int nh = 0;
+  st = residual_async(c, F, U, P->r);
+  if (st == H6_OK) st = wait(c);
+  if (st != H6_OK) return st;
+  info->iters = 0;
+  info->rel_resid = std::sqrt(c.host[kNorm]) / normF;
+  if (info->rel_resid <= info->tol) { info->history_len = 0; return H6_OK; }
+  double rho = 1.0 / sigma;
+  H6_TRY_HIP(launch_pinv(P, P->r, P->t, c.s));
+  H6_TRY_HIP(hipMemsetAsync(e, 0, c.N * sizeof(double2), c.s));
+  H6_TRY_HIP(launch_cheb_update(e, P->t, U, 0.0, 1.0 / theta, c.N, c.s));   // e_0; U_1 = U_0 + e_0
+  while (true) {
+    st = residual_async(c, F, U, P->r);
+    if (st == H6_OK) st = wait(c);
+    if (st != H6_OK) return st;
+    info->iters += 1;
+    info->rel_resid = std::sqrt(c.host[kNorm]) / normF;
+    record(info, nh, info->rel_resid);
+    if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
+    if (!std::isfinite(info->rel_resid) || info->rel_resid > 1e4) { info->history_len = nh; return H6_DIVERGED; }
+    if (info->iters >= info->maxit) { info->history_len = nh; return H6_NOT_CONVERGED; }
+    const double rho_next = 1.0 / (2.0 * sigma - rho);
+    H6_TRY_HIP(launch_pinv(P, P->r, P->t, c.s));
+    H6_TRY_HIP(launch_cheb_update(e, P->t, U, rho_next * rho, 2.0 * rho_next / delta, c.N, c.s));
+    rho = rho_next;
+  }
+}
+
 }  // namespace
 
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s) {
@@ -360,6 +407,7 @@ h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info
     return H6_OK;
   }
   if (info->method == H6_SKS) return sks(c, F, U, info, normF);
+  if (info->method == H6_CHEBYSHEV) return chebyshev(c, F, U, info, normF);
   return gmres(c, F, U, info, normF);
 }
 

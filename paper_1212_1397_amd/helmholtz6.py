@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhelmholtz6.so")
 H6_OK, H6_NOT_CONVERGED, H6_DIVERGED = 0, 1, 2
 H6_ERR_ARG, H6_ERR_UNSUPPORTED_BC, H6_ERR_ALLOC, H6_ERR_HIP, H6_ERR_SINGULAR = -1, -2, -3, -4, -5
 BC_CODES = {"D": 0, "N": 1, "S": 2}
-METHODS = {"gmres": 0, "fgmres": 1, "sks": 2}
+METHODS = {"gmres": 0, "fgmres": 1, "sks": 2, "chebyshev": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z", "mgs_dots",
                   "mgs_update", "norm", "axpy", "rhs")
@@ -27,7 +27,7 @@ KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z",
 EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
-            "helmholtz6_last_error")
+            "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
                 "helmholtz6_learned_steps", "h6net_destroy")
@@ -71,6 +71,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_status_string.restype = ctypes.c_char_p
     lib.helmholtz6_last_error.argtypes = [vp]
     lib.helmholtz6_last_error.restype = ctypes.c_char_p
+    lib.helmholtz6_spectrum_bounds.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double)]
+    lib.helmholtz6_spectrum_bounds.restype = ctypes.c_int
+    lib.helmholtz6_psi_order.argtypes = [ctypes.c_double] * 5
+    lib.helmholtz6_psi_order.restype = ctypes.c_double
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
                  "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
@@ -192,6 +197,12 @@ class Plan:
         status = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}[st]
         return U, dict(status=status, iters=info.iters, rel_resid=info.rel_resid,
                        history=list(hist[:info.history_len]))
+
+    def spectrum_bounds(self):
+        """(lo, hi): exact extreme eigenvalues of A A_p^{-1} (all-Dirichlet, real k)."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.helmholtz6_spectrum_bounds(self._plan, ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
 
     def attach_net(self, net):
         """Use the learned correction of `net` in flexible GMRES solves (None detaches)."""
@@ -327,6 +338,11 @@ def unpack_net_params(flat) -> dict:
         out[name] = (W, b)
         o += nw + cout
     return out
+
+
+def psi_order(r1_h: float, r2_h: float, r1_gh: float, r2_gh: float, gamma: float) -> float:
+    """eq. (PSI) from the first two SKS residual norms on grids h and gamma h."""
+    return _lib.helmholtz6_psi_order(float(r1_h), float(r2_h), float(r1_gh), float(r2_gh), float(gamma))
 
 
 def status_string(status: int) -> str:

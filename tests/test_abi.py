@@ -115,3 +115,13 @@ def test_singular_preconditioner_rejected_at_setup():
     with pytest.raises(h6.H6Error) as e:
         h6.Plan(n, h, k)
     assert e.value.status == -5
+
+
+def test_psi_order_matches_definition():
+    import math
+    from paper_1212_1397_amd import helmholtz6 as h6
+    from oracle import psi_order
+    assert math.isclose(h6.psi_order(1.0, 0.04, 1.0, 0.16, 2.0), psi_order(0.04, 0.16, 2.0), rel_tol=1e-14)
+    assert math.isclose(h6.psi_order(2.0, 0.5, 3.0, 0.75, 2.0), 0.0, abs_tol=1e-15)
+    assert math.isnan(h6.psi_order(0.0, 1.0, 1.0, 1.0, 2.0))
+    assert math.isnan(h6.psi_order(1.0, 1.0, 1.0, 1.0, 1.0))

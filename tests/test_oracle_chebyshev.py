@@ -16,9 +16,12 @@ from manufactured import source, table3_u
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
 
 
-@pytest.mark.parametrize("n,k", [(4, 10.0), (5, 7.5), (3, 2.0)])
+@pytest.mark.parametrize("n,k", [(4, 10.0), (5, 7.5), (3, 2.0), ((4, 5, 3), 6.0)])
 def test_spectrum_bounds_match_dense_eigenvalues(n, k):
-    prob = oracle.Problem.cube(n, k)
+    if isinstance(n, int):
+        prob = oracle.Problem.cube(n, k)
+    else:            # a box: common step h = 1/6, n_a + 1 steps per axis
+        prob = oracle.Problem(n=n, h=1.0 / 6, k=k, bc="DDDDDD")
     B = dense_A(prob) @ np.linalg.inv(dense_Ap(prob))
     ev = np.linalg.eigvals(B)
     assert np.max(np.abs(ev.imag)) < 1e-9
