@@ -138,6 +138,33 @@ h6_status helmholtz6_spectrum_bounds(h6_plan plan, double* lo, double* hi);
  * argument is not positive). */
 double helmholtz6_psi_order(double r1_h, double r2_h, double r1_gh, double r2_gh, double gamma);
 
+/* Solves count independent systems concurrently (the throughput form for many
+ * right-hand sides, wavenumbers and grid sizes): solve i is
+ * helmholtz6_solve(plans[i], F[i], U[i], &infos[i], s) on one of nstreams
+ * library-owned HIP streams (1..16), each driven by its own host thread;
+ * solves are started in decreasing order of an estimated cost (unknowns times
+ * a kh-based iteration estimate), longest first.  Every plan must appear once
+ * (a plan is not used by two threads).  statuses[i] receives solve i's
+ * status.  Returns H6_OK when every solve returned a non-negative status,
+ * otherwise the first negative one; waits for all solves. */
+h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* const* U,
+                                 h6_solve_info* infos, h6_status* statuses, int count, int nstreams);
+
+/* Captures each Arnoldi step of GMRES / FGMRES solves on the plan as a HIP
+ * graph (one per step index, built on first use and replayed by later
+ * solves; rebuilt when the workspace grows) and runs the solve on a
+ * plan-owned stream ordered after hip_stream.  Graphs are not used while
+ * kernel timing is enabled or a learned correction is attached.
+ * enable = 0 releases them. */
+h6_status helmholtz6_set_graphs(h6_plan plan, int enable);
+
+/* Autotuner: times the variants of the plan's kernels on the plan's own grid
+ * (stencil z-chunk depth 8, 16 or 32 planes per workgroup; for n'x or n'y + 1
+ * = 257 also the dense and the Rader transform) and keeps the fastest.  With
+ * cache_path != NULL the choice is read from, or appended to, that text file
+ * (one line per grid shape, precision and device).  Synchronous. */
+h6_status helmholtz6_autotune(h6_plan plan, const char* cache_path, void* hip_stream);
+
 /* Per-kernel timing: when enabled, the library records HIP events around
  * every kernel (or fused group of kernels) it launches on the caller's stream
  * and accumulates, per kernel class, the durations, the launch count and the

@@ -3,8 +3,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <new>
 
 #include "h6_internal.h"
@@ -252,6 +255,9 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
 
 void free_plan(h6_plan P) {
   if (!P) return;
+  release_graphs(P);
+  if (P->gstream) (void)hipStreamDestroy(P->gstream);
+  if (P->ev_order) (void)hipEventDestroy(P->ev_order);
   for (auto& a : P->ax) (void)hipFree(a.rader_mem);
   (void)hipFree(P->d_stencil);
   (void)hipFree(P->d_lambda_x);
@@ -465,6 +471,104 @@ h6_status spectrum_bounds(h6_plan P) {
   return H6_OK;
 }
 
+// Autotuner: time the kernel variants on the plan's grid and keep the fastest.
+h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
+  char devname[256] = "unknown";
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      std::snprintf(devname, sizeof devname, "%s", prop.gcnArchName);
+  }
+  char key[512];
+  std::snprintf(key, sizeof key, "h6tune1 %s %d %d %d %d", devname, P->dims[0], P->dims[1], P->dims[2],
+                P->p.precision);
+  const bool can_x = P->ax[0].rader_mem != nullptr, can_y = P->ax[1].rader_mem != nullptr;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[600];
+      while (std::fgets(line, sizeof line, f)) {
+        int tz = 0, xf = 0, yf = 0;
+        const size_t kl = std::strlen(key);
+        if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
+            std::sscanf(line + kl, " tz=%d xfast=%d yfast=%d", &tz, &xf, &yf) == 3 &&
+            (tz == 8 || tz == 16 || tz == 32)) {
+          std::fclose(f);
+          P->stencil_tz = tz;
+          P->ax[0].fast = can_x && xf;
+          P->ax[1].fast = can_y && yf;
+          return H6_OK;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  void *a = nullptr, *b = nullptr;
+  const size_t vb = P->N * sizeof(double2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&a, vb) != hipSuccess || hipMalloc(&b, vb) != hipSuccess ||
+      hipMemsetAsync(a, 0, vb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    P->last_error = "autotune: workspace allocation failed";
+    return H6_ERR_ALLOC;
+  }
+  const bool timing = P->timing.enabled;
+  P->timing.enabled = false;
+  auto time_it = [&](auto&& fn) -> double {     // best of 3 after a warm-up
+    fn();
+    double best = 1e30;
+    for (int r = 0; r < 3; ++r) {
+      (void)hipEventRecord(e0, s);
+      fn();
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        best = std::min(best, double(ms));
+    }
+    return best;
+  };
+  const double2* x = static_cast<const double2*>(a);
+  double2* y = static_cast<double2*>(b);
+  int best_tz = 16;
+  double best_ms = 1e30;
+  for (int tz : {8, 16, 32}) {
+    P->stencil_tz = tz;
+    const double ms = time_it([&] { (void)launch_stencil(P, x, y, nullptr, nullptr, nullptr, s); });
+    if (ms < best_ms) { best_ms = ms; best_tz = tz; }
+  }
+  P->stencil_tz = best_tz;
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!(ax == 0 ? can_x : can_y)) continue;
+    P->ax[ax].fast = 1;
+    const double fast = time_it([&] { (void)launch_pinv(P, x, y, s); });
+    P->ax[ax].fast = 0;
+    const double dense = time_it([&] { (void)launch_pinv(P, x, y, s); });
+    P->ax[ax].fast = fast <= dense ? 1 : 0;
+  }
+  P->timing.enabled = timing;
+  const hipError_t err = hipStreamSynchronize(s);
+  cleanup();
+  if (err != hipSuccess) {
+    P->last_error = std::string("autotune: ") + hipGetErrorString(err);
+    return H6_ERR_HIP;
+  }
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s tz=%d xfast=%d yfast=%d\n", key, P->stencil_tz, int(P->ax[0].fast),
+                   int(P->ax[1].fast));
+      std::fclose(f);
+    }
+  }
+  return H6_OK;
+}
+
 }  // namespace h6
 
 extern "C" {
@@ -596,6 +700,64 @@ const char* helmholtz6_status_string(h6_status s) {
     case H6_ERR_SINGULAR: return "preconditioner singular (k^2 on the 7-point spectrum)";
   }
   return "unknown status";
+}
+
+h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* const* U,
+                                 h6_solve_info* infos, h6_status* statuses, int count, int nstreams) {
+  if (count < 0 || nstreams < 1 || nstreams > 16 || (count > 0 && (!plans || !F || !U || !infos || !statuses)))
+    return H6_ERR_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return H6_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return H6_ERR_ARG;
+  }
+  if (count == 0) return H6_OK;
+  // longest first: unknowns times an iteration estimate growing with kh
+  std::vector<int> order(count);
+  std::vector<double> cost(count);
+  for (int i = 0; i < count; ++i) {
+    const double kh = std::abs(plans[i]->k) * plans[i]->p.h;
+    cost[i] = double(plans[i]->N) * (1.0 + 40.0 * kh * kh);
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return H6_ERR_HIP;
+  const int nt = std::min(nstreams, count);
+  std::vector<hipStream_t> streams(nt, nullptr);
+  for (int t = 0; t < nt; ++t)
+    if (hipStreamCreateWithFlags(&streams[t], hipStreamNonBlocking) != hipSuccess) {
+      for (int u = 0; u < t; ++u) (void)hipStreamDestroy(streams[u]);
+      return H6_ERR_HIP;
+    }
+  std::atomic<int> next{0};
+  auto worker = [&](int t) {
+    (void)hipSetDevice(dev);
+    for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
+      const int i = order[q];
+      statuses[i] = helmholtz6_solve(plans[i], F[i], U[i], &infos[i], streams[t]);
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int t = 1; t < nt; ++t) threads.emplace_back(worker, t);
+  worker(0);
+  for (auto& th : threads) th.join();
+  for (auto s : streams) (void)hipStreamDestroy(s);
+  for (int i = 0; i < count; ++i)
+    if (statuses[i] < 0) return statuses[i];
+  return H6_OK;
+}
+
+h6_status helmholtz6_set_graphs(h6_plan P, int enable) {
+  if (!P) return H6_ERR_ARG;
+  P->use_graphs = enable != 0;
+  if (!enable) release_graphs(P);
+  return H6_OK;
+}
+
+h6_status helmholtz6_autotune(h6_plan P, const char* cache_path, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  return autotune(P, cache_path, static_cast<hipStream_t>(hip_stream));
 }
 
 h6_status helmholtz6_spectrum_bounds(h6_plan P, double* lo, double* hi) {

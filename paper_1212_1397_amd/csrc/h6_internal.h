@@ -66,6 +66,16 @@ struct Timing {
   std::vector<Pending> pending;
 };
 
+// what a captured Arnoldi step depends on besides its index
+struct GraphKey {
+  void* V = nullptr;
+  void* Z = nullptr;
+  int m = 0, flex = 0, mixed = 0;
+  bool operator==(const GraphKey& o) const {
+    return V == o.V && Z == o.Z && m == o.m && flex == o.flex && mixed == o.mixed;
+  }
+};
+
 }  // namespace h6
 
 struct h6_plan_s {
@@ -102,6 +112,12 @@ struct h6_plan_s {
   double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
   struct h6_net_s* net = nullptr;              // learned correction for FGMRES (not owned)
+  bool use_graphs = false;                     // capture GMRES steps as HIP graphs
+  hipStream_t gstream = nullptr;               // plan-owned stream of graph-mode solves
+  hipEvent_t ev_order = nullptr;               // orders gstream after the caller's stream
+  std::vector<hipGraphExec_t> step_graphs;     // one per step index
+  h6::GraphKey graph_key;
+  int stencil_tz = 16;                         // autotuned stencil z-chunk (8, 16 or 32)
   bool spec_done = false;                      // exact spectrum bounds of A A_p^{-1} (Dirichlet)
   h6_status spec_status = H6_OK;
   double spec_lo = 0.0, spec_hi = 0.0;
@@ -197,6 +213,9 @@ h6_status spectrum_bounds(h6_plan P);
 // e = c1 e + c2 t; U += e (Chebyshev step)
 hipError_t launch_cheb_update(double2* e, const double2* t, double2* U, double c1, double c2, size_t n,
                               hipStream_t s);
+
+void release_graphs(h6_plan P);
+h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s);
 
 // solver
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s);

@@ -298,18 +298,16 @@ hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hi
 // components x 2048 blocks).  The same grid serves every instance: more
 // blocks did not help the narrow ones.
 int reduction_blocks() {
-  static int blocks = 0;
-  if (!blocks) {
-    int dev = 0, cus = 0, per = 0;
-    blocks = kRedBlocks;
+  static const int blocks = [] {     // initialised once, thread-safe
+    int dev = 0, cus = 0, per = 0, b = kRedBlocks;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, block_dots_kernel<kDotChunk>, kThreads, 0) ==
             hipSuccess &&
         cus > 0 && per > 0)
-      blocks = cus * per;
-    if (blocks > kRedBlocks * 2) blocks = kRedBlocks * 2;
-  }
+      b = cus * per;
+    return b > kRedBlocks * 2 ? kRedBlocks * 2 : b;
+  }();
   return blocks;
 }
 

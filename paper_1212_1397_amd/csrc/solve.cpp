@@ -167,6 +167,16 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
   const double kh = P->k.real() * P->p.h;      // feature of the learned correction
   P->learned_steps = 0;
+  // step graphs: valid while the workspace and the step shape are unchanged
+  const bool graphs = P->use_graphs && !P->timing.enabled && !P->net;
+  if (graphs) {
+    const GraphKey key{P->V, P->Z, m, int(flex), int(mixed)};
+    if (!(key == P->graph_key) || int(P->step_graphs.size()) < m) {
+      release_graphs(P);
+      P->graph_key = key;
+      P->step_graphs.assign(m, nullptr);
+    }
+  }
   // preconditioner passes of step j (z_j = A_p^{-1} q~_j)
   auto pinv = [&](int j, int part) -> hipError_t {
     const double2* qj = P->V + size_t(j) * N;
@@ -197,51 +207,82 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
         if (mixed) return launch_stencil_f32in(P, static_cast<const float2*>(z), out, c.s);
         return launch_stencil(P, static_cast<const double2*>(z), out, nullptr, nullptr, nullptr, c.s);
       };
-      H6_TRY_HIP(pinv(j, first_done ? PINV_REST : PINV_ALL));
-      if (j == 0 && flex && P->net) {
-        // judge of the correction for this cycle: ||q - A z|| with and without it
-        const size_t zb = N * (mixed ? sizeof(float2) : sizeof(double2));
-        H6_TRY_HIP(apply_A_z(zj, w));
-        H6_TRY_HIP(launch_diff_norm2(qj, w, N, P->partials, c.dev + kJudge, c.s));
-        H6_TRY_HIP(hipMemcpyAsync(P->t, zj, zb, hipMemcpyDeviceToDevice, c.s));
-        H6_TRY_HIP(net_apply_add(P->net, qj, kh, P->t, mixed, c.s));
-        H6_TRY_HIP(apply_A_z(P->t, P->r));
-        H6_TRY_HIP(launch_diff_norm2(qj, P->r, N, P->partials, c.dev + kJudge + 1, c.s));
-        st = fetch(c, kJudge, 2);
-        if (st != H6_OK) return st;
-        use_net = c.host[kJudge + 1] <= c.host[kJudge];
-        if (use_net) {
-          H6_TRY_HIP(hipMemcpyAsync(zj, P->t, zb, hipMemcpyDeviceToDevice, c.s));
-          H6_TRY_HIP(hipMemcpyAsync(w, P->r, N * sizeof(double2), hipMemcpyDeviceToDevice, c.s));
+      // the device part of the step after z_j = A_p^{-1} q_j and w = A z_j:
+      // inner products, MGS coefficients, update with the Gram row, and the
+      // copies of h and |w~|^2 to the pinned mirror
+      auto orthogonalise = [&]() -> hipError_t {
+        hipError_t e;
+        hipEvent_t ev;
+        timing_begin(P, KC_MGS_DOTS, c.s, &ev);
+        if ((e = launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s)) != hipSuccess) return e;
+        // Gram entries of q_j beyond the kGramMax formed by the last update pass
+        if (j > kGramMax &&
+            (e = launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, P->V + size_t(j) * N, N,
+                                   P->partials, c.dev + kGram2, c.s)) != hipSuccess)
+          return e;
+        timing_end(P, KC_MGS_DOTS, c.s, ev,
+                   double(N) * sizeof(double2) * ((j + 2) + (j > kGramMax ? j - kGramMax + 1 : 0)));
+        if ((e = launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu, P->d_gram,
+                                 P->gram_dim, dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s)) !=
+            hipSuccess)
+          return e;
+        timing_begin(P, KC_MGS_UPDATE, c.s, &ev);
+        if ((e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s)) != hipSuccess)
+          return e;
+        timing_end(P, KC_MGS_UPDATE, c.s, ev, double(N) * sizeof(double2) * (j + 3));
+        if ((e = hipMemcpyAsync(c.host + kHcol, c.dev + kHcol, sizeof(double) * 2 * (j + 1),
+                                hipMemcpyDeviceToHost, c.s)) != hipSuccess)
+          return e;
+        return hipMemcpyAsync(c.host + kNorm, c.dev + kNorm, sizeof(double), hipMemcpyDeviceToHost, c.s);
+      };
+      if (graphs) {
+        // the whole step is one captured graph per step index, replayed
+        hipGraphExec_t& g = P->step_graphs[j];
+        if (!g) {
+          hipGraph_t graph = nullptr;
+          H6_TRY_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeRelaxed));
+          hipError_t e = pinv(j, PINV_ALL);
+          if (e == hipSuccess) e = apply_A_z(zj, w);
+          if (e == hipSuccess) e = orthogonalise();
+          const hipError_t e2 = hipStreamEndCapture(c.s, &graph);
+          if (e == hipSuccess) e = e2;
+          if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+          if (graph) (void)hipGraphDestroy(graph);
+          H6_TRY_HIP(e);
         }
+        H6_TRY_HIP(hipGraphLaunch(g, c.s));
+        H6_TRY_HIP(hipEventRecord(P->ev_sync, c.s));
+        info->iters += 1;
       } else {
-        if (use_net) H6_TRY_HIP(net_apply_add(P->net, qj, kh, zj, mixed, c.s));
-        H6_TRY_HIP(apply_A_z(zj, w));
+        H6_TRY_HIP(pinv(j, first_done ? PINV_REST : PINV_ALL));
+        if (j == 0 && flex && P->net) {
+          // judge of the correction for this cycle: ||q - A z|| with and without it
+          const size_t zb = N * (mixed ? sizeof(float2) : sizeof(double2));
+          H6_TRY_HIP(apply_A_z(zj, w));
+          H6_TRY_HIP(launch_diff_norm2(qj, w, N, P->partials, c.dev + kJudge, c.s));
+          H6_TRY_HIP(hipMemcpyAsync(P->t, zj, zb, hipMemcpyDeviceToDevice, c.s));
+          H6_TRY_HIP(net_apply_add(P->net, qj, kh, P->t, mixed, c.s));
+          H6_TRY_HIP(apply_A_z(P->t, P->r));
+          H6_TRY_HIP(launch_diff_norm2(qj, P->r, N, P->partials, c.dev + kJudge + 1, c.s));
+          st = fetch(c, kJudge, 2);
+          if (st != H6_OK) return st;
+          use_net = c.host[kJudge + 1] <= c.host[kJudge];
+          if (use_net) {
+            H6_TRY_HIP(hipMemcpyAsync(zj, P->t, zb, hipMemcpyDeviceToDevice, c.s));
+            H6_TRY_HIP(hipMemcpyAsync(w, P->r, N * sizeof(double2), hipMemcpyDeviceToDevice, c.s));
+          }
+        } else {
+          if (use_net) H6_TRY_HIP(net_apply_add(P->net, qj, kh, zj, mixed, c.s));
+          H6_TRY_HIP(apply_A_z(zj, w));
+        }
+        if (use_net) P->learned_steps += 1;
+        info->iters += 1;
+        H6_TRY_HIP(orthogonalise());
+        H6_TRY_HIP(hipEventRecord(P->ev_sync, c.s));
+        // meanwhile the device starts on step j + 1
+        first_done = j + 1 < m && info->iters < info->maxit;
+        if (first_done) H6_TRY_HIP(pinv(j + 1, PINV_FIRST));
       }
-      if (use_net) P->learned_steps += 1;
-      info->iters += 1;
-      hipEvent_t ev;
-      timing_begin(P, KC_MGS_DOTS, c.s, &ev);
-      H6_TRY_HIP(launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s));
-      // Gram entries of q_j beyond the kGramMax formed by the last update pass
-      if (j > kGramMax)
-        H6_TRY_HIP(launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, P->V + size_t(j) * N,
-                                     N, P->partials, c.dev + kGram2, c.s));
-      timing_end(P, KC_MGS_DOTS, c.s, ev,
-                 double(N) * sizeof(double2) * ((j + 2) + (j > kGramMax ? j - kGramMax + 1 : 0)));
-      H6_TRY_HIP(launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu,
-                                 P->d_gram, P->gram_dim, dhcol, reinterpret_cast<double2*>(c.dev + kCoef),
-                                 c.s));
-      timing_begin(P, KC_MGS_UPDATE, c.s, &ev);
-      H6_TRY_HIP(launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s));
-      timing_end(P, KC_MGS_UPDATE, c.s, ev, double(N) * sizeof(double2) * (j + 3));
-      // h and |w~|^2 to the host; meanwhile the device starts on step j + 1
-      H6_TRY_HIP(hipMemcpyAsync(c.host + kHcol, c.dev + kHcol, sizeof(double) * 2 * (j + 1),
-                                hipMemcpyDeviceToHost, c.s));
-      st = fetch_async(c, kNorm, 1);
-      if (st != H6_OK) return st;
-      first_done = j + 1 < m && info->iters < info->maxit;
-      if (first_done) H6_TRY_HIP(pinv(j + 1, PINV_FIRST));
       st = wait(c);
       if (st != H6_OK) return st;
       nu[j + 1] = std::sqrt(std::max(c.host[kNorm], 0.0));
@@ -390,9 +431,26 @@ h6_status chebyshev(Ctx& c, const double2* F, double2* U, h6_solve_info* info, d
 
 }  // namespace
 
+void release_graphs(h6_plan P) {
+  for (auto& g : P->step_graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  P->step_graphs.clear();
+  P->graph_key = GraphKey{};
+}
+
 h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info, hipStream_t s) {
   h6_status st = ensure(P, info->method, info->restart);
   if (st != H6_OK) return st;
+  const bool krylov = info->method == H6_GMRES || info->method == H6_FGMRES;
+  if (P->use_graphs && krylov && !P->timing.enabled && !P->net) {
+    // graph mode runs on the plan's own stream (capturable), after the
+    // caller's pending work
+    if (!P->gstream) H6_TRY_HIP(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+    if (!P->ev_order) H6_TRY_HIP(hipEventCreateWithFlags(&P->ev_order, hipEventDisableTiming));
+    H6_TRY_HIP(hipEventRecord(P->ev_order, s));
+    H6_TRY_HIP(hipStreamWaitEvent(P->gstream, P->ev_order, 0));
+    s = P->gstream;
+  }
   Ctx c{P, s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
   double normF2 = 0.0;
   st = norm2(c, F, &normF2);

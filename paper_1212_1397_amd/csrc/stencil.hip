@@ -9,7 +9,7 @@
 // faces through zeros.
 //
 // Launch shape (2.5D march): a workgroup of 256 threads owns a 64 x 8 x-y tile
-// and a chunk of up to kTZ z-planes.  It streams the planes of its chunk plus
+// and a chunk of up to kTZ z-planes (8, 16 or 32: the plan's autotuned depth).  It streams the planes of its chunk plus
 // one halo plane on each side through a double-buffered LDS tile of 66 x 10
 // complex values, computes S_p once per plane, and scatters it into the two
 // running row accumulators.  Each plane is read from HBM once per tile
@@ -21,7 +21,7 @@
 namespace h6 {
 namespace {
 
-constexpr int kTX = 64, kTY = 8, kTZ = 16;
+constexpr int kTX = 64, kTY = 8;      // x-y tile; the z chunk (8, 16 or 32 planes) is a template parameter
 constexpr int kLX = kTX + 2, kLY = kTY + 2;
 constexpr int kThreads = 256;
 constexpr int kLoads = (kLX * kLY + kThreads - 1) / kThreads;   // 3
@@ -45,7 +45,7 @@ __device__ __forceinline__ void apply_w(double2& acc, const W9& w, const S3& s) 
 
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
-template <bool RESID, typename Tin, typename Tout>
+template <bool RESID, typename Tin, typename Tout, int kTZ>
 __global__ __launch_bounds__(kThreads) void stencil_kernel(
     const Tin* __restrict__ x, Tout* __restrict__ y, const double2* __restrict__ F,
     double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
@@ -195,9 +195,9 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 
 }  // namespace
 
-template <typename Tin, typename Tout>
-hipError_t stencil_impl(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
-                        int* nparts, hipStream_t s) {
+template <typename Tin, typename Tout, int kTZ>
+hipError_t stencil_launch(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
+                          int* nparts, hipStream_t s) {
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
   const int nwg = ntx * nty * ntz;
@@ -206,17 +206,26 @@ hipError_t stencil_impl(h6_plan P, const Tin* x, Tout* y, const double2* F, doub
   hipEvent_t ev;
   timing_begin(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, &ev);
   if (resid)
-    hipLaunchKernelGGL((stencil_kernel<true, Tin, Tout>), dim3(nwg), dim3(kThreads), 0, s, x, y, F,
+    hipLaunchKernelGGL((stencil_kernel<true, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y, F,
                        partials, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
                        P->zhi_closure, ntx, nty, nwg);
   else
-    hipLaunchKernelGGL((stencil_kernel<false, Tin, Tout>), dim3(nwg), dim3(kThreads), 0, s, x, y,
+    hipLaunchKernelGGL((stencil_kernel<false, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y,
                        nullptr, nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
                        P->zlo_closure, P->zhi_closure, ntx, nty, nwg);
   timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev,
              double(P->N) * (sizeof(Tin) + sizeof(Tout) + (resid ? sizeof(double2) : 0)));
   if (nparts) *nparts = nwg;
   return hipGetLastError();
+}
+
+// the plan's z-chunk depth (set by the autotuner; 16 by default)
+template <typename Tin, typename Tout>
+hipError_t stencil_impl(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
+                        int* nparts, hipStream_t s) {
+  if (P->stencil_tz == 8) return stencil_launch<Tin, Tout, 8>(P, x, y, F, partials, nparts, s);
+  if (P->stencil_tz == 32) return stencil_launch<Tin, Tout, 32>(P, x, y, F, partials, nparts, s);
+  return stencil_launch<Tin, Tout, 16>(P, x, y, F, partials, nparts, s);
 }
 
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,

@@ -27,7 +27,8 @@ KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z",
 EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
-            "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order")
+            "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
+            "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
                 "helmholtz6_learned_steps", "h6net_destroy")
@@ -76,6 +77,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_spectrum_bounds.restype = ctypes.c_int
     lib.helmholtz6_psi_order.argtypes = [ctypes.c_double] * 5
     lib.helmholtz6_psi_order.restype = ctypes.c_double
+    lib.helmholtz6_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(H6SolveInfo), ctypes.POINTER(ip), ip, ip]
+    lib.helmholtz6_solve_batch.restype = ctypes.c_int
+    lib.helmholtz6_set_graphs.argtypes = [vp, ip]
+    lib.helmholtz6_set_graphs.restype = ctypes.c_int
+    lib.helmholtz6_autotune.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.helmholtz6_autotune.restype = ctypes.c_int
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
                  "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
@@ -197,6 +205,15 @@ class Plan:
         status = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}[st]
         return U, dict(status=status, iters=info.iters, rel_resid=info.rel_resid,
                        history=list(hist[:info.history_len]))
+
+    def set_graphs(self, enable: bool = True):
+        """Capture GMRES / FGMRES Arnoldi steps as HIP graphs and replay them."""
+        self._check(_lib.helmholtz6_set_graphs(self._plan, int(enable)))
+
+    def autotune(self, cache_path=None, stream=None):
+        """Time the kernel variants on this grid and keep the fastest (optionally cached)."""
+        self._check(_lib.helmholtz6_autotune(self._plan, cache_path.encode() if cache_path else None,
+                                             _stream_handle(stream)))
 
     def spectrum_bounds(self):
         """(lo, hi): exact extreme eigenvalues of A A_p^{-1} (all-Dirichlet, real k)."""
@@ -338,6 +355,33 @@ def unpack_net_params(flat) -> dict:
         out[name] = (W, b)
         o += nw + cout
     return out
+
+
+def solve_batch(plans, Fs, Us, method="fgmres", restart=30, maxit=1000, tol=1e-8, nstreams=4,
+                history=0):
+    """Solve plans[i] x = Fs[i] into Us[i] (initial guesses, overwritten) concurrently on
+    `nstreams` library streams, longest first.  Returns a list of info dicts."""
+    n = len(plans)
+    if not (len(Fs) == len(Us) == n):
+        raise ValueError("plans, Fs and Us must have the same length")
+    P = (ctypes.c_void_p * n)(*[p._plan.value for p in plans])
+    Fp = (ctypes.c_void_p * n)(*[p._vec(F, "F").value for p, F in zip(plans, Fs)])
+    Up = (ctypes.c_void_p * n)(*[p._vec(U, "U").value for p, U in zip(plans, Us)])
+    hists = [(ctypes.c_double * max(history, 1))() for _ in range(n)]
+    infos = (H6SolveInfo * n)()
+    for i in range(n):
+        infos[i] = H6SolveInfo(METHODS[method], int(restart), int(maxit), float(tol), 0, 0.0,
+                               ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double)), int(history))
+    sts = (ctypes.c_int * n)()
+    torch.cuda.synchronize()              # inputs ready before the library streams start
+    st = _lib.helmholtz6_solve_batch(P, Fp, Up, infos, sts, n, int(nstreams))
+    if st < 0:
+        msgs = [plans[i]._plan and _lib.helmholtz6_last_error(plans[i]._plan).decode()
+                for i in range(n) if sts[i] < 0]
+        raise H6Error(st, "; ".join(m for m in msgs if m) or "batch solve failed")
+    names = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}
+    return [dict(status=names[sts[i]], iters=infos[i].iters, rel_resid=infos[i].rel_resid,
+                 history=list(hists[i][:infos[i].history_len])) for i in range(n)]
 
 
 def psi_order(r1_h: float, r2_h: float, r1_gh: float, r2_gh: float, gamma: float) -> float:

@@ -87,3 +87,35 @@ def init_net_params(layers, seed: int):
             W *= 1e-2
         out[name] = (W, np.zeros(cout))
     return out
+
+
+@dataclass(frozen=True)
+class BatchInstance:
+    n: int
+    k: complex
+    bc: str
+    centres: np.ndarray
+    amps: np.ndarray
+    sigma: float
+
+    @property
+    def h(self) -> float:
+        return 1.0 / (self.n + 1)
+
+
+def batch_workload(count: int = 96, seed: int = 4, sizes=(48, 64, 96, 128, 160)):
+    """The many-solve workload: `count` independent problems with n drawn
+    uniformly from `sizes`, k = kr (1 + 0.01 i) with kr ~ U[10, 60], faces
+    all Dirichlet or x Dirichlet / y Neumann / z Sommerfeld (equally likely),
+    one Gaussian source of width 4h and amplitude 1 at a seeded centre in
+    [0.25, 0.75]^3."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(sizes))
+        kr = float(rng.uniform(10.0, 60.0))
+        bc = "DDDDDD" if rng.integers(2) == 0 else "DDNNSS"
+        centre = rng.uniform(0.25, 0.75, size=(1, 3))
+        h = 1.0 / (n + 1)
+        out.append(BatchInstance(n, kr * (1 + 0.01j), bc, centre, np.ones(1, dtype=np.complex128), 4.0 * h))
+    return out

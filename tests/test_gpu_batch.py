@@ -1,0 +1,88 @@
+"""Throughput form: concurrent batched solves, graph-captured Arnoldi steps
+and the autotuner give the same results as plain sequential solves."""
+import os
+
+import pytest
+import torch
+
+from paper_1212_1397_amd.workloads import WORKLOADS, batch_workload, gaussian_sources
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h6():
+    from paper_1212_1397_amd import helmholtz6
+    return helmholtz6
+
+
+def make(h6, inst):
+    plan = h6.Plan(inst.n, inst.h, inst.k, inst.bc, precision="mixed")
+    F = plan.rhs_gaussians(inst.centres, inst.amps, inst.sigma)
+    return plan, F
+
+
+def test_batch_equals_sequential(h6):
+    insts = batch_workload(12, seed=11, sizes=(48, 64))
+    plans, Fs = zip(*[make(h6, i) for i in insts])
+    seq = []
+    for p, F in zip(plans, Fs):
+        U, info = p.solve(F, method="fgmres", restart=30, tol=1e-8, maxit=400)
+        seq.append((U.clone(), info))
+    Us = [torch.zeros_like(F) for F in Fs]
+    infos = h6.solve_batch(list(plans), list(Fs), Us, method="fgmres", restart=30, tol=1e-8, maxit=400,
+                           nstreams=4)
+    for (U0, i0), U1, i1 in zip(seq, Us, infos):
+        assert i1["status"] == i0["status"] and i1["iters"] == i0["iters"]
+        assert torch.equal(U0, U1)
+    print("iterations:", [i["iters"] for i in infos], flush=True)
+
+
+@pytest.mark.parametrize("precision,method", [("mixed", "fgmres"), ("fp64", "gmres")])
+def test_graph_replays_equal_eager(h6, precision, method):
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=precision)
+    F = plan.rhs_gaussians(*gaussian_sources(w))
+    U0, i0 = plan.solve(F, method=method, restart=w.restart, tol=w.tol, maxit=300)
+    plan.set_graphs(True)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()          # eager work between replays
+        U1, i1 = plan.solve(F, method=method, restart=w.restart, tol=w.tol, maxit=300)
+        torch.cuda.synchronize()
+        assert i1["iters"] == i0["iters"] and i1["history"] == i0["history"], rep
+        assert torch.equal(U1, U0), rep
+        del junk
+    plan.set_graphs(False)
+    U2, _ = plan.solve(F, method=method, restart=w.restart, tol=w.tol, maxit=300)
+    assert torch.equal(U2, U0)
+
+
+def test_graph_restart_cycles(h6):
+    """A short restart length exercises every step graph more than once."""
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    F = plan.rhs_gaussians(*gaussian_sources(w))
+    U0, i0 = plan.solve(F, method="fgmres", restart=4, tol=w.tol, maxit=300)
+    plan.set_graphs(True)
+    U1, i1 = plan.solve(F, method="fgmres", restart=4, tol=w.tol, maxit=300)
+    assert i1["iters"] == i0["iters"] and torch.equal(U1, U0)
+
+
+def test_autotune_keeps_results_and_caches(h6, tmp_path):
+    w = WORKLOADS["dns-256"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda")
+    y0 = plan.apply_A(x)
+    z0 = plan.apply_Pinv(x)
+    cache = os.path.join(tmp_path, "tune.txt")
+    plan.autotune(cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("h6tune1 ")
+    print(lines[0], flush=True)
+    assert torch.equal(plan.apply_A(x), y0)      # the stencil variants differ only in the launch shape
+    z1 = plan.apply_Pinv(x)
+    assert float(torch.linalg.norm(z1 - z0) / torch.linalg.norm(z0)) < 1e-5   # complex64 transforms
+    plan2 = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    plan2.autotune(cache)                          # read from the cache, not re-timed
+    assert len(open(cache).read().splitlines()) == 1
+    assert torch.equal(plan2.apply_A(x), y0)
