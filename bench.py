@@ -23,7 +23,11 @@ synchronisations.  The process prints one JSON line:
                        sample of the same problem (two iterations), scaled to
                        the iteration count of the FP64 GPU solve,
   extra                the other methods (plain FP64 GMRES and SKS, mixed
-                       FGMRES) timed once each, and the per-kernel breakdown.
+                       FGMRES) timed once each, the per-kernel breakdown, the
+                       learned correction in mixed FGMRES(30) (committed
+                       weights) with its network's matrix-core throughput, and
+                       the 96-problem batch (batched + graphs + autotuned vs
+                       sequential plain solves).
 """
 from __future__ import annotations
 
@@ -118,6 +122,8 @@ def main():
     ap.add_argument("--method", default="mixed-sks", choices=sorted(METHODS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before the timed region, copy one vector with a plain device copy "
                          "(the reference for scaling hardware byte counters)")
@@ -222,6 +228,25 @@ def main():
             extra["speedup_vs_fp64_gmres"] = round(others["fp64-gmres"]["s"] / dt, 3)
         if fp64_name in others:
             extra["speedup_vs_fp64_same_solver"] = round(others[fp64_name]["s"] / dt, 3)
+
+    if not args.no_extra and not args.no_learned and w.name == "dns-256":
+        import numpy as np
+        from paper_1212_1397_amd import learned
+        wpath = os.path.join(ROOT, "paper_1212_1397_amd", "data", "net_dns128.npz")
+        if os.path.exists(wpath):
+            d = np.load(wpath)
+            res = learned.solve_compare(w, d["params"], log=lambda m: None)
+            f_s, f_tf = learned.speed(plan.dims, reps=3)
+            res.update({"heldout_error_ratio": float(d["heldout_ratio"]),
+                        "forward_ms": round(1e3 * f_s, 3),
+                        "roofline": {"bound": "mfma", "kernel": "conv (BF16 MFMA, whole forward pass)",
+                                     "achieved": round(f_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                                     "frac": round(f_tf / 2500.0, 4),
+                                     "flops_per_forward": learned.net_flops(plan.dims)}})
+            extra["learned_fgmres"] = res
+    if not args.no_extra and not args.no_batch:
+        from paper_1212_1397_amd import batch
+        extra["batch"] = batch.run()
 
     cpu = None
     if not args.no_cpu_baseline:
