@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel variants")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before the timed region, copy one vector with a plain device copy "
                          "(the reference for scaling hardware byte counters)")
@@ -144,6 +145,8 @@ def main():
     def plan_for(prec):
         if prec not in plans:
             plans[prec] = h6.Plan(w.n, w.h, w.k, w.bc, precision=prec)
+            if not args.no_tune:
+                plans[prec].autotune()         # kernel variants for this grid (set-up, untimed)
         return plans[prec]
 
     prec, meth = METHODS[args.method]

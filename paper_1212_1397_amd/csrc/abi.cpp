@@ -347,6 +347,12 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
     free_plan(P);
     return H6_ERR_SINGULAR;
   }
+  for (int l = 0; l < P->dims[2]; ++l)      // the device z solver takes the off-diagonals as real
+    if (sub[l].imag() != 0.0 || sup[l].imag() != 0.0) {
+      err = "internal: complex z off-diagonal";
+      free_plan(P);
+      return H6_ERR_ARG;
+    }
   std::vector<double2> tri(3 * P->dims[2]);
   for (int l = 0; l < P->dims[2]; ++l) {
     tri[l] = make_double2(sub[l].real(), sub[l].imag());

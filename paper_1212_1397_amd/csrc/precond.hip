@@ -240,6 +240,9 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
   __syncthreads();
   const T2 shift = mk<R>(R(kap_re + lxi + lyj), R(kap_im));
 
+  // The off-diagonals of T_z are real (1 inside, 0 or 2 on the end rows):
+  // a and c scale complex values by real factors.
+  auto scl = [](T2 v, R f) { return mk<R>(v.x * f, v.y * f); };
   // local pass: c' from the stored start value, inverse pivots, and the
   // affine map d'_{last} = A d'_{r0-1} + B
   T2 cprev = cst, A = one, B = zero;
@@ -247,12 +250,13 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
       const int r = r0 + u;
-      const T2 a = tz[r], b = cadd<R>(tz[nz + r], shift), c = tz[2 * nz + r];
-      ip[u] = crecip<R>(csub<R>(b, cmulr<R>(a, cprev)));
-      const T2 al = cmulr<R>(mk<R>(-a.x, -a.y), ip[u]);
+      const R a = tz[r].x, c = tz[2 * nz + r].x;
+      const T2 b = cadd<R>(tz[nz + r], shift);
+      ip[u] = crecip<R>(csub<R>(b, scl(cprev, a)));
+      const T2 al = scl(ip[u], -a);
       A = cmulr<R>(al, A);
       B = cadd<R>(cmulr<R>(al, B), cmulr<R>(d[u], ip[u]));
-      cprev = cmulr<R>(c, ip[u]);
+      cprev = scl(ip[u], c);
     } else {
       ip[u] = zero;
     }
@@ -266,8 +270,8 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
-      const T2 a = tz[r0 + u];
-      d[u] = cmulr<R>(csub<R>(d[u], cmulr<R>(a, dprev)), ip[u]);
+      const R a = tz[r0 + u].x;
+      d[u] = cmulr<R>(csub<R>(d[u], scl(dprev, a)), ip[u]);
       dprev = d[u];
     }
   }
@@ -275,8 +279,7 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      const T2 c = tz[2 * nz + r0 + u];
-      const T2 ncp = cmulr<R>(mk<R>(-c.x, -c.y), ip[u]);      // -c'_u
+      const T2 ncp = scl(ip[u], -tz[2 * nz + r0 + u].x);     // -c'_u
       D = cadd<R>(d[u], cmulr<R>(ncp, D));
       C = cmulr<R>(ncp, C);
     }
@@ -290,8 +293,7 @@ __global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      const T2 c = tz[2 * nz + r0 + u];
-      x = csub<R>(d[u], cmulr<R>(cmulr<R>(c, ip[u]), x));
+      x = csub<R>(d[u], cmulr<R>(scl(ip[u], tz[2 * nz + r0 + u].x), x));
       if (active) out[mode + size_t(r0 + u) * stride] = x;
     }
   }
