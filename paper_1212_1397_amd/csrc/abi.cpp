@@ -142,8 +142,9 @@ bool factor_modes(h6_plan P, const std::vector<double>& lx, const std::vector<do
                   const std::vector<cplx>& sup, std::vector<cplx>& cstart, std::string& where) {
   const int L = P->dims[2];
   const size_t nmodes = lx.size() * ly.size();
-  const int S = (L + kZSegs - 1) / kZSegs;
-  cstart.assign(kZSegs * nmodes, cplx(0.0));
+  const int segs = z_segments(L, P->p.precision == H6_MIXED);
+  const int S = (L + segs - 1) / segs;
+  cstart.assign(size_t(segs) * nmodes, cplx(0.0));
   for (size_t j = 0; j < ly.size(); ++j)
     for (size_t i = 0; i < lx.size(); ++i) {
       const size_t mode = i + lx.size() * j;

@@ -95,7 +95,7 @@ struct h6_plan_s {
   double* d_trig_x = nullptr;       // sin, cos (pi t / M), t = 0..2M-1 (2 * 2M doubles)
   double* d_trig_y = nullptr;
   double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
-  void* d_cstart = nullptr;         // Thomas c' entering each z segment: [kZSegs][n'x n'y], complex
+  void* d_cstart = nullptr;         // Thomas c' entering each z segment: [z_segments(n'z)][n'x n'y], complex
                                     // (double2, or float2 in mixed plans)
 
   // preconditioner workspace (complex128 vectors, or complex64 in mixed plans)
@@ -133,8 +133,13 @@ constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
 constexpr int kMaxPartials = 1 << 20;
 constexpr int kScal = 4096;        // device scalar slots (double2)
 constexpr int kGramMax = 16;       // Gram row entries formed by launch_update_gram
-constexpr int kZSegs = 32;         // segments per z line in the partitioned z solver
+constexpr int kZSegs = 32;         // most segments per z line in the partitioned z solver
 constexpr int kMaxZ = kZSegs * 17; // largest n'z of the partitioned z solver
+// segments per z line: complex64 solves use 16 (32 modes per workgroup, 256-byte
+// row segments) up to n'z = 272; complex128 solves and longer lines use 32 (16
+// modes per workgroup, fewer registers per thread).  The segment-start table
+// is built for this count.
+inline int z_segments(int nz, bool f32) { return (f32 && nz <= 16 * 17) ? 16 : 32; }
 
 // Workgroup id remap for the 8 XCDs of the chip: the hardware hands out
 // consecutive workgroup ids round-robin over the XCDs (each with its own L2);

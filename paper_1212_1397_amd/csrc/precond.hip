@@ -160,7 +160,7 @@ __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename
 
 // Partitioned Gaussian elimination without pivoting (the Thomas algorithm
 // with its recurrences re-associated) on T_z + shift I, one transverse mode per
-// line.  A workgroup owns kTriLines consecutive modes (lanes) and splits every
+// line.  A workgroup owns kLanes consecutive modes (lanes) and splits every
 // z line into kSegs segments of S <= kSmax rows, one thread each, rows held in
 // registers.  Thomas' recurrences are
 //   c'_i = c_i / m_i,  m_i = b_i - a_i c'_{i-1}        (data independent),
@@ -171,8 +171,8 @@ __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename
 // check).  Each thread replays c' over its rows, composes the two affine maps
 // over its segment, and the segment maps are chained in order through LDS.
 // HBM traffic: one read and one write of the vector plus the small cstart table.
-constexpr int kSegs = kZSegs;      // 32 segments per line
-constexpr int kTriLines = 16;      // rows per segment: S <= kSmax (5, 9 or 17: n'z <= 544)
+// launch shapes: kLanes modes x kSegs segments = 512 threads; 32 x 16 up to
+// n'z = 272 (256-byte row segments), 16 x 32 above (n'z <= 544)
 
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T csub(typename C2<R>::T a, typename C2<R>::T b) {
@@ -199,22 +199,22 @@ __device__ __forceinline__ typename C2<R>::T crecip(typename C2<R>::T b) {
   return mk<R>(b.x * d, -b.y * d);
 }
 
-template <typename R, int kSmax>
-__global__ __launch_bounds__(kTriLines * kSegs) void tridiag_z_kernel(
+template <typename R, int kLanes, int kSegs, int kSmax>
+__global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
     const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
     const double2* __restrict__ tri, const typename C2<R>::T* __restrict__ cstart,
     const double* __restrict__ lx, const double* __restrict__ ly, double kap_re, double kap_im,
     int nx, int ny, int nz) {
   using T2 = typename C2<R>::T;
-  constexpr int kThr = kTriLines * kSegs;
+  constexpr int kThr = kLanes * kSegs;
   constexpr int kTabPer = (3 * kMaxZ + kThr - 1) / kThr;
-  __shared__ T2 sh[2][kSegs][kTriLines];
+  __shared__ T2 sh[2][kSegs][kLanes];
   __shared__ T2 tz[kTabPer * kThr];  // sub-, main and super-diagonal of T_z (main without the shift)
   const int tid = threadIdx.x;
-  const int lane = tid % kTriLines;
-  const int seg = tid / kTriLines;
+  const int lane = tid % kLanes;
+  const int seg = tid / kLanes;
   const int nmodes = nx * ny;
-  const int mode = blockIdx.x * kTriLines + lane;
+  const int mode = blockIdx.x * kLanes + lane;
   const bool active = mode < nmodes;
   const int mc = active ? mode : nmodes - 1;
   const int i = mc % nx, j = mc / nx;
@@ -340,18 +340,20 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
   {
-    const dim3 gt((nx * ny + kTriLines - 1) / kTriLines), bt(kTriLines * kSegs);
     const double kr = P->kappa.real(), ki = P->kappa.imag();
     const T2* cst = static_cast<const T2*>(P->d_cstart);
-    if (nz <= kSegs * 5)
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 5>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
+    auto go = [&](auto kern, int lanes) {
+      hipLaunchKernelGGL(kern, dim3((nx * ny + lanes - 1) / lanes), dim3(512), 0, s, w1, w0, P->d_tri, cst,
                          P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
-    else if (nz <= kSegs * 9)
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 9>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
-                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
-    else
-      hipLaunchKernelGGL((tridiag_z_kernel<R, 17>), gt, bt, 0, s, w1, w0, P->d_tri, cst,
-                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
+    };
+    if (z_segments(nz, sizeof(R) == 4) == 16) {
+      if (nz <= 16 * 5) go(tridiag_z_kernel<R, 32, 16, 5>, 32);
+      else if (nz <= 16 * 9) go(tridiag_z_kernel<R, 32, 16, 9>, 32);
+      else go(tridiag_z_kernel<R, 32, 16, 17>, 32);
+    } else {
+      if (nz <= 32 * 9) go(tridiag_z_kernel<R, 16, 32, 9>, 16);
+      else go(tridiag_z_kernel<R, 16, 32, 17>, 16);
+    }
   }
   timing_end(P, KC_TRIDIAG, s, ev, Nd * 2 * sizeof(T2));
   xform_y(true, w0, w1);
