@@ -44,6 +44,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1212_1397_amd", "csrc")
+# autotuner choices per device and grid (read back, so no variant is re-timed)
+TUNE_CACHE = os.path.join(ROOT, "paper_1212_1397_amd", "data", "autotune.txt")
 METHODS = {
     "mixed-fgmres": ("mixed", "fgmres"),
     "mixed-sks": ("mixed", "sks"),
@@ -146,7 +148,7 @@ def main():
         if prec not in plans:
             plans[prec] = h6.Plan(w.n, w.h, w.k, w.bc, precision=prec)
             if not args.no_tune:
-                plans[prec].autotune()         # kernel variants for this grid (set-up, untimed)
+                plans[prec].autotune(TUNE_CACHE)   # kernel variants for this grid (set-up, untimed)
         return plans[prec]
 
     prec, meth = METHODS[args.method]

@@ -42,10 +42,9 @@ def run(count: int = 96, streams: int = 4, graphs: bool = True, tune: bool = Tru
     # batched: autotuned tiles (one tuning per grid shape), graphs, concurrent streams
     if tune:
         import os
-        import tempfile
-        cache = os.path.join(tempfile.mkdtemp(prefix="h6tune"), "tune.txt")
+        cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "autotune.txt")
         for p in plans:
-            p.autotune(cache)         # timed once per grid shape and precision, then read back
+            p.autotune(cache)         # read back per grid shape and precision (timed once if absent)
     for p in plans:
         p.set_graphs(graphs)
     Us = [torch.zeros_like(F) for F in Fs]
