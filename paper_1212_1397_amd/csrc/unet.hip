@@ -2,8 +2,9 @@
 // BF16 activations and weights, FP32 accumulation on the matrix cores.
 //
 // Convolutions are implicit GEMMs with v_mfma_f32_16x16x16bf16_1k:
-//   forward / input gradient: rows = 16 voxels (flattened x-fastest index),
-//     columns = output channels, k = (tap, input channel);
+//   forward / input gradient: rows = voxels (flattened x-fastest index; a wave
+//     owns four 16-voxel tiles), columns = output channels, k = (tap, input
+//     channel), the tap's weights staged in LDS;
 //   weight gradient: rows = output channels, columns = input channels,
 //     k = voxels, one tap per workgroup, deterministic two-stage reduction.
 // Operand lane layout of the instruction (lane l, element e = 0..3):
@@ -46,59 +47,99 @@ struct View {           // channels-last BF16 view
 };
 
 constexpr int kConvWaves = 4;
+constexpr int kConvMT = 4;       // 16-voxel row tiles per wave: a workgroup owns 256 voxels
 
 // out[v][co] = act(b[co] + sum_{tap, ci} W[tap][co][ci] in[v + tap][ci]), CIN and
-// COUTP multiples of 16; writes co < cout (BF16 view, or FP32 [v][2] when f32out).
+// COUTP multiples of 16; writes co < cout (BF16 view, or FP32 [v][2] when out32).
+// The weights of one tap (COUTP x CIN) are staged in LDS, double-buffered over
+// the taps, and every B fragment read from LDS feeds kConvMT matrix
+// instructions (one per row tile of the wave); A fragments come from global
+// memory (L1/L2: each input voxel is read by 27 taps).
 template <int CIN, int COUTP>
 __global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(View in, const bf16* __restrict__ W,
                                                                const float* __restrict__ bias, View out,
                                                                float* __restrict__ out32, int cout,
                                                                int relu, Grid3 g) {
-  constexpr int NT = COUTP / 16;
-  const int l = threadIdx.x & 63;
-  const long long tile = (long long)blockIdx.x * kConvWaves + (threadIdx.x >> 6);
-  const long long P = g.P();
-  if (tile * 16 >= P) return;                 // no barriers in this kernel
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = kConvMT;
+  constexpr int RS = CIN + 4;                        // LDS row stride (bf16): fewer bank conflicts
+  constexpr int WN = COUTP * CIN;                    // weights of one tap
+  __shared__ __attribute__((aligned(16))) bf16 ws[2][COUTP * RS];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
   const int i = l & 15, kq = l >> 4;
-  const long long v = tile * 16 + i;
-  const bool vok = v < P;
-  const int x = int(v % g.X), y = int((v / g.X) % g.Y), z = int(v / ((long long)g.X * g.Y));
-  f4 acc[NT];
+  const long long P = g.P();
+  const long long v0 = ((long long)blockIdx.x * kConvWaves + wave) * (16 * MT);
+  int xs[MT], ys[MT], zs[MT];
+  bool vok[MT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MT; ++m) {
+    const long long v = v0 + 16 * m + i;
+    vok[m] = v < P;
+    const long long vc = vok[m] ? v : 0;
+    xs[m] = int(vc % g.X);
+    ys[m] = int((vc / g.X) % g.Y);
+    zs[m] = int(vc / ((long long)g.X * g.Y));
+  }
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+  auto stage = [&](int tap, int b) {
+    for (int idx = tid; idx < WN / 4; idx += 64 * kConvWaves) {
+      const int row = (4 * idx) / CIN, col = (4 * idx) % CIN;
+      *reinterpret_cast<s4*>(&ws[b][row * RS + col]) =
+          *reinterpret_cast<const s4*>(W + (size_t)tap * WN + 4 * idx);
+    }
+  };
+  stage(0, 0);
+  __syncthreads();
   for (int tap = 0; tap < 27; ++tap) {
+    const int b = tap & 1;
+    if (tap + 1 < 27) stage(tap + 1, b ^ 1);
     const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const bool ok = vok && x + dx >= 0 && x + dx < g.X && y + dy >= 0 && y + dy < g.Y && z + dz >= 0 &&
-                    z + dz < g.Z;
-    const long long nv = ok ? v + dx + (long long)g.X * (dy + (long long)g.Y * dz) : 0;
-    const bf16* src = in.p + nv * in.cs + in.coff + 4 * kq;
-    const bf16* wt = W + ((size_t)tap * COUTP + i) * CIN + 4 * kq;
+    const bf16* src[MT];
+    bool ok[MT];
 #pragma unroll
-    for (int kc = 0; kc < CIN / 16; ++kc) {
-      s4 a = *reinterpret_cast<const s4*>(src + 16 * kc);
-      if (!ok) a = s4{0, 0, 0, 0};
+    for (int m = 0; m < MT; ++m) {
+      ok[m] = vok[m] && xs[m] + dx >= 0 && xs[m] + dx < g.X && ys[m] + dy >= 0 && ys[m] + dy < g.Y &&
+              zs[m] + dz >= 0 && zs[m] + dz < g.Z;
+      const long long nv = ok[m] ? v0 + 16 * m + i + dx + (long long)g.X * (dy + (long long)g.Y * dz) : 0;
+      src[m] = in.p + nv * in.cs + in.coff + 4 * kq;
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      s4 a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        a[m] = *reinterpret_cast<const s4*>(src[m] + 16 * kc);
+        if (!ok[m]) a[m] = s4{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const s4 b = *reinterpret_cast<const s4*>(wt + (size_t)t * 16 * CIN + 16 * kc);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        const s4 bf = *reinterpret_cast<const s4*>(&ws[b][(t * 16 + i) * RS + 16 * kc + 4 * kq]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
       }
     }
+    __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + i;
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const long long vo = tile * 16 + 4 * kq + e;
-      if (vo >= P || co >= cout) continue;
-      float val = acc[t][e] + (bias ? bias[co] : 0.f);
-      if (relu) val = fmaxf(val, 0.f);
-      if (out32)
-        out32[vo * 2 + co] = val;
-      else
-        out.p[vo * out.cs + out.coff + co] = f2bf(val);
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long long vo = v0 + 16 * m + 4 * kq + e;
+        if (vo >= P || co >= cout) continue;
+        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (out32)
+          out32[vo * 2 + co] = val;
+        else
+          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      }
     }
-  }
 }
 
 constexpr int kWgTile = 64;      // voxels per weight-gradient tile
@@ -421,7 +462,7 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s) {
-  const unsigned grid = unsigned((g.P() + 16 * kConvWaves - 1) / (16 * kConvWaves));
+  const unsigned grid = unsigned((g.P() + 16 * kConvMT * kConvWaves - 1) / (16 * kConvMT * kConvWaves));
 #define H6_CONV(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                  \
     hipLaunchKernelGGL((conv_kernel<CI, CO>), dim3(grid), dim3(64 * kConvWaves), 0, s, in, W, bias, \
