@@ -379,8 +379,10 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
       e = upload(reinterpret_cast<double2**>(&P->d_cstart), cd, s);
     }
   }
-  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+  for (int a = 0; a < 2 && e == hipSuccess; ++a) {
     if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
+    P->ax[a].lines = a == 0 ? 4 : 16;     // untuned default: best on gfx950 at 256^3
+  }
   const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipMalloc(&P->w_pc[i], P->N * elem);
   if (e == hipSuccess) e = hipMalloc(&P->partials, sizeof(double) * 2 * kMaxPartials);
@@ -488,22 +490,25 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
       std::snprintf(devname, sizeof devname, "%s", prop.gcnArchName);
   }
   char key[512];
-  std::snprintf(key, sizeof key, "h6tune1 %s %d %d %d %d", devname, P->dims[0], P->dims[1], P->dims[2],
+  std::snprintf(key, sizeof key, "h6tune2 %s %d %d %d %d", devname, P->dims[0], P->dims[1], P->dims[2],
                 P->p.precision);
   const bool can_x = P->ax[0].rader_mem != nullptr, can_y = P->ax[1].rader_mem != nullptr;
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[600];
       while (std::fgets(line, sizeof line, f)) {
-        int tz = 0, xf = 0, yf = 0;
+        int tz = 0, xf = 0, yf = 0, xl = 0, yl = 0;
         const size_t kl = std::strlen(key);
         if (std::strncmp(line, key, kl) == 0 && line[kl] == ' ' &&
-            std::sscanf(line + kl, " tz=%d xfast=%d yfast=%d", &tz, &xf, &yf) == 3 &&
-            (tz == 8 || tz == 16 || tz == 32)) {
+            std::sscanf(line + kl, " tz=%d xfast=%d yfast=%d xlines=%d ylines=%d", &tz, &xf, &yf, &xl,
+                        &yl) == 5 &&
+            (tz == 8 || tz == 16 || tz == 32) && rader_lines_ok(0, xl) && rader_lines_ok(1, yl)) {
           std::fclose(f);
           P->stencil_tz = tz;
           P->ax[0].fast = can_x && xf;
           P->ax[1].fast = can_y && yf;
+          P->ax[0].lines = xl;
+          P->ax[1].lines = yl;
           return H6_OK;
         }
       }
@@ -551,13 +556,22 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
     if (ms < best_ms) { best_ms = ms; best_tz = tz; }
   }
   P->stencil_tz = best_tz;
+  // per transform axis: the Rader path at each supported workgroup width
+  // against the dense sums, timed inside the whole A_p^{-1}
   for (int ax = 0; ax < 2; ++ax) {
     if (!(ax == 0 ? can_x : can_y)) continue;
-    P->ax[ax].fast = 1;
-    const double fast = time_it([&] { (void)launch_pinv(P, x, y, s); });
     P->ax[ax].fast = 0;
-    const double dense = time_it([&] { (void)launch_pinv(P, x, y, s); });
-    P->ax[ax].fast = fast <= dense ? 1 : 0;
+    double best = time_it([&] { (void)launch_pinv(P, x, y, s); });
+    int best_lines = 0;
+    for (int lines : {4, 8, 16}) {
+      if (!rader_lines_ok(ax, lines)) continue;
+      P->ax[ax].fast = 1;
+      P->ax[ax].lines = lines;
+      const double ms = time_it([&] { (void)launch_pinv(P, x, y, s); });
+      if (ms < best) { best = ms; best_lines = lines; }
+    }
+    P->ax[ax].fast = best_lines ? 1 : 0;
+    P->ax[ax].lines = best_lines ? best_lines : (ax == 0 ? 4 : 16);
   }
   P->timing.enabled = timing;
   const hipError_t err = hipStreamSynchronize(s);
@@ -568,8 +582,8 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
   }
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s tz=%d xfast=%d yfast=%d\n", key, P->stencil_tz, int(P->ax[0].fast),
-                   int(P->ax[1].fast));
+      std::fprintf(f, "%s tz=%d xfast=%d yfast=%d xlines=%d ylines=%d\n", key, P->stencil_tz,
+                   int(P->ax[0].fast), int(P->ax[1].fast), P->ax[0].lines, P->ax[1].lines);
       std::fclose(f);
     }
   }

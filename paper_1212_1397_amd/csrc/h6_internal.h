@@ -52,6 +52,7 @@ struct AxisXform {
   int M = 0;        // n + 1
   int neumann = 0;  // 0: DST-I pair, 1: DCT-I pair
   int fast = 0;     // 1: Rader FFT path (M = 257), 0: dense sums in LDS
+  int lines = 0;    // Rader path: lines (x) / columns (y) per workgroup (autotuned)
   RaderTables rader{};
   void* rader_mem = nullptr;   // one device allocation holding the tables
 };

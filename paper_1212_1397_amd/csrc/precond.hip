@@ -318,7 +318,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   auto xform_x = [&](bool inv, auto* src, auto* dst, int accumulate) {
     timing_begin(P, KC_XFORM_X, s, &ev);
     if (X.fast)
-      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate);
+      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines);
     else
       hipLaunchKernelGGL((xform_x_kernel<std::remove_cv_t<std::remove_pointer_t<decltype(src)>>,
                                          std::remove_pointer_t<decltype(dst)>, R>),
@@ -329,7 +329,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
     timing_begin(P, KC_XFORM_Y, s, &ev);
     if (Y.fast)
-      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s);
+      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines);
     else
       hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, src, dst, nx, Y.L, Y.M,
                          Y.neumann, inv ? 1 : 0, P->d_trig_y);

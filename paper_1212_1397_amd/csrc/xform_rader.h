@@ -23,12 +23,16 @@ struct RaderTables {
 
 constexpr int kRaderM = 257;
 
-// accumulate != 0 (inverse transforms with a complex128 output only): out += result
+// Lines per workgroup supported per axis (x: 4, 8; y: 8, 16).
+bool rader_lines_ok(int axis, int lines);
+
+// accumulate != 0 (inverse transforms with a complex128 output only): out += result.
+// lines: lines (x) or columns (y) per workgroup, one of rader_lines_ok's values.
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s, int accumulate = 0);
+                          const RaderTables& tab, hipStream_t s, int accumulate, int lines);
 template <typename R, typename T>
 hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
-                          const RaderTables& tab, hipStream_t s);
+                          const RaderTables& tab, hipStream_t s, int lines);
 
 }  // namespace h6

@@ -30,8 +30,9 @@
 // Forward transforms apply W^{-1} ((2/M) sine sum, or (2/M) C W^T C for the
 // cosine basis, C = diag(1/2, 1, .., 1, 1/2)); inverse transforms apply W
 // (plain sums).  Lines are staged through LDS with coalesced loads/stores;
-// along x a workgroup owns kLines whole lines, along y a tile of kLines
-// consecutive x columns at one z.
+// along x a workgroup owns KL whole lines, along y a tile of KL consecutive x
+// columns at one z (KL = 4, 8 or 16, chosen per axis: more columns make
+// longer contiguous row segments along y, fewer lines more workgroups along x).
 #include "h6_internal.h"
 #include "xform_rader.h"
 
@@ -116,7 +117,6 @@ __device__ __forceinline__ void fft16(T2 (&v)[16]) {
   for (int i = 0; i < 16; ++i) v[i] = t[i];
 }
 
-constexpr int kLines = 8;          // lines per workgroup (16 threads each)
 constexpr int kStride = 273;       // LDS row stride (complex) per line, >= 258 and >= 16*17
 constexpr int kHalf = 128;         // (M - 1) / 2
 
@@ -148,17 +148,18 @@ __device__ __forceinline__ R tab_cos(const RaderTables& tab, int i) {
   else return tab.cos_a[i];
 }
 
-template <typename R, int AXIS, bool NEU, bool INV, typename Tin, typename Tout>
-__global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __restrict__ in,
+template <typename R, int AXIS, bool NEU, bool INV, int KL, typename Tin, typename Tout>
+__global__ __launch_bounds__(KL * 16) void rader257_kernel(const Tin* __restrict__ in,
                                                                Tout* __restrict__ out, int nlines,
                                                                int nx, int L, RaderTables tab,
                                                                int acc) {
-  __shared__ T2 buf[kLines][kStride];
+  __shared__ T2 buf[KL][kStride];
+  constexpr int kPx = (258 + KL * 16 - 1) / (KL * 16);   // loads per x line (L <= 258)
   constexpr int M = 257;
   const int tid = threadIdx.x;
   const int g = tid >> 4, t = tid & 15;
   const int* __restrict__ slot = NEU ? tab.slot_n : tab.slot_d;
-  // ---- load kLines lines into LDS in Rader order: all global reads of a
+  // ---- load KL lines into LDS in Rader order: all global reads of a
   // thread are issued before any LDS write (coalesced, many loads in flight) ----
   int nl;
   size_t gbase;
@@ -170,48 +171,48 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
     bx = lid % gridDim.x;
     by = lid / gridDim.x;
   }
-  const int line0 = bx * kLines;
+  const int line0 = bx * KL;
   if (AXIS == 0) {
-    nl = min(kLines, nlines - line0);
+    nl = min(KL, nlines - line0);
     gbase = size_t(line0) * L;
     // LDS slots first, unconditionally (clamped), so that no slot lookup is
     // waited on between the data loads and their LDS writes
-    int sl[3];
+    int sl[kPx];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sl[k] = slot[min(tid + k * kLines * 16, L - 1)];
-    T2 r[kLines][3];
+    for (int k = 0; k < kPx; ++k) sl[k] = slot[min(tid + k * KL * 16, L - 1)];
+    T2 r[KL][kPx];
 #pragma unroll
-    for (int b = 0; b < kLines; ++b)
+    for (int b = 0; b < KL; ++b)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int p = tid + k * kLines * 16;
+      for (int k = 0; k < kPx; ++k) {
+        const int p = tid + k * KL * 16;
         if (b < nl && p < L) r[b][k] = cv<T2>(in[gbase + size_t(b) * L + p]);
       }
 #pragma unroll
-    for (int b = 0; b < kLines; ++b)
+    for (int b = 0; b < KL; ++b)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int p = tid + k * kLines * 16;
+      for (int k = 0; k < kPx; ++k) {
+        const int p = tid + k * KL * 16;
         if (b < nl && p < L) buf[b][sl[k]] = r[b][k];
       }
   } else {
-    nl = min(kLines, nx - line0);                   // x columns i0 .. i0 + nl - 1
+    nl = min(KL, nx - line0);                   // x columns i0 .. i0 + nl - 1
     gbase = size_t(by) * nx * L + line0;
-    constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
+    constexpr int kPer = (KL * 258 + KL * 16 - 1) / (KL * 16);
     int sl[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) sl[k] = slot[min((tid + k * kLines * 16) / kLines, L - 1)];
+    for (int k = 0; k < kPer; ++k) sl[k] = slot[min((tid + k * KL * 16) / KL, L - 1)];
     T2 r[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int e = tid + k * kLines * 16;
-      const int q = e / kLines, b = e - q * kLines;
+      const int e = tid + k * KL * 16;
+      const int q = e / KL, b = e - q * KL;
       if (q < L && b < nl) r[k] = cv<T2>(in[gbase + size_t(q) * nx + b]);
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int e = tid + k * kLines * 16;
-      const int q = e / kLines, b = e - q * kLines;
+      const int e = tid + k * KL * 16;
+      const int q = e / KL, b = e - q * KL;
       if (q < L && b < nl) buf[b][sl[k]] = r[k];
     }
   }
@@ -349,19 +350,19 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
   // ---- store (coalesced); with acc, out += result (all reads issued first) ----
   if (AXIS == 0) {
     if (acc) {
-      Tout o[kLines][3];
+      Tout o[KL][kPx];
 #pragma unroll
-      for (int b = 0; b < kLines; ++b)
+      for (int b = 0; b < KL; ++b)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int p = tid + k * kLines * 16;
+        for (int k = 0; k < kPx; ++k) {
+          const int p = tid + k * KL * 16;
           if (b < nl && p < L) o[b][k] = out[gbase + size_t(b) * L + p];
         }
 #pragma unroll
-      for (int b = 0; b < kLines; ++b)
+      for (int b = 0; b < KL; ++b)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int p = tid + k * kLines * 16;
+        for (int k = 0; k < kPx; ++k) {
+          const int p = tid + k * KL * 16;
           if (b < nl && p < L) {
             const Tout v = cv<Tout>(buf[b][p]);
             Tout u;
@@ -372,19 +373,19 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
         }
     } else {
 #pragma unroll
-      for (int b = 0; b < kLines; ++b)
+      for (int b = 0; b < KL; ++b)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int p = tid + k * kLines * 16;
+        for (int k = 0; k < kPx; ++k) {
+          const int p = tid + k * KL * 16;
           if (b < nl && p < L) out[gbase + size_t(b) * L + p] = cv<Tout>(buf[b][p]);
         }
     }
   } else {
-    constexpr int kPer = (kLines * 258 + kLines * 16 - 1) / (kLines * 16);
+    constexpr int kPer = (KL * 258 + KL * 16 - 1) / (KL * 16);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const int e = tid + k * kLines * 16;
-      const int q = e / kLines, b = e - q * kLines;
+      const int e = tid + k * KL * 16;
+      const int q = e / KL, b = e - q * KL;
       if (q < L && b < nl) out[gbase + size_t(q) * nx + b] = cv<Tout>(buf[b][q]);
     }
   }
@@ -392,51 +393,68 @@ __global__ __launch_bounds__(kLines * 16) void rader257_kernel(const Tin* __rest
 
 #undef T2
 
-template <typename R, int AXIS, bool NEU, typename Tin, typename Tout>
+template <typename R, int AXIS, bool NEU, int KL, typename Tin, typename Tout>
 void launch_one(bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
-                const RaderTables& tab, hipStream_t s, int acc = 0) {
-  const dim3 grid = AXIS == 0 ? dim3((nlines + kLines - 1) / kLines) : dim3((nx + kLines - 1) / kLines, nz);
+                const RaderTables& tab, hipStream_t s, int acc) {
+  const dim3 grid = AXIS == 0 ? dim3((nlines + KL - 1) / KL) : dim3((nx + KL - 1) / KL, nz);
   if (inv)
-    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, true, Tin, Tout>), grid, dim3(kLines * 16), 0,
+    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, true, KL, Tin, Tout>), grid, dim3(KL * 16), 0,
                        s, in, out, nlines, nx, L, tab, acc);
   else
-    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, false, Tin, Tout>), grid, dim3(kLines * 16), 0,
+    hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, false, KL, Tin, Tout>), grid, dim3(KL * 16), 0,
                        s, in, out, nlines, nx, L, tab, 0);
+}
+
+template <typename R, int AXIS, int KL, typename Tin, typename Tout>
+void launch_bc(bool neumann, bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
+               const RaderTables& tab, hipStream_t s, int acc) {
+  if (neumann)
+    launch_one<R, AXIS, true, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc);
+  else
+    launch_one<R, AXIS, false, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc);
 }
 
 }  // namespace
 
+bool rader_lines_ok(int axis, int lines) {
+  return axis == 0 ? (lines == 4 || lines == 8) : (lines == 8 || lines == 16);
+}
+
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s, int accumulate) {
-  if (neumann)
-    launch_one<R, 0, true>(inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
+                          const RaderTables& tab, hipStream_t s, int accumulate, int lines) {
+  if (lines == 4)
+    launch_bc<R, 0, 4>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
+  else if (lines == 8)
+    launch_bc<R, 0, 8>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
   else
-    launch_one<R, 0, false>(inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename R, typename T>
 hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
-                          const RaderTables& tab, hipStream_t s) {
-  if (neumann)
-    launch_one<R, 1, true>(inverse, in, out, 0, nx, L, nz, tab, s);
+                          const RaderTables& tab, hipStream_t s, int lines) {
+  if (lines == 8)
+    launch_bc<R, 1, 8>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0);
+  else if (lines == 16)
+    launch_bc<R, 1, 16>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0);
   else
-    launch_one<R, 1, false>(inverse, in, out, 0, nx, L, nz, tab, s);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template hipError_t launch_rader_x<double, double2, double2>(bool, bool, const double2*, double2*,
-                                                             int, int, const RaderTables&, hipStream_t, int);
+                                                             int, int, const RaderTables&, hipStream_t, int, int);
 template hipError_t launch_rader_x<float, double2, float2>(bool, bool, const double2*, float2*, int,
-                                                           int, const RaderTables&, hipStream_t, int);
+                                                           int, const RaderTables&, hipStream_t, int, int);
 template hipError_t launch_rader_x<float, float2, double2>(bool, bool, const float2*, double2*, int,
-                                                           int, const RaderTables&, hipStream_t, int);
+                                                           int, const RaderTables&, hipStream_t, int, int);
 template hipError_t launch_rader_x<float, float2, float2>(bool, bool, const float2*, float2*, int,
-                                                          int, const RaderTables&, hipStream_t, int);
+                                                          int, const RaderTables&, hipStream_t, int, int);
 template hipError_t launch_rader_y<double, double2>(bool, bool, const double2*, double2*, int, int,
-                                                    int, const RaderTables&, hipStream_t);
+                                                    int, const RaderTables&, hipStream_t, int);
 template hipError_t launch_rader_y<float, float2>(bool, bool, const float2*, float2*, int, int, int,
-                                                  const RaderTables&, hipStream_t);
+                                                  const RaderTables&, hipStream_t, int);
 
 }  // namespace h6

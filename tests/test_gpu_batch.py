@@ -77,7 +77,7 @@ def test_autotune_keeps_results_and_caches(h6, tmp_path):
     cache = os.path.join(tmp_path, "tune.txt")
     plan.autotune(cache)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("h6tune1 ")
+    assert len(lines) == 1 and lines[0].startswith("h6tune2 ")
     print(lines[0], flush=True)
     assert torch.equal(plan.apply_A(x), y0)      # the stencil variants differ only in the launch shape
     z1 = plan.apply_Pinv(x)
@@ -86,3 +86,24 @@ def test_autotune_keeps_results_and_caches(h6, tmp_path):
     plan2.autotune(cache)                          # read from the cache, not re-timed
     assert len(open(cache).read().splitlines()) == 1
     assert torch.equal(plan2.apply_A(x), y0)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_transform_workgroup_widths_agree(h6, tmp_path, precision):
+    """Every Rader workgroup width the autotuner may pick (lines along x,
+    columns along y) runs the same per-line arithmetic: bit-identical z.
+    The choice is forced through the autotuner's cache file."""
+    w = WORKLOADS["dns-256"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=precision)
+    g = torch.Generator(device="cuda").manual_seed(21)
+    x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda", generator=g)
+    z0 = plan.apply_Pinv(x)
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    nx, ny, nz = plan.dims
+    pnum = h6.PRECISIONS[precision]
+    for xl, yl in [(8, 8), (8, 16), (4, 8), (4, 16)]:
+        path = os.path.join(tmp_path, f"tune_{xl}_{yl}.txt")
+        with open(path, "w") as f:
+            f.write(f"h6tune2 {arch} {nx} {ny} {nz} {pnum} tz=16 xfast=1 yfast=1 xlines={xl} ylines={yl}\n")
+        plan.autotune(path)
+        assert torch.equal(plan.apply_Pinv(x), z0), (xl, yl)
