@@ -112,6 +112,35 @@ h6_status helmholtz6_apply_Pinv(h6_plan plan, const void* r, void* z, void* hip_
 h6_status helmholtz6_rhs_gaussians(h6_plan plan, int nsrc, const double* centres,
                                    const double* amps, double sigma, void* F, void* hip_stream);
 
+/* F for a separable source (the manufactured solutions of Section 4 are of
+ * this form): the same interior and face terms as helmholtz6_rhs_gaussians for
+ *   f(x,y,z) = sum_{s < nterms} c_s X_s(x) Y_s(y) Z_s(z).
+ * coef: host array of 2*nterms doubles (re, im of c_s).  tx, ty, tz: host
+ * arrays of complex128 values (re, im interleaved) holding, for each term s
+ * and derivative order o = 0..4, the o-th derivative of the axis factor at
+ * the n'_a unknown nodes of that axis:
+ *   tx[2 * ((s * 5 + o) * n'x + i) + {0, 1}] = d^o X_s / dx^o at x = q_i h,
+ * q_i = i for a non-Dirichlet low face and i + 1 for a Dirichlet one (likewise
+ * ty with n'y, tz with n'z).  Faces are unknown nodes wherever their face
+ * terms apply, so node samples suffice.  nterms in 0..1024 (0 gives F = 0).
+ * The tables are copied to a plan-owned device buffer (grown on demand);
+ * synchronises hip_stream before returning, so the host arrays may be
+ * released afterwards. */
+h6_status helmholtz6_rhs_separable(h6_plan plan, int nterms, const double* coef, const double* tx,
+                                   const double* ty, const double* tz, void* F, void* hip_stream);
+
+/* Nonhomogeneous Dirichlet data on a z face (side 0: z = 0, side 1: the top
+ * face), as in Table 5's problem.  The unknown plane next to the face couples
+ * to the face values through the in-plane operator G of eq. (scheme)'s
+ * delta_z^2 term, G = I + (1 + kappa/30)/6 (D_x + D_y) + (1/30) D_x D_y with
+ * D = h^2 delta^2, so F -= G g on that plane.  g: device complex128 array of
+ * n'x * n'y values (x fastest) at the face nodes above or below the
+ * unknowns; on the face's own edges g is taken as 0 next to a Dirichlet x or
+ * y face and mirrored next to a Neumann one (the data of a consistent
+ * solution).  The face must be Dirichlet (H6_ERR_ARG otherwise).  Call after
+ * building the source part of F.  Enqueue only. */
+h6_status helmholtz6_rhs_dirichlet_z(h6_plan plan, int side, const void* g, void* F, void* hip_stream);
+
 /* Solves A U = F.  U is the initial guess on entry (may be zero) and the
  * solution on return.  F and U must not alias.  GMRES/FGMRES: right
  * preconditioning, modified Gram-Schmidt Arnoldi, Givens least squares in FP64

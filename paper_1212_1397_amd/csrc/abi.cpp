@@ -275,6 +275,7 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->partials);
   (void)hipFree(P->d_scal);
   (void)hipFree(P->d_gram);
+  (void)hipFree(P->d_sep);
   if (P->ev_sync) (void)hipEventDestroy(P->ev_sync);
   if (P->h_pinned) (void)hipHostFree(P->h_pinned);
   for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
@@ -337,6 +338,12 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
     P->ax[a].L = P->dims[a];
     P->ax[a].M = p->n[a] + 1;
     P->ax[a].neumann = p->bc[2 * a] == H6_NEUMANN;
+    if (!dense_transform_fits(a, P->ax[a].L, P->ax[a].M, p->precision == H6_MIXED)) {
+      err = std::string("n'") + (a == 0 ? "x" : "y") + " = " + std::to_string(P->ax[a].L) +
+            " exceeds the transform limit (line and tables must fit one workgroup's LDS)";
+      free_plan(P);
+      return H6_ERR_ARG;
+    }
   }
   std::vector<double> lx = mode_lambdas(P->ax[0]), ly = mode_lambdas(P->ax[1]);
   std::vector<cplx> sub, diag, sup;
@@ -644,6 +651,40 @@ h6_status helmholtz6_rhs_gaussians(h6_plan P, int nsrc, const double* centres, c
   }
   H6_TRY_HIP(launch_rhs(P, nsrc, centres, amps, sigma, static_cast<double2*>(F),
                         static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_rhs_separable(h6_plan P, int nterms, const double* coef, const double* tx,
+                                   const double* ty, const double* tz, void* F, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!F || nterms < 0 || nterms > 1024 || (nterms > 0 && (!coef || !tx || !ty || !tz))) {
+    P->last_error = "bad rhs_separable arguments";
+    return H6_ERR_ARG;
+  }
+  if (nterms == 0) {
+    H6_TRY_HIP(hipMemsetAsync(F, 0, P->N * sizeof(double2), static_cast<hipStream_t>(hip_stream)));
+    return H6_OK;
+  }
+  const double* tab[3] = {tx, ty, tz};
+  H6_TRY_HIP(launch_rhs_separable(P, nterms, coef, tab, static_cast<double2*>(F),
+                                  static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_rhs_dirichlet_z(h6_plan P, int side, const void* g, void* F, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!g || !F || (side != 0 && side != 1)) {
+    P->last_error = "bad rhs_dirichlet_z arguments";
+    return H6_ERR_ARG;
+  }
+  if (P->p.bc[4 + side] != H6_DIRICHLET) {
+    P->last_error = "Dirichlet data given for a z face that is not Dirichlet";
+    return H6_ERR_ARG;
+  }
+  H6_TRY_HIP(launch_rhs_dirichlet_z(P, side, static_cast<const double2*>(g), static_cast<double2*>(F),
+                                    static_cast<hipStream_t>(hip_stream)));
   return H6_OK;
 }
 

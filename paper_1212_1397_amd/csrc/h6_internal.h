@@ -111,6 +111,7 @@ struct h6_plan_s {
   double2* d_scal = nullptr;                   // device scalars: reduction results, coefficients (kScal entries)
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
   double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
+  void* d_sep = nullptr;  size_t sep_bytes = 0;  // separable-source tables (helmholtz6_rhs_separable)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
   struct h6_net_s* net = nullptr;              // learned correction for FGMRES (not owned)
   bool use_graphs = false;                     // capture GMRES steps as HIP graphs
@@ -176,8 +177,15 @@ hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStrea
 // callers that only hand r to a complex64 preconditioner
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
                                double* partials, int* nparts, hipStream_t s);
+// whether the dense transform along axis (0: x, 1: y) of line length L fits
+// the LDS budget of one workgroup (checked at setup)
+bool dense_transform_fits(int axis, int L, int M, bool f32);
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
+// tab[a]: host complex128 samples, nterms x 5 derivative orders x dims[a]; synchronises s
+hipError_t launch_rhs_separable(h6_plan P, int nterms, const double* coef, const double* const tab[3],
+                                double2* F, hipStream_t s);
+hipError_t launch_rhs_dirichlet_z(h6_plan P, int side, const double2* g, double2* F, hipStream_t s);
 
 // Krylov helpers (double2 vectors of length P->N); reductions end in device doubles
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s);

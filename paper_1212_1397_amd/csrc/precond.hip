@@ -84,7 +84,8 @@ __device__ __forceinline__ typename C2<R>::T dense_out(const typename C2<R>::T* 
 }
 
 constexpr int kXLines = 4;      // x lines per workgroup
-constexpr int kYCols = 8;       // x columns per y-transform workgroup
+constexpr int kYCols = 8;       // most x columns per y-transform workgroup (fewer for long lines)
+constexpr size_t kDenseLds = 65536;   // LDS budget of one dense-transform workgroup
 
 template <typename Tin, typename Tout, typename R>
 __global__ __launch_bounds__(256) void xform_x_kernel(const Tin* __restrict__ in,
@@ -121,7 +122,7 @@ template <typename T2in, typename R>
 __global__ __launch_bounds__(256) void xform_y_kernel(const T2in* __restrict__ in,
                                                       T2in* __restrict__ out, int nx, int L,
                                                       int M, int neumann, int inverse,
-                                                      const double* __restrict__ trig) {
+                                                      const double* __restrict__ trig, int cols) {
   using T2 = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   R* sinT = reinterpret_cast<R*>(smem_raw);
@@ -131,16 +132,16 @@ __global__ __launch_bounds__(256) void xform_y_kernel(const T2in* __restrict__ i
     sinT[t] = R(trig[t]);
     cosT[t] = R(trig[2 * M + t]);
   }
-  const int i0 = blockIdx.x * kYCols;
-  const int nc = min(kYCols, nx - i0);
+  const int i0 = blockIdx.x * cols;
+  const int nc = min(cols, nx - i0);
   const size_t zoff = size_t(blockIdx.y) * nx * L;
-  for (int e = threadIdx.x; e < L * kYCols; e += blockDim.x) {
-    const int q = e / kYCols, c = e - q * kYCols;
+  for (int e = threadIdx.x; e < L * cols; e += blockDim.x) {
+    const int q = e / cols, c = e - q * cols;
     if (c < nc) buf[c * L + q] = cvt<T2>(in[zoff + size_t(q) * nx + i0 + c]);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < L * kYCols; e += blockDim.x) {
-    const int m = e / kYCols, c = e - m * kYCols;
+  for (int e = threadIdx.x; e < L * cols; e += blockDim.x) {
+    const int m = e / cols, c = e - m * cols;
     if (c < nc)
       out[zoff + size_t(m) * nx + i0 + c] =
           cvt<T2in>(dense_out<R>(buf + c * L, 1, L, M, neumann, inverse, m, sinT, cosT));
@@ -310,8 +311,12 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   const AxisXform& Y = P->ax[1];
   const int nlines_x = ny * nz;
   const size_t shx = 4 * X.M * sizeof(R) + sizeof(R) + kXLines * X.L * sizeof(T2) + 16;
-  const size_t shy = 4 * Y.M * sizeof(R) + sizeof(R) + kYCols * Y.L * sizeof(T2) + 16;
-  const dim3 gx((nlines_x + kXLines - 1) / kXLines), gy((nx + kYCols - 1) / kYCols, nz);
+  auto shy_of = [&](int cols) { return 4 * Y.M * sizeof(R) + sizeof(R) + cols * Y.L * sizeof(T2) + 16; };
+  int ycols = kYCols;
+  while (ycols > 1 && shy_of(ycols) > kDenseLds) ycols /= 2;
+  const size_t shy = shy_of(ycols);
+  if ((!X.fast && shx > kDenseLds) || (!Y.fast && shy > kDenseLds)) return hipErrorInvalidConfiguration;
+  const dim3 gx((nlines_x + kXLines - 1) / kXLines), gy((nx + ycols - 1) / ycols, nz);
   hipEvent_t ev;
 
   const double Nd = double(P->N);
@@ -332,7 +337,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
       (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines);
     else
       hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, src, dst, nx, Y.L, Y.M,
-                         Y.neumann, inv ? 1 : 0, P->d_trig_y);
+                         Y.neumann, inv ? 1 : 0, P->d_trig_y, ycols);
     timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
   if (part & PINV_FIRST) xform_x(false, r, w0, 0);
@@ -362,6 +367,12 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
 }
 
 }  // namespace
+
+bool dense_transform_fits(int axis, int L, int M, bool f32) {
+  const size_t rs = f32 ? sizeof(float) : sizeof(double);
+  const size_t rows = axis == 0 ? kXLines : 1;
+  return 4 * size_t(M) * rs + rs + rows * size_t(L) * 2 * rs + 16 <= kDenseLds;
+}
 
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part) {
   if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, z, s, part);

@@ -1,6 +1,8 @@
-// F = h^2-scaled compact right-hand side for a sum of Gaussian sources
-//   f = sum_s a_s exp(-|x - c_s|^2 / (2 sigma^2)),
-// one thread per unknown node.
+// F = h^2-scaled compact right-hand side, one thread per unknown node, for
+//  (a) a sum of Gaussian sources f = sum_s a_s exp(-|x - c_s|^2 / (2 sigma^2)),
+//  (b) a separable source f = sum_s c_s X_s(x) Y_s(y) Z_s(z) given by samples of
+//      each factor and its derivatives up to fourth order at the unknown nodes,
+// and (c) the plane term of nonhomogeneous Dirichlet data on a z face.
 //
 // Interior part, eq. (scheme) right side times h^2 (mixed fourth-derivative
 // coefficient h^4/180, the value that makes the scheme sixth order):
@@ -13,6 +15,10 @@
 // with fbar_m = d^m/dz'^m (e^{ikz'} f), Lbar = fbar_xxz + fbar_yyz and
 //   Fbar = (h^2/6 + k^2h^4/45) fbar_1 - (ikh^4/90) fbar_2 + (h^4/120)(fbar_3 - Lbar),
 // z' = z at the bottom face and z' = top - z at the top face.
+// Dirichlet data g on a z face: the unknown plane next to the face couples to
+// the face plane through the in-plane operator G of eq. (scheme)'s delta_z^2
+// term, G = I + (1 + kappa/30)/6 (D_x + D_y) + (1/30) D_x D_y (D = h^2 delta^2),
+// so F -= G g on that plane.
 //
 // Gaussian derivatives: d^n/dx^n exp(-t^2/2), t = (x - c)/sigma, equals
 // (-1/sigma)^n He_n(t) exp(-t^2/2) with the probabilists' Hermite polynomials.
@@ -23,16 +29,22 @@ namespace {
 
 constexpr int kMaxSrc = 64;
 
-struct RhsArgs {
-  int nsrc;
+// grid and coefficient data shared by every source form
+struct RhsCoef {
   int n[3];        // interior counts
   int dims[3];     // unknown counts
   int qlo[3];      // q index of the first unknown per axis
   int face[6];
-  double h, inv_sigma;
+  double h;
   double2 cK, c_lap, c_bil, c_mix;               // interior coefficients (already times h^2)
   double2 nN1, nN3, nNm;                         // Neumann R_N coefficients (times 2h)
   double2 ik, sA, sB, sC, e1mu3, mu1h5;          // Sommerfeld coefficients
+};
+
+struct RhsArgs {
+  RhsCoef c;
+  int nsrc;
+  double inv_sigma;
   double cx[kMaxSrc], cy[kMaxSrc], cz[kMaxSrc];
   double2 amp[kMaxSrc];
 };
@@ -61,32 +73,8 @@ enum {
   D100, D300, D120, D102, D010, D030, D210, D012, D001, D003, D201, D021, ND
 };
 
-__global__ __launch_bounds__(256) void rhs_kernel(RhsArgs a, double2* __restrict__ F) {
-  const size_t N = size_t(a.dims[0]) * a.dims[1] * a.dims[2];
-  const size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
-  if (idx >= N) return;
-  const int i = int(idx % a.dims[0]);
-  const int j = int((idx / a.dims[0]) % a.dims[1]);
-  const int l = int(idx / (size_t(a.dims[0]) * a.dims[1]));
-  const int q[3] = {i + a.qlo[0], j + a.qlo[1], l + a.qlo[2]};
-  const double X = q[0] * a.h, Y = q[1] * a.h, Z = q[2] * a.h;
-  double2 d[ND];
-  for (int t = 0; t < ND; ++t) d[t] = make_double2(0.0, 0.0);
-  for (int s = 0; s < a.nsrc; ++s) {
-    double gx[5], gy[5], gz[5];
-    gauss_derivs(X, a.cx[s], a.inv_sigma, gx);
-    gauss_derivs(Y, a.cy[s], a.inv_sigma, gy);
-    gauss_derivs(Z, a.cz[s], a.inv_sigma, gz);
-    const double2 A = a.amp[s];
-    const double v[ND] = {
-        gx[0] * gy[0] * gz[0], gx[2] * gy[0] * gz[0], gx[0] * gy[2] * gz[0], gx[0] * gy[0] * gz[2],
-        gx[4] * gy[0] * gz[0], gx[0] * gy[4] * gz[0], gx[0] * gy[0] * gz[4], gx[2] * gy[2] * gz[0],
-        gx[2] * gy[0] * gz[2], gx[0] * gy[2] * gz[2], gx[1] * gy[0] * gz[0], gx[3] * gy[0] * gz[0],
-        gx[1] * gy[2] * gz[0], gx[1] * gy[0] * gz[2], gx[0] * gy[1] * gz[0], gx[0] * gy[3] * gz[0],
-        gx[2] * gy[1] * gz[0], gx[0] * gy[1] * gz[2], gx[0] * gy[0] * gz[1], gx[0] * gy[0] * gz[3],
-        gx[2] * gy[0] * gz[1], gx[0] * gy[2] * gz[1]};
-    for (int t = 0; t < ND; ++t) d[t] = ca(d[t], cs(A, v[t]));
-  }
+// F at node q from the accumulated derivative combinations d[] of f there
+__device__ double2 assemble(const RhsCoef& a, const double2 (&d)[ND], const int (&q)[3]) {
   const double2 lap = ca(ca(d[D200], d[D020]), d[D002]);
   const double2 mix = ca(ca(d[D220], d[D202]), d[D022]);
   const double2 quart = ca(ca(d[D400], d[D040]), d[D004]);
@@ -122,18 +110,127 @@ __global__ __launch_bounds__(256) void rhs_kernel(RhsArgs a, double2* __restrict
                           cm(a.sC, ca(fb3, cs(Lb, -1.0))));
     Fv = ca(Fv, cm(a.e1mu3, ca(cs(Fb, 2.0 * a.h), cm(a.mu1h5, Lb))));
   }
-  F[idx] = Fv;
+  return Fv;
+}
+
+// derivative orders (x, y, z) of each combination
+__constant__ int kOrd[ND][3] = {
+    {0, 0, 0}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {4, 0, 0}, {0, 4, 0}, {0, 0, 4}, {2, 2, 0},
+    {2, 0, 2}, {0, 2, 2}, {1, 0, 0}, {3, 0, 0}, {1, 2, 0}, {1, 0, 2}, {0, 1, 0}, {0, 3, 0},
+    {2, 1, 0}, {0, 1, 2}, {0, 0, 1}, {0, 0, 3}, {2, 0, 1}, {0, 2, 1}};
+
+__device__ __forceinline__ void node_of(const RhsCoef& a, size_t idx, int (&ijl)[3], int (&q)[3]) {
+  ijl[0] = int(idx % a.dims[0]);
+  ijl[1] = int((idx / a.dims[0]) % a.dims[1]);
+  ijl[2] = int(idx / (size_t(a.dims[0]) * a.dims[1]));
+  for (int ax = 0; ax < 3; ++ax) q[ax] = ijl[ax] + a.qlo[ax];
+}
+
+__global__ __launch_bounds__(256) void rhs_kernel(RhsArgs a, double2* __restrict__ F) {
+  const size_t N = size_t(a.c.dims[0]) * a.c.dims[1] * a.c.dims[2];
+  const size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+  if (idx >= N) return;
+  int ijl[3], q[3];
+  node_of(a.c, idx, ijl, q);
+  const double X = q[0] * a.c.h, Y = q[1] * a.c.h, Z = q[2] * a.c.h;
+  double2 d[ND];
+  for (int t = 0; t < ND; ++t) d[t] = make_double2(0.0, 0.0);
+  for (int s = 0; s < a.nsrc; ++s) {
+    double gx[5], gy[5], gz[5];
+    gauss_derivs(X, a.cx[s], a.inv_sigma, gx);
+    gauss_derivs(Y, a.cy[s], a.inv_sigma, gy);
+    gauss_derivs(Z, a.cz[s], a.inv_sigma, gz);
+    const double2 A = a.amp[s];
+    for (int t = 0; t < ND; ++t)
+      d[t] = ca(d[t], cs(A, gx[kOrd[t][0]] * gy[kOrd[t][1]] * gz[kOrd[t][2]]));
+  }
+  F[idx] = assemble(a.c, d, q);
+}
+
+// Separable source: tab[a] holds, per term s and derivative order o = 0..4,
+// the samples of the axis-a factor at the dims[a] unknown nodes of axis a:
+// tab[a][(s * 5 + o) * dims[a] + i].  coef[s] multiplies term s.
+__global__ __launch_bounds__(256) void rhs_separable_kernel(RhsCoef a, int nterms,
+                                                            const double2* __restrict__ coef,
+                                                            const double2* __restrict__ tx,
+                                                            const double2* __restrict__ ty,
+                                                            const double2* __restrict__ tz,
+                                                            double2* __restrict__ F) {
+  const size_t N = size_t(a.dims[0]) * a.dims[1] * a.dims[2];
+  const size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+  if (idx >= N) return;
+  int ijl[3], q[3];
+  node_of(a, idx, ijl, q);
+  double2 d[ND];
+  for (int t = 0; t < ND; ++t) d[t] = make_double2(0.0, 0.0);
+  for (int s = 0; s < nterms; ++s) {
+    double2 gx[5], gy[5], gz[5];
+    for (int o = 0; o < 5; ++o) {
+      gx[o] = tx[size_t(s * 5 + o) * a.dims[0] + ijl[0]];
+      gy[o] = ty[size_t(s * 5 + o) * a.dims[1] + ijl[1]];
+      gz[o] = tz[size_t(s * 5 + o) * a.dims[2] + ijl[2]];
+    }
+    const double2 c = coef[s];
+    for (int t = 0; t < ND; ++t)
+      d[t] = ca(d[t], cm(c, cm(gx[kOrd[t][0]], cm(gy[kOrd[t][1]], gz[kOrd[t][2]]))));
+  }
+  F[idx] = assemble(a, d, q);
+}
+
+// Dirichlet data g (n'x x n'y, x fastest) on a z face: Fp -= G g on the
+// adjacent unknown plane Fp.  D_x, D_y take the neighbour outside the unknown
+// range as 0 next to a Dirichlet face and as the mirror value (index 1 or
+// n' - 2) next to a Neumann face.
+struct PlaneRule {
+  int nx, ny;
+  int xlo_n, xhi_n, ylo_n, yhi_n;   // 1 where that in-plane face is Neumann
+};
+
+// index of the neighbour of i (i = -1 or n) under the face rule, or -1 for a zero value
+__device__ __forceinline__ int ext_index(int i, int n, int lo_n, int hi_n) {
+  if (i >= 0 && i < n) return i;
+  if (n < 2) return -1;
+  if (i < 0) return lo_n ? 1 : -1;
+  return hi_n ? n - 2 : -1;
+}
+
+__device__ __forceinline__ double2 dx_row(const double2* __restrict__ g, const PlaneRule& r, int i, int j) {
+  const double2* row = g + size_t(j) * r.nx;
+  const int im = ext_index(i - 1, r.nx, r.xlo_n, r.xhi_n), ip = ext_index(i + 1, r.nx, r.xlo_n, r.xhi_n);
+  double2 v = cs(row[i], -2.0);
+  if (im >= 0) v = ca(v, row[im]);
+  if (ip >= 0) v = ca(v, row[ip]);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void dirichlet_plane_kernel(const double2* __restrict__ g,
+                                                              double2* __restrict__ Fp, PlaneRule r,
+                                                              double2 ca_, double cb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= r.nx * r.ny) return;
+  const int i = idx % r.nx, j = idx / r.nx;
+  const int jm = ext_index(j - 1, r.ny, r.ylo_n, r.yhi_n), jp = ext_index(j + 1, r.ny, r.ylo_n, r.yhi_n);
+  const double2 g0 = g[idx];
+  const double2 dx0 = dx_row(g, r, i, j);
+  // D_y g and D_y D_x g at (i, j)
+  double2 dy = cs(g0, -2.0), dyx = cs(dx0, -2.0);
+  if (jm >= 0) {
+    dy = ca(dy, g[size_t(jm) * r.nx + i]);
+    dyx = ca(dyx, dx_row(g, r, i, jm));
+  }
+  if (jp >= 0) {
+    dy = ca(dy, g[size_t(jp) * r.nx + i]);
+    dyx = ca(dyx, dx_row(g, r, i, jp));
+  }
+  const double2 Gg = ca(ca(g0, cm(ca_, ca(dx0, dy))), cs(dyx, cb));
+  const double2 f = Fp[idx];
+  Fp[idx] = make_double2(f.x - Gg.x, f.y - Gg.y);
 }
 
 double2 d2(cplx c) { return make_double2(c.real(), c.imag()); }
 
-}  // namespace
-
-hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
-                      double sigma, double2* F, hipStream_t s) {
-  if (nsrc > kMaxSrc) return hipErrorInvalidValue;
-  RhsArgs a{};
-  a.nsrc = nsrc;
+RhsCoef rhs_coef(h6_plan P) {
+  RhsCoef a{};
   for (int ax = 0; ax < 3; ++ax) {
     a.n[ax] = P->p.n[ax];
     a.dims[ax] = P->dims[ax];
@@ -143,7 +240,6 @@ hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* 
   const double h = P->p.h;
   const cplx I(0.0, 1.0), k = P->k, kap = P->kappa, ikh = I * k * h;
   a.h = h;
-  a.inv_sigma = 1.0 / sigma;
   const double h2 = h * h, h4 = h2 * h2;
   a.cK = d2(h2 * (1.0 - kap / 12.0 + kap * kap / 360.0));
   a.c_lap = d2(h2 * (h2 / 12.0) * (1.0 - kap / 30.0));
@@ -160,6 +256,18 @@ hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* 
   a.sC = d2(cplx(h4 / 120.0));
   a.e1mu3 = d2(std::exp(ikh) * mu3);
   a.mu1h5 = d2(mu1 * h * h4 / 3.0);
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
+                      double sigma, double2* F, hipStream_t s) {
+  if (nsrc > kMaxSrc) return hipErrorInvalidValue;
+  RhsArgs a{};
+  a.c = rhs_coef(P);
+  a.nsrc = nsrc;
+  a.inv_sigma = 1.0 / sigma;
   for (int i = 0; i < nsrc; ++i) {
     a.cx[i] = centres[3 * i];
     a.cy[i] = centres[3 * i + 1];
@@ -171,6 +279,60 @@ hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* 
   const size_t nb = (P->N + 255) / 256;
   hipLaunchKernelGGL(rhs_kernel, dim3(unsigned(nb)), dim3(256), 0, s, a, F);
   timing_end(P, KC_RHS, s, ev, double(P->N) * sizeof(double2));
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_separable(h6_plan P, int nterms, const double* coef, const double* const tab[3],
+                                double2* F, hipStream_t s) {
+  // device copy of the coefficients and the three factor tables, in one
+  // plan-owned buffer grown on demand
+  const size_t total = size_t(nterms) * (1 + 5 * (size_t(P->dims[0]) + P->dims[1] + P->dims[2]));
+  hipError_t e = hipSuccess;
+  if (total * sizeof(double2) > P->sep_bytes) {
+    (void)hipFree(P->d_sep);
+    P->d_sep = nullptr;
+    P->sep_bytes = 0;
+    e = hipMalloc(&P->d_sep, total * sizeof(double2));
+    if (e != hipSuccess) return e;
+    P->sep_bytes = total * sizeof(double2);
+  }
+  double2* base = static_cast<double2*>(P->d_sep);
+  const double2* dcoef = base;
+  const double2* dtab[3];
+  e = hipMemcpyAsync(base, coef, size_t(nterms) * sizeof(double2), hipMemcpyHostToDevice, s);
+  size_t at = size_t(nterms);
+  for (int ax = 0; ax < 3 && e == hipSuccess; ++ax) {
+    const size_t cnt = size_t(nterms) * 5 * P->dims[ax];
+    dtab[ax] = base + at;
+    e = hipMemcpyAsync(base + at, tab[ax], cnt * sizeof(double2), hipMemcpyHostToDevice, s);
+    at += cnt;
+  }
+  if (e != hipSuccess) return e;
+  hipEvent_t ev;
+  timing_begin(P, KC_RHS, s, &ev);
+  const size_t nb = (P->N + 255) / 256;
+  hipLaunchKernelGGL(rhs_separable_kernel, dim3(unsigned(nb)), dim3(256), 0, s, rhs_coef(P), nterms,
+                     dcoef, dtab[0], dtab[1], dtab[2], F);
+  timing_end(P, KC_RHS, s, ev, double(P->N) * sizeof(double2));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the host tables may be released once the call returns
+  return hipStreamSynchronize(s);
+}
+
+hipError_t launch_rhs_dirichlet_z(h6_plan P, int side, const double2* g, double2* F, hipStream_t s) {
+  PlaneRule r{};
+  r.nx = P->dims[0];
+  r.ny = P->dims[1];
+  r.xlo_n = P->p.bc[0] == H6_NEUMANN;
+  r.xhi_n = P->p.bc[1] == H6_NEUMANN;
+  r.ylo_n = P->p.bc[2] == H6_NEUMANN;
+  r.yhi_n = P->p.bc[3] == H6_NEUMANN;
+  const size_t plane = size_t(r.nx) * r.ny;
+  double2* Fp = F + (side == 0 ? size_t(0) : plane * (P->dims[2] - 1));
+  const double2 ca_ = d2((1.0 + P->kappa / 30.0) / 6.0);
+  const unsigned nb = unsigned((plane + 255) / 256);
+  hipLaunchKernelGGL(dirichlet_plane_kernel, dim3(nb), dim3(256), 0, s, g, Fp, r, ca_, 1.0 / 30.0);
   return hipGetLastError();
 }
 

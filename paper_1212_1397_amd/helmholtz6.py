@@ -28,7 +28,8 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
-            "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune")
+            "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune",
+            "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
                 "helmholtz6_learned_steps", "h6net_destroy")
@@ -84,6 +85,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_set_graphs.restype = ctypes.c_int
     lib.helmholtz6_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     lib.helmholtz6_autotune.restype = ctypes.c_int
+    lib.helmholtz6_rhs_separable.argtypes = [vp, ip] + [ctypes.POINTER(ctypes.c_double)] * 4 + [vp, vp]
+    lib.helmholtz6_rhs_separable.restype = ctypes.c_int
+    lib.helmholtz6_rhs_dirichlet_z.argtypes = [vp, ip, vp, vp, vp]
+    lib.helmholtz6_rhs_dirichlet_z.restype = ctypes.c_int
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
                  "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
@@ -192,6 +197,36 @@ class Plan:
             self._plan, int(c.shape[0]), c.ctypes.data_as(dp), ab.ctypes.data_as(dp), float(sigma),
             self._vec(out, "out"), _stream_handle(stream)))
         return out
+
+    def rhs_separable(self, coef, tx, ty, tz, out=None, stream=None):
+        """F for f = sum_s coef[s] X_s(x) Y_s(y) Z_s(z); tx, ty, tz: arrays of
+        shape (nterms, 5, n'_a) holding derivative orders 0..4 of each factor at
+        the unknown nodes of its axis (include/helmholtz6.h)."""
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128).reshape(-1))
+        nt = c.shape[0]
+        tabs = []
+        for name, t, n in (("tx", tx, self.dims[0]), ("ty", ty, self.dims[1]), ("tz", tz, self.dims[2])):
+            a = np.ascontiguousarray(np.asarray(t, dtype=np.complex128))
+            if a.shape != (nt, 5, n):
+                raise ValueError(f"{name} must have shape {(nt, 5, n)}, got {a.shape}")
+            tabs.append(a)
+        out = self.empty() if out is None else out
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(_lib.helmholtz6_rhs_separable(
+            self._plan, nt, c.ctypes.data_as(dp), *[a.ctypes.data_as(dp) for a in tabs],
+            self._vec(out, "out"), _stream_handle(stream)))
+        return out
+
+    def rhs_dirichlet_z(self, side: int, g, F, stream=None):
+        """F -= G g on the unknown plane next to Dirichlet z face `side` (0 or 1);
+        g: contiguous complex128 CUDA tensor of shape (n'y, n'x)."""
+        if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.complex128
+                and g.is_contiguous() and tuple(g.shape) == (self.dims[1], self.dims[0])):
+            raise ValueError(f"g must be a contiguous complex128 CUDA tensor of shape {(self.dims[1], self.dims[0])}")
+        self._check(_lib.helmholtz6_rhs_dirichlet_z(self._plan, int(side), ctypes.c_void_p(g.data_ptr()),
+                                                   self._vec(F, "F"), _stream_handle(stream)))
+        return F
 
     def solve(self, F, U=None, method="gmres", restart=30, maxit=1000, tol=1e-10, history=512,
               stream=None):

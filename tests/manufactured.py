@@ -41,3 +41,29 @@ def mixed_pattern_u(k):
 
 def source(u, k):
     return helmholtz_source(u, k)
+
+
+def factor_tables(f, pts):
+    """Inputs of helmholtz6_rhs_separable for a separable f: the term
+    coefficients and, per axis, the derivatives of orders 0..4 of each
+    factor at the unknown nodes pts = (x, y, z)."""
+    import numpy as np
+    coef = np.array([t.c for t in f.terms], dtype=np.complex128)
+    tabs = [np.stack([np.stack([getattr(t, fa).d(p, o) for o in range(5)]) for t in f.terms])
+            for fa, p in zip(("fx", "fy", "fz"), pts)]
+    return (coef, *tabs)
+
+
+def cuda_values(u, pts, device="cuda"):
+    """u at the tensor grid pts as a complex128 CUDA tensor of shape
+    (len(z), len(y), len(x)), built term by term on the device."""
+    import numpy as np
+    import torch
+    x, y, z = pts
+    out = torch.zeros((len(z), len(y), len(x)), dtype=torch.complex128, device=device)
+    for t in u.terms:
+        X = torch.from_numpy(np.asarray(t.fx.d(x, 0), dtype=np.complex128)).to(device)
+        Y = torch.from_numpy(np.asarray(t.fy.d(y, 0), dtype=np.complex128)).to(device)
+        Z = torch.from_numpy(np.asarray(t.fz.d(z, 0), dtype=np.complex128)).to(device)
+        out += t.c * Z[:, None, None] * Y[None, :, None] * X[None, None, :]
+    return out

@@ -125,3 +125,22 @@ def test_psi_order_matches_definition():
     assert math.isclose(h6.psi_order(2.0, 0.5, 3.0, 0.75, 2.0), 0.0, abs_tol=1e-15)
     assert math.isnan(h6.psi_order(0.0, 1.0, 1.0, 1.0, 2.0))
     assert math.isnan(h6.psi_order(1.0, 1.0, 1.0, 1.0, 1.0))
+
+
+def test_rhs_entry_points_reject_bad_arguments():
+    """Argument checks happen before any device work: a null plan is refused."""
+    from paper_1212_1397_amd import helmholtz6 as h6
+    lib = h6._lib
+    assert lib.helmholtz6_rhs_separable(None, 1, None, None, None, None, None, None) == h6.H6_ERR_ARG
+    assert lib.helmholtz6_rhs_dirichlet_z(None, 0, None, None, None) == h6.H6_ERR_ARG
+
+
+@pytest.mark.parametrize("n,precision", [((900, 8, 8), "fp64"), ((8, 1500, 8), "fp64"), ((8, 8, 600), "fp64"),
+                                         ((1500, 8, 8), "mixed")])
+def test_grids_beyond_kernel_limits_rejected(n, precision):
+    """Setup refuses grids whose transform lines or z lines exceed what one
+    workgroup holds (host-side checks, before any device allocation)."""
+    from paper_1212_1397_amd import helmholtz6 as h6
+    with pytest.raises(h6.H6Error) as e:
+        h6.Plan(n, 1.0 / (max(n) + 1), 2.0, precision=precision)
+    assert e.value.status == -1

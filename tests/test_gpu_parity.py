@@ -46,6 +46,11 @@ SMALL_CASES = [
     # n = 256 on x and y: the M = 257 FFT (Rader) transform path, both bases
     ((256, 256, 3), 30.0 + 0.3j, "DDNNSS"),
     ((256, 256, 2), 25.0, "NNDDDN"),
+    # the longest lines the kernels take: dense transforms with n'x = 511 and
+    # n'y = 513 (fewer y columns per workgroup), and n'z = 513 (32 z segments)
+    ((511, 3, 2), 20.0 + 0.2j, "DDNNSS"),
+    ((3, 511, 2), 20.0, "DDNNDN"),
+    ((5, 4, 511), 30.0 + 0.3j, "DDDDSS"),
 ]
 
 
