@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhelmholtz6.so")
 ARCH = os.environ.get("H6_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "solve.cpp", "stencil.hip", "precond.hip", "xform_rader.hip", "krylov.hip",
+SOURCES = ["abi.cpp", "solve.cpp", "stencil.hip", "precond.hip", "xform_rader.hip", "xform_dense.hip",
+           "krylov.hip",
            "rhs.hip", "unet.hip"]
 
 # Packed FP32 instructions are disabled for every device pass.

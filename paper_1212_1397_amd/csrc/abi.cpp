@@ -103,13 +103,42 @@ std::vector<double> mode_lambdas(const AxisXform& a) {
   return l;
 }
 
-std::vector<double> trig_table(int M) {
-  std::vector<double> t(4 * M);
-  for (int i = 0; i < 2 * M; ++i) {
-    t[i] = std::sin(M_PI * i / M);
-    t[2 * M + i] = std::cos(M_PI * i / M);
-  }
-  return t;
+// Basis matrices of the dense transforms of one axis (xform_dense.hip), in
+// the compute precision R: forward then inverse, each [Lm][Lq] row-major
+// (row m = output, column q = input), zero-padded.  Inverse: W_mq =
+// sin(pi (q+1)(m+1) / M) (sine basis) or cos(pi q m / M) (cosine basis);
+// forward W^{-1} = (2/M) W (sine) or (2/M) C W C, C = diag(1/2, 1, .., 1, 1/2)
+// (cosine).  Angles are reduced modulo 2M in integers.
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s);
+
+template <typename R>
+hipError_t build_dense(AxisXform& ax, hipStream_t s) {
+  const int L = ax.L, M = ax.M;
+  ax.Lm = (L + 63) / 64 * 64;
+  ax.Lq = (L + 15) / 16 * 16;
+  const size_t one = size_t(ax.Lm) * ax.Lq;
+  std::vector<R> h(2 * one, R(0));
+  for (int m = 0; m < L; ++m)
+    for (int q = 0; q < L; ++q) {
+      double inv, fwd;
+      if (!ax.neumann) {
+        const long long t = (long long)(q + 1) * (m + 1) % (2 * M);
+        inv = std::sin(M_PI * double(t) / M);
+        fwd = (2.0 / M) * inv;
+      } else {
+        const long long t = (long long)q * m % (2 * M);
+        inv = std::cos(M_PI * double(t) / M);
+        const double cq = (q == 0 || q == L - 1) ? 0.5 : 1.0, sm = (m == 0 || m == L - 1) ? 0.5 : 1.0;
+        fwd = (2.0 / M) * sm * cq * inv;
+      }
+      h[size_t(m) * ax.Lq + q] = R(fwd);
+      h[one + size_t(m) * ax.Lq + q] = R(inv);
+    }
+  R* d = nullptr;
+  const hipError_t e = upload(&d, h, s);
+  ax.wmat = d;
+  return e;
 }
 
 // T_z of eq. (3DAP): tridiag(1, -2, 1), corner entry 2 next to a Neumann or
@@ -263,8 +292,7 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->d_stencil);
   (void)hipFree(P->d_lambda_x);
   (void)hipFree(P->d_lambda_y);
-  (void)hipFree(P->d_trig_x);
-  (void)hipFree(P->d_trig_y);
+  for (auto& a : P->ax) (void)hipFree(a.wmat);
   (void)hipFree(P->d_tri);
   (void)hipFree(P->d_cstart);
   for (void* w : P->w_pc) (void)hipFree(w);
@@ -338,9 +366,9 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
     P->ax[a].L = P->dims[a];
     P->ax[a].M = p->n[a] + 1;
     P->ax[a].neumann = p->bc[2 * a] == H6_NEUMANN;
-    if (!dense_transform_fits(a, P->ax[a].L, P->ax[a].M, p->precision == H6_MIXED)) {
+    if (P->ax[a].L > kMaxLine) {
       err = std::string("n'") + (a == 0 ? "x" : "y") + " = " + std::to_string(P->ax[a].L) +
-            " exceeds the transform limit (line and tables must fit one workgroup's LDS)";
+            " exceeds the transform limit of " + std::to_string(kMaxLine);
       free_plan(P);
       return H6_ERR_ARG;
     }
@@ -372,8 +400,8 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   if (e == hipSuccess) e = upload(&P->d_stencil, st, s);
   if (e == hipSuccess) e = upload(&P->d_lambda_x, lx, s);
   if (e == hipSuccess) e = upload(&P->d_lambda_y, ly, s);
-  if (e == hipSuccess) e = upload(&P->d_trig_x, trig_table(P->ax[0].M), s);
-  if (e == hipSuccess) e = upload(&P->d_trig_y, trig_table(P->ax[1].M), s);
+  for (int a = 0; a < 2 && e == hipSuccess; ++a)
+    e = p->precision == H6_MIXED ? build_dense<float>(P->ax[a], s) : build_dense<double>(P->ax[a], s);
   if (e == hipSuccess) e = upload(&P->d_tri, tri, s);
   if (e == hipSuccess) {
     if (p->precision == H6_MIXED) {

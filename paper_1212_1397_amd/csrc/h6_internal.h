@@ -53,6 +53,8 @@ struct AxisXform {
   int neumann = 0;  // 0: DST-I pair, 1: DCT-I pair
   int fast = 0;     // 1: Rader FFT path (M = 257), 0: dense sums in LDS
   int lines = 0;    // Rader path: lines (x) / columns (y) per workgroup (autotuned)
+  void* wmat = nullptr;   // dense path: forward then inverse basis matrix, [Lm][Lq] each
+  int Lm = 0, Lq = 0;     // padded rows (multiple of 64) and columns (multiple of 16)
   RaderTables rader{};
   void* rader_mem = nullptr;   // one device allocation holding the tables
 };
@@ -93,8 +95,6 @@ struct h6_plan_s {
   h6::StencilTable* d_stencil = nullptr;
   double* d_lambda_x = nullptr;     // transverse eigenvalues per mode
   double* d_lambda_y = nullptr;
-  double* d_trig_x = nullptr;       // sin, cos (pi t / M), t = 0..2M-1 (2 * 2M doubles)
-  double* d_trig_y = nullptr;
   double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
   void* d_cstart = nullptr;         // Thomas c' entering each z segment: [z_segments(n'z)][n'x n'y], complex
                                     // (double2, or float2 in mixed plans)
@@ -177,9 +177,15 @@ hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStrea
 // callers that only hand r to a complex64 preconditioner
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
                                double* partials, int* nparts, hipStream_t s);
-// whether the dense transform along axis (0: x, 1: y) of line length L fits
-// the LDS budget of one workgroup (checked at setup)
-bool dense_transform_fits(int axis, int L, int M, bool f32);
+// Dense (matrix-core) transforms along x / y with the axis' basis matrices
+// (xform_dense.hip); acc != 0: out += result
+template <typename R, typename Tin, typename Tout>
+hipError_t launch_dense_x(const AxisXform& X, bool inverse, const Tin* in, Tout* out, int nlines, int acc,
+                          hipStream_t s);
+template <typename R, typename T2>
+hipError_t launch_dense_y(const AxisXform& Y, bool inverse, const T2* in, T2* out, int nx, int nz,
+                          hipStream_t s);
+constexpr int kMaxLine = 4096;    // largest n'x, n'y (basis matrices of the dense transforms)
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
 // tab[a]: host complex128 samples, nterms x 5 derivative orders x dims[a]; synchronises s

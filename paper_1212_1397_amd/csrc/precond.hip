@@ -9,8 +9,11 @@
 // W_qm = cos(pi q m / M) (q, m = 0..M); W^{-1} = (2/M) W^T and
 // (2/M) C W^T C (C = diag(1/2, 1, .., 1, 1/2)) respectively.
 //
-// Compute type R is double (FP64 plans) or float (mixed plans, complex64
-// intermediates); the input r and output z are complex128 in both.
+// Steps 1, 2, 4, 5 use the Rader FFT path for M = 257 (xform_rader.hip) and
+// the dense basis-matrix products on the matrix cores otherwise
+// (xform_dense.hip).  Compute type R is double (FP64 plans) or float (mixed
+// plans, complex64 intermediates); the input r and output z are complex128 in
+// both.
 #include <type_traits>
 
 #include "h6_internal.h"
@@ -36,116 +39,6 @@ __device__ __forceinline__ Tdst cvt(Tsrc v) {
   d.x = v.x;
   d.y = v.y;
   return d;
-}
-
-// out_m = scale_m * sum_q coef(q, m) * w_q * buf[q * es]: the dense sum of
-// one output of a DST-I / DCT-I pair (see the file header).
-template <typename R>
-__device__ __forceinline__ typename C2<R>::T dense_out(const typename C2<R>::T* buf, int es, int L,
-                                                       int M, int neumann, int inverse, int m,
-                                                       const R* sinT, const R* cosT) {
-  const int twoM = 2 * M;
-  R sx = 0, sy = 0;
-  if (!neumann) {
-    const int step = m + 1;
-    int t = step;
-    for (int q = 0; q < L; ++q) {
-      const R c = sinT[t];
-      const typename C2<R>::T v = buf[q * es];
-      sx += c * v.x;
-      sy += c * v.y;
-      t += step;
-      if (t >= twoM) t -= twoM;
-    }
-    if (!inverse) {
-      const R s = R(2) / R(M);
-      sx *= s;
-      sy *= s;
-    }
-  } else {
-    int t = 0;
-    for (int q = 0; q < L; ++q) {
-      R c = cosT[t];
-      if (!inverse && (q == 0 || q == L - 1)) c *= R(0.5);
-      const typename C2<R>::T v = buf[q * es];
-      sx += c * v.x;
-      sy += c * v.y;
-      t += m;
-      if (t >= twoM) t -= twoM;
-    }
-    if (!inverse) {
-      R s = R(2) / R(M);
-      if (m == 0 || m == L - 1) s *= R(0.5);
-      sx *= s;
-      sy *= s;
-    }
-  }
-  return mk<R>(sx, sy);
-}
-
-constexpr int kXLines = 4;      // x lines per workgroup
-constexpr int kYCols = 8;       // most x columns per y-transform workgroup (fewer for long lines)
-constexpr size_t kDenseLds = 65536;   // LDS budget of one dense-transform workgroup
-
-template <typename Tin, typename Tout, typename R>
-__global__ __launch_bounds__(256) void xform_x_kernel(const Tin* __restrict__ in,
-                                                      Tout* __restrict__ out, int nlines, int L,
-                                                      int M, int neumann, int inverse,
-                                                      const double* __restrict__ trig, int acc) {
-  using T2 = typename C2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  R* sinT = reinterpret_cast<R*>(smem_raw);
-  R* cosT = sinT + 2 * M;
-  T2* buf = reinterpret_cast<T2*>(cosT + 2 * M + ((4 * M) & 1));
-  for (int t = threadIdx.x; t < 2 * M; t += blockDim.x) {
-    sinT[t] = R(trig[t]);
-    cosT[t] = R(trig[2 * M + t]);
-  }
-  const int line0 = blockIdx.x * kXLines;
-  const int nl = min(kXLines, nlines - line0);
-  const size_t base = size_t(line0) * L;
-  for (int e = threadIdx.x; e < nl * L; e += blockDim.x) buf[e] = cvt<T2>(in[base + e]);
-  __syncthreads();
-  for (int e = threadIdx.x; e < nl * L; e += blockDim.x) {
-    const int b = e / L, m = e - b * L;
-    Tout v = cvt<Tout>(dense_out<R>(buf + b * L, 1, L, M, neumann, inverse, m, sinT, cosT));
-    if (acc) {                    // out += result
-      const Tout o = out[base + e];
-      v.x += o.x;
-      v.y += o.y;
-    }
-    out[base + e] = v;
-  }
-}
-
-template <typename T2in, typename R>
-__global__ __launch_bounds__(256) void xform_y_kernel(const T2in* __restrict__ in,
-                                                      T2in* __restrict__ out, int nx, int L,
-                                                      int M, int neumann, int inverse,
-                                                      const double* __restrict__ trig, int cols) {
-  using T2 = typename C2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  R* sinT = reinterpret_cast<R*>(smem_raw);
-  R* cosT = sinT + 2 * M;
-  T2* buf = reinterpret_cast<T2*>(cosT + 2 * M + ((4 * M) & 1));
-  for (int t = threadIdx.x; t < 2 * M; t += blockDim.x) {
-    sinT[t] = R(trig[t]);
-    cosT[t] = R(trig[2 * M + t]);
-  }
-  const int i0 = blockIdx.x * cols;
-  const int nc = min(cols, nx - i0);
-  const size_t zoff = size_t(blockIdx.y) * nx * L;
-  for (int e = threadIdx.x; e < L * cols; e += blockDim.x) {
-    const int q = e / cols, c = e - q * cols;
-    if (c < nc) buf[c * L + q] = cvt<T2>(in[zoff + size_t(q) * nx + i0 + c]);
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < L * cols; e += blockDim.x) {
-    const int m = e / cols, c = e - m * cols;
-    if (c < nc)
-      out[zoff + size_t(m) * nx + i0 + c] =
-          cvt<T2in>(dense_out<R>(buf + c * L, 1, L, M, neumann, inverse, m, sinT, cosT));
-  }
 }
 
 template <typename R>
@@ -310,13 +203,6 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   const AxisXform& X = P->ax[0];
   const AxisXform& Y = P->ax[1];
   const int nlines_x = ny * nz;
-  const size_t shx = 4 * X.M * sizeof(R) + sizeof(R) + kXLines * X.L * sizeof(T2) + 16;
-  auto shy_of = [&](int cols) { return 4 * Y.M * sizeof(R) + sizeof(R) + cols * Y.L * sizeof(T2) + 16; };
-  int ycols = kYCols;
-  while (ycols > 1 && shy_of(ycols) > kDenseLds) ycols /= 2;
-  const size_t shy = shy_of(ycols);
-  if ((!X.fast && shx > kDenseLds) || (!Y.fast && shy > kDenseLds)) return hipErrorInvalidConfiguration;
-  const dim3 gx((nlines_x + kXLines - 1) / kXLines), gy((nx + ycols - 1) / ycols, nz);
   hipEvent_t ev;
 
   const double Nd = double(P->N);
@@ -325,10 +211,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
     if (X.fast)
       (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines);
     else
-      hipLaunchKernelGGL((xform_x_kernel<std::remove_cv_t<std::remove_pointer_t<decltype(src)>>,
-                                         std::remove_pointer_t<decltype(dst)>, R>),
-                         gx, dim3(256), shx, s, src, dst, nlines_x, X.L, X.M, X.neumann, inv ? 1 : 0,
-                         P->d_trig_x, accumulate);
+      (void)launch_dense_x<R>(X, inv, src, dst, nlines_x, accumulate, s);
     timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst) * (accumulate ? 2 : 1)));
   };
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
@@ -336,8 +219,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
     if (Y.fast)
       (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines);
     else
-      hipLaunchKernelGGL((xform_y_kernel<T2, R>), gy, dim3(256), shy, s, src, dst, nx, Y.L, Y.M,
-                         Y.neumann, inv ? 1 : 0, P->d_trig_y, ycols);
+      (void)launch_dense_y<R>(Y, inv, src, dst, nx, nz, s);
     timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
   if (part & PINV_FIRST) xform_x(false, r, w0, 0);
@@ -367,12 +249,6 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
 }
 
 }  // namespace
-
-bool dense_transform_fits(int axis, int L, int M, bool f32) {
-  const size_t rs = f32 ? sizeof(float) : sizeof(double);
-  const size_t rows = axis == 0 ? kXLines : 1;
-  return 4 * size_t(M) * rs + rs + rows * size_t(L) * 2 * rs + 16 <= kDenseLds;
-}
 
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part) {
   if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, z, s, part);

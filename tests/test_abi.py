@@ -135,11 +135,13 @@ def test_rhs_entry_points_reject_bad_arguments():
     assert lib.helmholtz6_rhs_dirichlet_z(None, 0, None, None, None) == h6.H6_ERR_ARG
 
 
-@pytest.mark.parametrize("n,precision", [((900, 8, 8), "fp64"), ((8, 1500, 8), "fp64"), ((8, 8, 600), "fp64"),
-                                         ((1500, 8, 8), "mixed")])
+@pytest.mark.parametrize("n,precision", [((5000, 8, 8), "fp64"), ((8, 5000, 8), "fp64"), ((8, 8, 600), "fp64"),
+                                         ((4100, 8, 8), "mixed")])
 def test_grids_beyond_kernel_limits_rejected(n, precision):
-    """Setup refuses grids whose transform lines or z lines exceed what one
-    workgroup holds (host-side checks, before any device allocation)."""
+    """Setup refuses grids beyond the kernels' limits: z lines longer than the
+    partitioned solver holds (n'z > 544), x / y lines longer than 4096 (the
+    dense transforms' basis matrices); host-side checks, before any device
+    allocation."""
     from paper_1212_1397_amd import helmholtz6 as h6
     with pytest.raises(h6.H6Error) as e:
         h6.Plan(n, 1.0 / (max(n) + 1), 2.0, precision=precision)
