@@ -179,12 +179,18 @@ double helmholtz6_psi_order(double r1_h, double r2_h, double r1_gh, double r2_gh
 h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* const* U,
                                  h6_solve_info* infos, h6_status* statuses, int count, int nstreams);
 
-/* Captures each Arnoldi step of GMRES / FGMRES solves on the plan as a HIP
- * graph (one per step index, built on first use and replayed by later
- * solves; rebuilt when the workspace grows) and runs the solve on a
- * plan-owned stream ordered after hip_stream.  Graphs are not used while
- * kernel timing is enabled or a learned correction is attached.
- * enable = 0 releases them. */
+/* HIP graphs for GMRES / FGMRES solves on the plan, run on a plan-owned
+ * stream ordered after hip_stream; built on first use, replayed by later
+ * solves, rebuilt when the workspace, restart length or solution vector
+ * changes.  enable = 1: one graph per Arnoldi step; the host applies the
+ * Givens rotations and decides after every step.  enable = 2: one graph per
+ * restart cycle; the rotations and the least-squares solution are computed on
+ * the device, a device flag set when the estimate meets the tolerance (or
+ * the step budget, or a breakdown) makes the remaining steps' kernels return
+ * at once, and the host waits once per cycle (iterates equal mode 1's up to
+ * rounding).  Graphs are not used while kernel timing is enabled or a learned
+ * correction is attached.  enable = 0 releases them; other values give
+ * H6_ERR_ARG. */
 h6_status helmholtz6_set_graphs(h6_plan plan, int enable);
 
 /* Autotuner: times the variants of the plan's kernels on the plan's own grid

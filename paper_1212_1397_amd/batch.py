@@ -17,7 +17,7 @@ from . import helmholtz6 as h6
 from .workloads import batch_workload
 
 
-def run(count: int = 96, streams: int = 4, graphs: bool = True, tune: bool = True, seed: int = 4,
+def run(count: int = 96, streams: int = 4, graphs=True, tune: bool = True, seed: int = 4,
         log=None):
     """Seconds for the sequential plain solves and for the batched solves
     (mixed FGMRES(30) to 1e-8), iteration counts and agreement."""
@@ -75,9 +75,12 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=96)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--cycle-graphs", action="store_true",
+                    help="one graph per restart cycle (device Givens) instead of one per step")
     ap.add_argument("--no-tune", action="store_true")
     a = ap.parse_args(argv)
-    print(json.dumps(run(a.count, a.streams, not a.no_graphs, not a.no_tune)), flush=True)
+    graphs = False if a.no_graphs else ("cycle" if a.cycle_graphs else True)
+    print(json.dumps(run(a.count, a.streams, graphs, not a.no_tune)), flush=True)
 
 
 if __name__ == "__main__":

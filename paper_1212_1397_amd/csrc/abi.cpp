@@ -286,6 +286,7 @@ hipError_t build_rader(AxisXform& ax, hipStream_t s) {
 void free_plan(h6_plan P) {
   if (!P) return;
   release_graphs(P);
+  (void)hipFree(P->d_givens);
   if (P->gstream) (void)hipStreamDestroy(P->gstream);
   if (P->ev_order) (void)hipEventDestroy(P->ev_order);
   for (auto& a : P->ax) (void)hipFree(a.rader_mem);
@@ -840,8 +841,12 @@ h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* con
 
 h6_status helmholtz6_set_graphs(h6_plan P, int enable) {
   if (!P) return H6_ERR_ARG;
-  P->use_graphs = enable != 0;
-  if (!enable) release_graphs(P);
+  if (enable < 0 || enable > 2) {
+    P->last_error = "set_graphs: mode must be 0, 1 or 2";
+    return H6_ERR_ARG;
+  }
+  if (enable != P->use_graphs) release_graphs(P);
+  P->use_graphs = enable;
   return H6_OK;
 }
 

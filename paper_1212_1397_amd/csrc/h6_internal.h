@@ -73,9 +73,11 @@ struct Timing {
 struct GraphKey {
   void* V = nullptr;
   void* Z = nullptr;
-  int m = 0, flex = 0, mixed = 0;
+  void* U = nullptr;                    // solution vector (whole-cycle graphs update it)
+  int m = 0, flex = 0, mixed = 0, mode = 0;
   bool operator==(const GraphKey& o) const {
-    return V == o.V && Z == o.Z && m == o.m && flex == o.flex && mixed == o.mixed;
+    return V == o.V && Z == o.Z && U == o.U && m == o.m && flex == o.flex && mixed == o.mixed &&
+           mode == o.mode;
   }
 };
 
@@ -114,10 +116,14 @@ struct h6_plan_s {
   void* d_sep = nullptr;  size_t sep_bytes = 0;  // separable-source tables (helmholtz6_rhs_separable)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
   struct h6_net_s* net = nullptr;              // learned correction for FGMRES (not owned)
-  bool use_graphs = false;                     // capture GMRES steps as HIP graphs
+  int use_graphs = 0;                          // 1: capture GMRES steps as HIP graphs, 2: whole cycles
+  const int* skip = nullptr;                   // while a cycle graph is captured: device stop flag that
+                                               // every kernel of an Arnoldi step checks on entry
+  double* d_givens = nullptr;  int givens_dim = 0;  // device least-squares state of cycle graphs
   hipStream_t gstream = nullptr;               // plan-owned stream of graph-mode solves
   hipEvent_t ev_order = nullptr;               // orders gstream after the caller's stream
-  std::vector<hipGraphExec_t> step_graphs;     // one per step index
+  std::vector<hipGraphExec_t> step_graphs;     // one per step index (mode 1)
+  hipGraphExec_t cycle_graph = nullptr;        // one restart cycle (mode 2)
   h6::GraphKey graph_key;
   int stencil_tz = 16;                         // autotuned stencil z-chunk (8, 16 or 32)
   bool spec_done = false;                      // exact spectrum bounds of A A_p^{-1} (Dirichlet)
@@ -181,10 +187,10 @@ hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const dou
 // (xform_dense.hip); acc != 0: out += result
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_dense_x(const AxisXform& X, bool inverse, const Tin* in, Tout* out, int nlines, int acc,
-                          hipStream_t s);
+                          hipStream_t s, const int* skip = nullptr);
 template <typename R, typename T2>
 hipError_t launch_dense_y(const AxisXform& Y, bool inverse, const T2* in, T2* out, int nx, int nz,
-                          hipStream_t s);
+                          hipStream_t s, const int* skip = nullptr);
 constexpr int kMaxLine = 4096;    // largest n'x, n'y (basis matrices of the dense transforms)
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
                       double sigma, double2* F, hipStream_t s);
@@ -197,11 +203,12 @@ hipError_t launch_rhs_dirichlet_z(h6_plan P, int side, const double2* g, double2
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s);
 hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
 // out[2i..2i+1] = <q_i, w> for i < m, q_i = Q + i n
+// skip (all Arnoldi-step launchers): device flag; when nonzero the kernels return at once
 hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n, double* partials,
-                             double* out, hipStream_t s);
+                             double* out, hipStream_t s, const int* skip = nullptr);
 // w -= sum_{i<m} c_i q_i; out[0] = |w|^2, out[1+2i..2+2i] = <q_i, w> for i < min(m, kGramMax)
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
-                              double* partials, double* out, hipStream_t s);
+                              double* partials, double* out, hipStream_t s, const int* skip = nullptr);
 // MGS coefficients of Arnoldi step j on the device (one workgroup), from the
 // block dots <q~_i, w~> (dots, i <= j), the norm / Gram row of the last update
 // pass (nrow: |q~_j|^2, <q~_i, q~_j> for i < min(j, kGramMax)) and the extra
@@ -210,7 +217,7 @@ hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, in
 // coefficients c_i = nu_j h_i / nu_i (coef).
 hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
                            double* nu, double2* G, int gdim, double2* hcol, double2* coef,
-                           hipStream_t s);
+                           hipStream_t s, const int* skip = nullptr);
 // out = |a - b|^2 (device double)
 hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
                              hipStream_t s);
@@ -218,10 +225,36 @@ hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, doubl
 hipError_t net_apply_add(struct h6_net_s* net, const double2* q, double kh, void* z, bool z_f32,
                          hipStream_t s);
 bool net_matches(struct h6_net_s* net, const int dims[3]);
+// out (+)= sum_{i < count} y_i V_i, count = min(m, *mdev) when mdev is given (device int)
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
-                             int accumulate, hipStream_t s);     // out (+)= sum_i y_i V_i
+                             int accumulate, hipStream_t s, const int* mdev = nullptr);
 hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y, int m, size_t n,
-                                 int accumulate, hipStream_t s);
+                                 int accumulate, hipStream_t s, const int* mdev = nullptr);
+// Least-squares state of a whole-cycle graph (device, one restart cycle of
+// at most m steps): g (m + 1 complex), cosines (m), sines (m complex), the
+// rotated Hessenberg R (m x m complex, column-major), per-step residual
+// estimates (m), and int slots: stop flag, steps done.
+struct GivensState {
+  double2* g;
+  double* cs;
+  double2* sn;
+  double2* R;
+  double* est;
+  int* stop;
+  int* jdone;
+};
+GivensState givens_state(h6_plan P, int m);
+size_t givens_bytes(int m);
+// step j of the cycle: Hessenberg column (hcol, h_{i,j}, i <= j) and
+// H(j+1, j) = sqrt(nrow[0]) / nu[j]; previous rotations, new rotation, g,
+// estimate |g_{j+1}| / prm[1]; stop when it is <= prm[2], when j + 1 reaches
+// prm[0] steps, or on breakdown.  prm: (steps allowed, ||F||, tol) doubles.
+hipError_t launch_givens_step(int j, const double* nrow, const double* nu, const double2* hcol,
+                              GivensState st, int m, const double* prm, hipStream_t s);
+// y = R^{-1} g over the steps done, divided by nu_i (unnormalised basis), into y[0..m)
+hipError_t launch_lsq_solve(int m, GivensState st, const double* nu, double2* y, hipStream_t s);
+// device int slot <- 0 (a one-thread kernel; keeps memset nodes out of graphs)
+hipError_t launch_clear_int(int* p, hipStream_t s);
 
 // timing helpers
 void timing_begin(h6_plan P, int cls, hipStream_t s, hipEvent_t* a);

@@ -77,7 +77,9 @@ __global__ __launch_bounds__(kThreads) void diff_norm2_kernel(const double2* __r
 template <int CNT>
 __global__ __launch_bounds__(kThreads) void block_dots_kernel(const double2* __restrict__ Q, int i0,
                                                               const double2* __restrict__ w,
-                                                              size_t n, double* __restrict__ partials) {
+                                                              size_t n, double* __restrict__ partials,
+                                                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
   double acc[2 * CNT];
 #pragma unroll
   for (int c = 0; c < 2 * CNT; ++c) acc[c] = 0.0;
@@ -105,7 +107,9 @@ template <int MG>
 __global__ __launch_bounds__(kThreads) void update_gram_kernel(double2* __restrict__ w,
                                                                const double2* __restrict__ Q,
                                                                const double2* __restrict__ c, int m,
-                                                               size_t n, double* __restrict__ partials) {
+                                                               size_t n, double* __restrict__ partials,
+                                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
   double acc[1 + 2 * MG];
 #pragma unroll
   for (int i = 0; i < 1 + 2 * MG; ++i) acc[i] = 0.0;
@@ -158,7 +162,9 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
                                                       const double* __restrict__ gram2,
                                                       double* __restrict__ nu, double2* __restrict__ G,
                                                       int gdim, double2* __restrict__ hcol,
-                                                      double2* __restrict__ coef) {
+                                                      double2* __restrict__ coef,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double2 h[kCoefMax];
   const int t = threadIdx.x;
   const double nuj = sqrt(fmax(nrow[0], 0.0));
@@ -202,7 +208,9 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
 
 // out[c] = sum_b partials[c * nblocks + b], one block per component
 __global__ __launch_bounds__(kThreads) void reduce_cols_kernel(const double* __restrict__ partials,
-                                                               int nblocks, double* __restrict__ out) {
+                                                               int nblocks, double* __restrict__ out,
+                                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double s[kThreads];
   double a = 0.0;
   const double* p = partials + size_t(blockIdx.x) * nblocks;
@@ -223,8 +231,10 @@ template <typename TV>
 __global__ __launch_bounds__(kThreads) void multi_axpy_kernel(double2* __restrict__ out,
                                                               const TV* __restrict__ V,
                                                               const double2* __restrict__ y, int m,
-                                                              size_t n, int accumulate) {
+                                                              size_t n, int accumulate,
+                                                              const int* __restrict__ mdev) {
   constexpr int kU = 8;
+  if (mdev) m = min(m, *mdev);
   for (size_t i = blockIdx.x * size_t(kThreads) + threadIdx.x; i < n; i += size_t(gridDim.x) * kThreads) {
     double2 acc = accumulate ? out[i] : make_double2(0.0, 0.0);
     for (int j = 0; j < m; j += kU) {
@@ -256,6 +266,87 @@ __global__ __launch_bounds__(kThreads) void cheb_update_kernel(double2* __restri
   }
 }
 
+// Complex Givens rotation (c real, s complex) with [c s; -conj(s) c] [a; b] = [r; 0], b real >= 0.
+__device__ void givens_rot(double2 a, double b, double& c, double2& s, double2& r) {
+  const double aa = hypot(a.x, a.y);
+  if (b == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); r = a; return; }
+  if (aa == 0.0) { c = 0.0; s = make_double2(1.0, 0.0); r = make_double2(b, 0.0); return; }
+  const double t = hypot(aa, b);
+  const double2 ph = make_double2(a.x / aa, a.y / aa);
+  c = aa / t;
+  s = make_double2(ph.x * b / t, ph.y * b / t);
+  r = make_double2(ph.x * t, ph.y * t);
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// One step of the least-squares update of a whole-cycle graph (one thread;
+// the same arithmetic as the host path of the per-step solver).
+__global__ __launch_bounds__(64) void givens_step_kernel(int j, int m, const double* __restrict__ nrow,
+                                                         const double* __restrict__ nu,
+                                                         const double2* __restrict__ hcol, GivensState st,
+                                                         const double* __restrict__ prm) {
+  if (*st.stop) return;
+  if (threadIdx.x != 0) return;
+  double2* Rj = st.R + size_t(j) * m;
+  for (int i = 0; i <= j; ++i) Rj[i] = hcol[i];
+  const double nuj = nu[j];
+  const double hn = sqrt(fmax(nrow[0], 0.0)) / nuj;
+  if (j == 0) st.g[0] = make_double2(nuj, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double c = st.cs[i];
+    const double2 sn = st.sn[i], a = Rj[i], b = Rj[i + 1];
+    const double2 t = make_double2(c * a.x + zmul(sn, b).x, c * a.y + zmul(sn, b).y);
+    const double2 u = zmul(zconj(sn), a);
+    Rj[i + 1] = make_double2(-u.x + c * b.x, -u.y + c * b.y);
+    Rj[i] = t;
+  }
+  double c;
+  double2 sr, rr;
+  givens_rot(Rj[j], hn, c, sr, rr);
+  st.cs[j] = c;
+  st.sn[j] = sr;
+  Rj[j] = rr;
+  const double2 gj = st.g[j];
+  const double2 gn = zmul(zconj(sr), gj);
+  st.g[j + 1] = make_double2(-gn.x, -gn.y);
+  st.g[j] = make_double2(c * gj.x, c * gj.y);
+  const double est = hypot(gn.x, gn.y) / prm[1];
+  st.est[j] = est;
+  *st.jdone = j + 1;
+  const bool breakdown = !(hn > 1e-300);
+  if (est <= prm[2] || double(j + 1) >= prm[0] || breakdown || !isfinite(est)) *st.stop = 1;
+}
+
+// y = R^{-1} g over the steps done; y_i / nu_i for the unnormalised basis;
+// zero beyond (one thread)
+__global__ __launch_bounds__(64) void lsq_solve_kernel(int m, GivensState st, const double* __restrict__ nu,
+                                                       double2* __restrict__ y) {
+  if (threadIdx.x != 0) return;
+  const int jd = min(max(*st.jdone, 0), m);
+  for (int i = m - 1; i >= jd; --i) y[i] = make_double2(0.0, 0.0);
+  for (int i = jd - 1; i >= 0; --i) {
+    double2 acc = st.g[i];
+    for (int k = i + 1; k < jd; ++k) {
+      const double2 p = zmul(st.R[size_t(k) * m + i], y[k]);
+      acc.x -= p.x;
+      acc.y -= p.y;
+    }
+    const double2 d = st.R[size_t(i) * m + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    y[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+  }
+  // the basis is stored unnormalised: coefficients of q~_i are y_i / nu_i
+  for (int i = 0; i < jd; ++i) y[i] = make_double2(y[i].x / nu[i], y[i].y / nu[i]);
+}
+
+__global__ void clear_int_kernel(int* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
 int grid_for(size_t n) {
   const size_t b = (n + kThreads - 1) / kThreads;
   return int(b < size_t(kRedBlocks) ? (b > 0 ? b : 1) : kRedBlocks);
@@ -268,28 +359,31 @@ constexpr int kGramChunk = kGramMax;
 
 hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
                            double* nu, double2* G, int gdim, double2* hcol, double2* coef,
-                           hipStream_t s) {
+                           hipStream_t s, const int* skip) {
   if (j < 0 || j >= kCoefMax || j >= gdim) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mgs_coef_kernel, dim3(1), dim3(64), 0, s, j, dots, nrow, gram2, nu, G, gdim,
-                     hcol, coef);
+                     hcol, coef, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s) {
   hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, n, partials);
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out,
+                     static_cast<const int*>(nullptr));
   return hipGetLastError();
 }
 
 hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
                              hipStream_t s) {
   hipLaunchKernelGGL(diff_norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, b, n, partials);
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out,
+                     static_cast<const int*>(nullptr));
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, out);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, out,
+                     static_cast<const int*>(nullptr));
   return hipGetLastError();
 }
 
@@ -315,7 +409,7 @@ int reduction_blocks() {
 #define H6_COUNTS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n, double* partials,
-                             double* out, hipStream_t s) {
+                             double* out, hipStream_t s, const int* skip) {
   // one grid size for all chunks (the partials of all 2m components are
   // reduced together)
   const int nb = reduction_blocks();
@@ -324,32 +418,32 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
     switch (cnt) {
 #define H6_DOTS(C)                                                                                \
   case C:                                                                                         \
-    hipLaunchKernelGGL(block_dots_kernel<C>, dim3(nb), dim3(kThreads), 0, s, Q, i0, w, n, partials); \
+    hipLaunchKernelGGL(block_dots_kernel<C>, dim3(nb), dim3(kThreads), 0, s, Q, i0, w, n, partials, skip); \
     break;
       H6_COUNTS(H6_DOTS)
 #undef H6_DOTS
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(2 * m), dim3(kThreads), 0, s, partials, nb, out);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(2 * m), dim3(kThreads), 0, s, partials, nb, out, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
-                              double* partials, double* out, hipStream_t s) {
+                              double* partials, double* out, hipStream_t s, const int* skip) {
   const int nb = reduction_blocks();
   const int mg = m < kGramChunk ? m : kGramChunk;
   if (mg < 1) return hipErrorInvalidValue;
   switch (mg) {
 #define H6_UPD(C)                                                                                  \
   case C:                                                                                          \
-    hipLaunchKernelGGL(update_gram_kernel<C>, dim3(nb), dim3(kThreads), 0, s, w, Q, c, m, n, partials); \
+    hipLaunchKernelGGL(update_gram_kernel<C>, dim3(nb), dim3(kThreads), 0, s, w, Q, c, m, n, partials, skip); \
     break;
     H6_COUNTS(H6_UPD)
 #undef H6_UPD
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out, skip);
   return hipGetLastError();
 }
 
@@ -360,16 +454,51 @@ hipError_t launch_cheb_update(double2* e, const double2* t, double2* U, double c
 }
 
 hipError_t launch_multi_axpy(double2* out, const double2* V, const double2* y, int m, size_t n,
-                             int accumulate, hipStream_t s) {
+                             int accumulate, hipStream_t s, const int* mdev) {
   hipLaunchKernelGGL(multi_axpy_kernel<double2>, dim3(grid_for(n)), dim3(kThreads), 0, s, out, V, y, m,
-                     n, accumulate);
+                     n, accumulate, mdev);
   return hipGetLastError();
 }
 
 hipError_t launch_multi_axpy_f32(double2* out, const float2* V, const double2* y, int m, size_t n,
-                                 int accumulate, hipStream_t s) {
+                                 int accumulate, hipStream_t s, const int* mdev) {
   hipLaunchKernelGGL(multi_axpy_kernel<float2>, dim3(grid_for(n)), dim3(kThreads), 0, s, out, V, y, m,
-                     n, accumulate);
+                     n, accumulate, mdev);
+  return hipGetLastError();
+}
+
+size_t givens_bytes(int m) {
+  // g (m + 1), sn (m), R (m * m) complex; cs, est (m) doubles; two ints
+  return sizeof(double2) * (size_t(m + 1) + m + size_t(m) * m) + sizeof(double) * 2 * m + 2 * sizeof(int) + 64;
+}
+
+GivensState givens_state(h6_plan P, int m) {
+  char* b = reinterpret_cast<char*>(P->d_givens);
+  GivensState st;
+  st.g = reinterpret_cast<double2*>(b);
+  st.sn = st.g + (m + 1);
+  st.R = st.sn + m;
+  st.cs = reinterpret_cast<double*>(st.R + size_t(m) * m);
+  st.est = st.cs + m;
+  st.stop = reinterpret_cast<int*>(st.est + m);
+  st.jdone = st.stop + 1;
+  return st;
+}
+
+hipError_t launch_givens_step(int j, const double* nrow, const double* nu, const double2* hcol, GivensState st,
+                              int m, const double* prm, hipStream_t s) {
+  if (j < 0 || j >= m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(givens_step_kernel, dim3(1), dim3(64), 0, s, j, m, nrow, nu, hcol, st, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsq_solve(int m, GivensState st, const double* nu, double2* y, hipStream_t s) {
+  hipLaunchKernelGGL(lsq_solve_kernel, dim3(1), dim3(64), 0, s, m, st, nu, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_int(int* p, hipStream_t s) {
+  hipLaunchKernelGGL(clear_int_kernel, dim3(1), dim3(64), 0, s, p);
   return hipGetLastError();
 }
 

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
     const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
     const double2* __restrict__ tri, const typename C2<R>::T* __restrict__ cstart,
     const double* __restrict__ lx, const double* __restrict__ ly, double kap_re, double kap_im,
-    int nx, int ny, int nz) {
+    int nx, int ny, int nz, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   using T2 = typename C2<R>::T;
   constexpr int kThr = kLanes * kSegs;
   constexpr int kTabPer = (3 * kMaxZ + kThr - 1) / kThr;
@@ -209,17 +210,18 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   auto xform_x = [&](bool inv, auto* src, auto* dst, int accumulate) {
     timing_begin(P, KC_XFORM_X, s, &ev);
     if (X.fast)
-      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines);
+      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines,
+                              P->skip);
     else
-      (void)launch_dense_x<R>(X, inv, src, dst, nlines_x, accumulate, s);
+      (void)launch_dense_x<R>(X, inv, src, dst, nlines_x, accumulate, s, P->skip);
     timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst) * (accumulate ? 2 : 1)));
   };
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
     timing_begin(P, KC_XFORM_Y, s, &ev);
     if (Y.fast)
-      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines);
+      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines, P->skip);
     else
-      (void)launch_dense_y<R>(Y, inv, src, dst, nx, nz, s);
+      (void)launch_dense_y<R>(Y, inv, src, dst, nx, nz, s, P->skip);
     timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
   if (part & PINV_FIRST) xform_x(false, r, w0, 0);
@@ -231,7 +233,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
     const T2* cst = static_cast<const T2*>(P->d_cstart);
     auto go = [&](auto kern, int lanes) {
       hipLaunchKernelGGL(kern, dim3((nx * ny + lanes - 1) / lanes), dim3(512), 0, s, w1, w0, P->d_tri, cst,
-                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz);
+                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz, P->skip);
     };
     if (z_segments(nz, sizeof(R) == 4) == 16) {
       if (nz <= 16 * 5) go(tridiag_z_kernel<R, 32, 16, 5>, 32);

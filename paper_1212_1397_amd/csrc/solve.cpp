@@ -22,6 +22,8 @@
 // the true residual ||F - A U|| / ||F||, recomputed at every restart.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "h6_internal.h"
@@ -38,6 +40,9 @@ constexpr int kGram2 = 3000;    // Gram entries beyond kGramMax (2 m doubles)
 constexpr int kNu = 3600;       // m + 1 doubles: basis norms nu_i
 constexpr int kHcol = 4000;     // 2 (m + 1) doubles: Hessenberg column of the current step
 constexpr int kJudge = 4600;    // 2 doubles: |q - A z|^2 without / with the learned correction
+constexpr int kCycEst = 5000;   // whole-cycle graphs: m doubles of per-step residual estimates (host)
+constexpr int kCycInt = 5300;   // steps done (an int in one double slot, host)
+constexpr int kPrm = 5400;      // (steps allowed, ||F||, tol) for the device Givens steps
 
 struct Ctx {
   h6_plan P;
@@ -76,6 +81,14 @@ h6_status ensure(h6_plan P, int method, int m) {
     }
   }
   if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m, zb);
+  if (e == hipSuccess && P->use_graphs == 2 && (method == H6_GMRES || method == H6_FGMRES) &&
+      P->givens_dim < m) {
+    (void)hipFree(P->d_givens);
+    P->d_givens = nullptr;
+    P->givens_dim = 0;
+    e = hipMalloc(reinterpret_cast<void**>(&P->d_givens), givens_bytes(m));
+    if (e == hipSuccess) P->givens_dim = m;
+  }
   if (e != hipSuccess) {
     P->last_error = std::string("workspace allocation failed: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
@@ -148,6 +161,111 @@ h6_status upload_coefs(Ctx& c, int off, const std::vector<cplx>& v, int count) {
   return H6_OK;
 }
 
+// GMRES / FGMRES with whole restart cycles as one captured HIP graph: every
+// step's kernels (preconditioner, A, MGS) are followed by a one-thread
+// Givens update of the least-squares problem on the device; when it meets
+// the tolerance, the step budget or a breakdown it raises a device stop flag,
+// and the kernels of the later steps return at once (no conditional nodes
+// are needed).  The cycle ends with y = R^{-1} g and U += Z y (or
+// U += A_p^{-1} V y) on the device, so the host waits once per cycle, for the
+// true residual, the steps done and their estimates.
+h6_status gmres_cycles(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
+  h6_plan P = c.P;
+  const int m = info->restart;
+  const bool flex = info->method == H6_FGMRES;
+  const bool mixed = P->p.precision == H6_MIXED;
+  const size_t N = c.N;
+  const GivensState gs = givens_state(P, m);
+  double* prm = c.dev + kPrm;
+  const GraphKey key{P->V, P->Z, U, m, int(flex), int(mixed), 2};
+  if (!(key == P->graph_key)) {
+    release_graphs(P);
+    P->graph_key = key;
+  }
+  if (!P->cycle_graph) {
+    hipGraph_t graph = nullptr;
+    H6_TRY_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    P->skip = gs.stop;
+    const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
+    double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
+    for (int j = 0; j < m && e == hipSuccess; ++j) {
+      const double2* qj = P->V + size_t(j) * N;
+      double2* w = P->V + size_t(j + 1) * N;
+      if (mixed) {
+        float2* z = static_cast<float2*>(P->Z) + size_t(j) * N;
+        e = launch_pinv_f32out(P, qj, z, c.s, PINV_ALL);
+        if (e == hipSuccess) e = launch_stencil_f32in(P, z, w, c.s);
+      } else {
+        double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
+        e = launch_pinv(P, qj, z, c.s, PINV_ALL);
+        if (e == hipSuccess) e = launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s);
+      }
+      if (e == hipSuccess) e = launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s, gs.stop);
+      if (e == hipSuccess && j > kGramMax)
+        e = launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, qj, N, P->partials, c.dev + kGram2,
+                              c.s, gs.stop);
+      if (e == hipSuccess)
+        e = launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu, P->d_gram, P->gram_dim,
+                            dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s, gs.stop);
+      if (e == hipSuccess)
+        e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s, gs.stop);
+      if (e == hipSuccess) e = launch_givens_step(j, c.dev + kNorm, c.dev + kNu, dhcol, gs, m, prm, c.s);
+    }
+    P->skip = nullptr;
+    double2* dy = reinterpret_cast<double2*>(c.dev + kY);
+    if (e == hipSuccess) e = launch_lsq_solve(m, gs, c.dev + kNu, dy, c.s);
+    if (e == hipSuccess) {
+      if (flex && mixed)
+        e = launch_multi_axpy_f32(U, static_cast<float2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
+      else if (flex)
+        e = launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
+      else {
+        e = launch_multi_axpy(P->t, P->V, dy, m, N, 0, c.s, gs.jdone);
+        if (e == hipSuccess) e = launch_pinv_acc(P, P->t, U, c.s);
+      }
+    }
+    const hipError_t e2 = hipStreamEndCapture(c.s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->cycle_graph, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    H6_TRY_HIP(e);
+  }
+  int nh = 0;
+  h6_status st = residual_async(c, F, U, P->V);
+  if (st == H6_OK) st = wait(c);
+  if (st != H6_OK) return st;
+  double beta2 = c.host[kNorm];
+  info->iters = 0;
+  while (true) {
+    info->rel_resid = std::sqrt(beta2) / normF;
+    if (!std::isfinite(info->rel_resid)) { info->history_len = nh; return H6_DIVERGED; }
+    if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
+    if (info->iters >= info->maxit) { info->history_len = nh; return H6_NOT_CONVERGED; }
+    // cycle parameters and a cleared stop flag, outside the graph
+    c.host[kPrm] = double(std::min(m, info->maxit - info->iters));
+    c.host[kPrm + 1] = normF;
+    c.host[kPrm + 2] = info->tol;
+    H6_TRY_HIP(hipMemcpyAsync(prm, c.host + kPrm, 3 * sizeof(double), hipMemcpyHostToDevice, c.s));
+    H6_TRY_HIP(launch_clear_int(gs.stop, c.s));
+    H6_TRY_HIP(hipGraphLaunch(P->cycle_graph, c.s));
+    H6_TRY_HIP(hipMemcpyAsync(c.host + kCycEst, gs.est, sizeof(double) * m, hipMemcpyDeviceToHost, c.s));
+    H6_TRY_HIP(hipMemcpyAsync(c.host + kCycInt, gs.jdone, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    st = residual_async(c, F, U, P->V);
+    if (st == H6_OK) st = wait(c);
+    if (st != H6_OK) return st;
+    int jd = 0;
+    std::memcpy(&jd, c.host + kCycInt, sizeof(int));
+    if (jd < 1 || jd > m) {
+      P->last_error = "internal: whole-cycle graph reported " + std::to_string(jd) + " steps";
+      return H6_ERR_HIP;
+    }
+    for (int j = 0; j < jd; ++j) record(info, nh, c.host[kCycEst + j]);
+    info->iters += jd;
+    beta2 = c.host[kNorm];
+  }
+}
+
 h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
   h6_plan P = c.P;
   const int m = info->restart;
@@ -169,8 +287,9 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   P->learned_steps = 0;
   // step graphs: valid while the workspace and the step shape are unchanged
   const bool graphs = P->use_graphs && !P->timing.enabled && !P->net;
+  if (graphs && P->use_graphs == 2) return gmres_cycles(c, F, U, info, normF);
   if (graphs) {
-    const GraphKey key{P->V, P->Z, m, int(flex), int(mixed)};
+    const GraphKey key{P->V, P->Z, nullptr, m, int(flex), int(mixed), 1};
     if (!(key == P->graph_key) || int(P->step_graphs.size()) < m) {
       release_graphs(P);
       P->graph_key = key;
@@ -435,6 +554,8 @@ void release_graphs(h6_plan P) {
   for (auto& g : P->step_graphs)
     if (g) (void)hipGraphExecDestroy(g);
   P->step_graphs.clear();
+  if (P->cycle_graph) (void)hipGraphExecDestroy(P->cycle_graph);
+  P->cycle_graph = nullptr;
   P->graph_key = GraphKey{};
 }
 

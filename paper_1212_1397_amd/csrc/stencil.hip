@@ -49,7 +49,8 @@ template <bool RESID, typename Tin, typename Tout, int kTZ>
 __global__ __launch_bounds__(kThreads) void stencil_kernel(
     const Tin* __restrict__ x, Tout* __restrict__ y, const double2* __restrict__ F,
     double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
-    int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg) {
+    int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double2 tile[2][kLY][kLX];
   __shared__ double red[kThreads / 64];
 
@@ -208,11 +209,11 @@ hipError_t stencil_launch(h6_plan P, const Tin* x, Tout* y, const double2* F, do
   if (resid)
     hipLaunchKernelGGL((stencil_kernel<true, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y, F,
                        partials, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
-                       P->zhi_closure, ntx, nty, nwg);
+                       P->zhi_closure, ntx, nty, nwg, P->skip);
   else
     hipLaunchKernelGGL((stencil_kernel<false, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y,
                        nullptr, nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
-                       P->zlo_closure, P->zhi_closure, ntx, nty, nwg);
+                       P->zlo_closure, P->zhi_closure, ntx, nty, nwg, P->skip);
   timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev,
              double(P->N) * (sizeof(Tin) + sizeof(Tout) + (resid ? sizeof(double2) : 0)));
   if (nparts) *nparts = nwg;

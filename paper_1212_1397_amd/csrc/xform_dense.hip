@@ -51,7 +51,8 @@ constexpr int kPad = kKC + 1;
 template <typename R, typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
                                                       const R* __restrict__ W, int Lq, int L, int nlines,
-                                                      int acc) {
+                                                      int acc, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   using M = Mma<R>;
   __shared__ R As[kT][kPad];   // rows (line, part) of 32 lines, K chunk
   __shared__ R Ws[kT][kPad];   // rows m, K chunk
@@ -124,7 +125,9 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
 
 template <typename R>
 __global__ __launch_bounds__(256) void dense_y_kernel(const R* __restrict__ in, R* __restrict__ out,
-                                                      const R* __restrict__ W, int Lq, int L, int ncols) {
+                                                      const R* __restrict__ W, int Lq, int L, int ncols,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
   using M = Mma<R>;
   __shared__ R Ws[kT][kPad];          // rows m, K chunk
   __shared__ R Xs[kKC][kT + 1];       // K chunk, columns
@@ -172,35 +175,35 @@ __global__ __launch_bounds__(256) void dense_y_kernel(const R* __restrict__ in, 
 
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_dense_x(const AxisXform& X, bool inverse, const Tin* in, Tout* out, int nlines, int acc,
-                          hipStream_t s) {
+                          hipStream_t s, const int* skip) {
   const R* W = static_cast<const R*>(X.wmat) + (inverse ? size_t(X.Lm) * X.Lq : 0);
   const dim3 grid((X.L + kT - 1) / kT, (nlines + kT / 2 - 1) / (kT / 2));
-  hipLaunchKernelGGL((dense_x_kernel<R, Tin, Tout>), grid, dim3(256), 0, s, in, out, W, X.Lq, X.L, nlines, acc);
+  hipLaunchKernelGGL((dense_x_kernel<R, Tin, Tout>), grid, dim3(256), 0, s, in, out, W, X.Lq, X.L, nlines, acc, skip);
   return hipGetLastError();
 }
 
 template <typename R, typename T2>
 hipError_t launch_dense_y(const AxisXform& Y, bool inverse, const T2* in, T2* out, int nx, int nz,
-                          hipStream_t s) {
+                          hipStream_t s, const int* skip) {
   const R* W = static_cast<const R*>(Y.wmat) + (inverse ? size_t(Y.Lm) * Y.Lq : 0);
   const int ncols = 2 * nx;
   const dim3 grid((ncols + kT - 1) / kT, (Y.L + kT - 1) / kT, nz);
   hipLaunchKernelGGL((dense_y_kernel<R>), grid, dim3(256), 0, s, reinterpret_cast<const R*>(in),
-                     reinterpret_cast<R*>(out), W, Y.Lq, Y.L, ncols);
+                     reinterpret_cast<R*>(out), W, Y.Lq, Y.L, ncols, skip);
   return hipGetLastError();
 }
 
 template hipError_t launch_dense_x<double, double2, double2>(const AxisXform&, bool, const double2*, double2*,
-                                                             int, int, hipStream_t);
+                                                             int, int, hipStream_t, const int*);
 template hipError_t launch_dense_x<float, double2, float2>(const AxisXform&, bool, const double2*, float2*,
-                                                           int, int, hipStream_t);
+                                                           int, int, hipStream_t, const int*);
 template hipError_t launch_dense_x<float, float2, double2>(const AxisXform&, bool, const float2*, double2*,
-                                                           int, int, hipStream_t);
+                                                           int, int, hipStream_t, const int*);
 template hipError_t launch_dense_x<float, float2, float2>(const AxisXform&, bool, const float2*, float2*,
-                                                          int, int, hipStream_t);
+                                                          int, int, hipStream_t, const int*);
 template hipError_t launch_dense_y<double, double2>(const AxisXform&, bool, const double2*, double2*, int, int,
-                                                    hipStream_t);
+                                                    hipStream_t, const int*);
 template hipError_t launch_dense_y<float, float2>(const AxisXform&, bool, const float2*, float2*, int, int,
-                                                  hipStream_t);
+                                                  hipStream_t, const int*);
 
 }  // namespace h6

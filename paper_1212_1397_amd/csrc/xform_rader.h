@@ -28,11 +28,13 @@ bool rader_lines_ok(int axis, int lines);
 
 // accumulate != 0 (inverse transforms with a complex128 output only): out += result.
 // lines: lines (x) or columns (y) per workgroup, one of rader_lines_ok's values.
+// skip: device flag; when nonzero the kernels return at once (whole-cycle graphs).
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s, int accumulate, int lines);
+                          const RaderTables& tab, hipStream_t s, int accumulate, int lines,
+                          const int* skip = nullptr);
 template <typename R, typename T>
 hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
-                          const RaderTables& tab, hipStream_t s, int lines);
+                          const RaderTables& tab, hipStream_t s, int lines, const int* skip = nullptr);
 
 }  // namespace h6

@@ -152,7 +152,8 @@ template <typename R, int AXIS, bool NEU, bool INV, int KL, typename Tin, typena
 __global__ __launch_bounds__(KL * 16) void rader257_kernel(const Tin* __restrict__ in,
                                                                Tout* __restrict__ out, int nlines,
                                                                int nx, int L, RaderTables tab,
-                                                               int acc) {
+                                                               int acc, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ T2 buf[KL][kStride];
   constexpr int kPx = (258 + KL * 16 - 1) / (KL * 16);   // loads per x line (L <= 258)
   constexpr int M = 257;
@@ -395,23 +396,23 @@ __global__ __launch_bounds__(KL * 16) void rader257_kernel(const Tin* __restrict
 
 template <typename R, int AXIS, bool NEU, int KL, typename Tin, typename Tout>
 void launch_one(bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
-                const RaderTables& tab, hipStream_t s, int acc) {
+                const RaderTables& tab, hipStream_t s, int acc, const int* skip) {
   const dim3 grid = AXIS == 0 ? dim3((nlines + KL - 1) / KL) : dim3((nx + KL - 1) / KL, nz);
   if (inv)
     hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, true, KL, Tin, Tout>), grid, dim3(KL * 16), 0,
-                       s, in, out, nlines, nx, L, tab, acc);
+                       s, in, out, nlines, nx, L, tab, acc, skip);
   else
     hipLaunchKernelGGL((rader257_kernel<R, AXIS, NEU, false, KL, Tin, Tout>), grid, dim3(KL * 16), 0,
-                       s, in, out, nlines, nx, L, tab, 0);
+                       s, in, out, nlines, nx, L, tab, 0, skip);
 }
 
 template <typename R, int AXIS, int KL, typename Tin, typename Tout>
 void launch_bc(bool neumann, bool inv, const Tin* in, Tout* out, int nlines, int nx, int L, int nz,
-               const RaderTables& tab, hipStream_t s, int acc) {
+               const RaderTables& tab, hipStream_t s, int acc, const int* skip) {
   if (neumann)
-    launch_one<R, AXIS, true, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc);
+    launch_one<R, AXIS, true, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc, skip);
   else
-    launch_one<R, AXIS, false, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc);
+    launch_one<R, AXIS, false, KL>(inv, in, out, nlines, nx, L, nz, tab, s, acc, skip);
 }
 
 }  // namespace
@@ -422,11 +423,11 @@ bool rader_lines_ok(int axis, int lines) {
 
 template <typename R, typename Tin, typename Tout>
 hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, int nlines, int L,
-                          const RaderTables& tab, hipStream_t s, int accumulate, int lines) {
+                          const RaderTables& tab, hipStream_t s, int accumulate, int lines, const int* skip) {
   if (lines == 4)
-    launch_bc<R, 0, 4>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
+    launch_bc<R, 0, 4>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate, skip);
   else if (lines == 8)
-    launch_bc<R, 0, 8>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate);
+    launch_bc<R, 0, 8>(neumann, inverse, in, out, nlines, 0, L, 0, tab, s, accumulate, skip);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -434,27 +435,27 @@ hipError_t launch_rader_x(bool neumann, bool inverse, const Tin* in, Tout* out, 
 
 template <typename R, typename T>
 hipError_t launch_rader_y(bool neumann, bool inverse, const T* in, T* out, int nx, int L, int nz,
-                          const RaderTables& tab, hipStream_t s, int lines) {
+                          const RaderTables& tab, hipStream_t s, int lines, const int* skip) {
   if (lines == 8)
-    launch_bc<R, 1, 8>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0);
+    launch_bc<R, 1, 8>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0, skip);
   else if (lines == 16)
-    launch_bc<R, 1, 16>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0);
+    launch_bc<R, 1, 16>(neumann, inverse, in, out, 0, nx, L, nz, tab, s, 0, skip);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template hipError_t launch_rader_x<double, double2, double2>(bool, bool, const double2*, double2*,
-                                                             int, int, const RaderTables&, hipStream_t, int, int);
+                                                             int, int, const RaderTables&, hipStream_t, int, int, const int*);
 template hipError_t launch_rader_x<float, double2, float2>(bool, bool, const double2*, float2*, int,
-                                                           int, const RaderTables&, hipStream_t, int, int);
+                                                           int, const RaderTables&, hipStream_t, int, int, const int*);
 template hipError_t launch_rader_x<float, float2, double2>(bool, bool, const float2*, double2*, int,
-                                                           int, const RaderTables&, hipStream_t, int, int);
+                                                           int, const RaderTables&, hipStream_t, int, int, const int*);
 template hipError_t launch_rader_x<float, float2, float2>(bool, bool, const float2*, float2*, int,
-                                                          int, const RaderTables&, hipStream_t, int, int);
+                                                          int, const RaderTables&, hipStream_t, int, int, const int*);
 template hipError_t launch_rader_y<double, double2>(bool, bool, const double2*, double2*, int, int,
-                                                    int, const RaderTables&, hipStream_t, int);
+                                                    int, const RaderTables&, hipStream_t, int, const int*);
 template hipError_t launch_rader_y<float, float2>(bool, bool, const float2*, float2*, int, int, int,
-                                                  const RaderTables&, hipStream_t, int);
+                                                  const RaderTables&, hipStream_t, int, const int*);
 
 }  // namespace h6

@@ -241,9 +241,12 @@ class Plan:
         return U, dict(status=status, iters=info.iters, rel_resid=info.rel_resid,
                        history=list(hist[:info.history_len]))
 
-    def set_graphs(self, enable: bool = True):
-        """Capture GMRES / FGMRES Arnoldi steps as HIP graphs and replay them."""
-        self._check(_lib.helmholtz6_set_graphs(self._plan, int(enable)))
+    def set_graphs(self, mode=True):
+        """HIP graphs for GMRES / FGMRES: False / 0 off, True / 1 one graph per
+        Arnoldi step, 2 or "cycle" one graph per restart cycle with the Givens
+        rotations on the device."""
+        m = 2 if mode == "cycle" else int(mode)
+        self._check(_lib.helmholtz6_set_graphs(self._plan, m))
 
     def autotune(self, cache_path=None, stream=None):
         """Time the kernel variants on this grid and keep the fastest (optionally cached)."""

@@ -146,3 +146,8 @@ def test_grids_beyond_kernel_limits_rejected(n, precision):
     with pytest.raises(h6.H6Error) as e:
         h6.Plan(n, 1.0 / (max(n) + 1), 2.0, precision=precision)
     assert e.value.status == -1
+
+
+def test_set_graphs_rejects_unknown_mode():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    assert h6._lib.helmholtz6_set_graphs(None, 1) == h6.H6_ERR_ARG

@@ -107,3 +107,39 @@ def test_transform_workgroup_widths_agree(h6, tmp_path, precision):
             f.write(f"h6tune2 {arch} {nx} {ny} {nz} {pnum} tz=16 xfast=1 yfast=1 xlines={xl} ylines={yl}\n")
         plan.autotune(path)
         assert torch.equal(plan.apply_Pinv(x), z0), (xl, yl)
+
+
+@pytest.mark.parametrize("precision,method,restart,maxit", [("mixed", "fgmres", 30, 300), ("fp64", "gmres", 30, 300),
+                                                            ("fp64", "fgmres", 30, 300), ("mixed", "fgmres", 4, 300),
+                                                            ("fp64", "gmres", 30, 7)])
+def test_cycle_graphs_match_step_solver(h6, precision, method, restart, maxit):
+    """Whole-cycle graphs (Givens rotations and least squares on the device,
+    a device stop flag for the remaining steps) reproduce the host-driven
+    solver: the same steps and status and the same per-step estimates up to
+    rounding, on repeated replays with eager work in between; a restart
+    length of 4 runs the cycle graph many times, maxit = 7 stops inside the
+    first cycle.  Within a cycle the estimates agree to 1e-8; after a restart
+    the device's rotations and division round differently from the host's,
+    and the solution's O(1e-16) change reaches the next residual amplified by
+    ||U|| / ||F|| (about 1e4 here), hence 1e-4 on the estimates overall."""
+    import numpy as np
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=precision)
+    F = plan.rhs_gaussians(*gaussian_sources(w))
+    U0, i0 = plan.solve(F, method=method, restart=restart, tol=w.tol, maxit=maxit)
+    plan.set_graphs("cycle")
+    U = torch.zeros_like(F)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        U.zero_()
+        U1, i1 = plan.solve(F, U, method=method, restart=restart, tol=w.tol, maxit=maxit)
+        torch.cuda.synchronize()
+        print(f"rep {rep}: {i1['iters']} steps ({i0['iters']}), {i1['status']}", flush=True)
+        assert i1["iters"] == i0["iters"] and i1["status"] == i0["status"], rep
+        np.testing.assert_allclose(i1["history"][:restart], i0["history"][:restart], rtol=1e-8)
+        np.testing.assert_allclose(i1["history"], i0["history"], rtol=1e-4)
+        assert float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0)) < 1e-9, rep
+        del junk
+    plan.set_graphs(0)
+    U2, i2 = plan.solve(F, method=method, restart=restart, tol=w.tol, maxit=maxit)
+    assert torch.equal(U2, U0)
