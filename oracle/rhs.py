@@ -27,6 +27,12 @@ Face terms (the source parts of the ghost relations, moved to the right):
   At z = top the same holds in the reflected coordinate z' = top - z.
 * Nonhomogeneous Dirichlet data g on a z face (used for Table 5): the row
   next to the face holds G g (the h^2-scaled plane coupling), so F -= G g.
+* Neumann data beta = du/dn (n the face's axis, derivative along +n) on a
+  Neumann face, eq. (3DN): the ghost relation carries, besides -2h R_N,
+    -2h B,  B = (1 - kappa/6 + kappa^2/120) beta
+                - (h^4/180)(beta_t1t1t2t2 + beta_t1t1t1t1 + beta_t2t2t2t2)
+                - (k^2 h^4/180)(beta_t1t1 + beta_t2t2),
+  so F += 2h B on the low face and F -= 2h B on the high face (as R_N).
 
 Edges and corners where several such faces meet receive the terms of every
 face independently.
@@ -75,6 +81,23 @@ def _neumann_RN(prob: Problem, f: Separable, ax: int, side: int) -> np.ndarray:
             + (7.0 * h ** 4 / 360.0) * (D(1, 2, 0) + D(1, 0, 2)))
 
 
+def _neumann_data_term(prob: Problem, g: Separable, ax: int, side: int) -> np.ndarray:
+    """B of eq. (3DN) for Neumann data beta = g on the face (tangential
+    derivatives of g taken on the face plane)."""
+    h, kap = prob.h, prob.kappa
+    pts = _face_points(prob, ax, side)
+    t1, t2 = [a for a in range(3) if a != ax]
+
+    def D(n1, n2):
+        o = [0, 0, 0]
+        o[t1], o[t2] = n1, n2
+        return g.deriv(pts, tuple(o))
+
+    return ((1.0 - kap / 6.0 + kap * kap / 120.0) * D(0, 0)
+            - (h ** 4 / 180.0) * (D(2, 2) + D(4, 0) + D(0, 4))
+            - (prob.k ** 2 * h ** 4 / 180.0) * (D(2, 0) + D(0, 2)))
+
+
 def _sommerfeld_term(prob: Problem, f: Separable, side: int) -> np.ndarray:
     """e^{ikh} mu3 [2h Fbar + mu1 h^5/3 Lbar] on a z face (reflected at the top)."""
     h, k = prob.h, prob.k
@@ -104,8 +127,10 @@ def _add_face(F: np.ndarray, ax: int, side: int, term: np.ndarray):
     F[tuple(idx)] += term
 
 
-def rhs(prob: Problem, f: Separable, dirichlet_z=(None, None)) -> np.ndarray:
-    """F for source f; dirichlet_z = optional data g (Separable) on the z faces."""
+def rhs(prob: Problem, f: Separable, dirichlet_z=(None, None), neumann=None) -> np.ndarray:
+    """F for source f; dirichlet_z = optional data g (Separable) on the z faces;
+    neumann = optional {face index 0..5 (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi):
+    Separable whose values on that face are beta = du/dn (along +axis)}."""
     F = interior_rhs(prob, f)
     h = prob.h
     for ax in range(3):
@@ -116,6 +141,11 @@ def rhs(prob: Problem, f: Separable, dirichlet_z=(None, None)) -> np.ndarray:
                 _add_face(F, ax, side, (2.0 * h if side == 0 else -2.0 * h) * RN)
             elif code == "S":
                 _add_face(F, ax, side, _sommerfeld_term(prob, f, side))
+    for face, g in (neumann or {}).items():
+        ax, side = divmod(face, 2)
+        if prob.bc[face] != "N":
+            raise ValueError("Neumann data given on a non-Neumann face")
+        _add_face(F, ax, side, (2.0 * h if side == 0 else -2.0 * h) * _neumann_data_term(prob, g, ax, side))
     for side, g in enumerate(dirichlet_z):
         if g is None:
             continue

@@ -1,7 +1,7 @@
 """Manufactured solutions used by the oracle tests (exact u, f = lap u + k^2 u)."""
 import math
 
-from oracle.functions import Cos, Exp, Poly, Separable, Sin, Term, helmholtz_source
+from oracle.functions import Cos, Exp, Poly, Separable, Shifted, Sin, Term, helmholtz_source
 
 
 def table3_u(k):
@@ -67,3 +67,23 @@ def cuda_values(u, pts, device="cuda"):
         Z = torch.from_numpy(np.asarray(t.fz.d(z, 0), dtype=np.complex128)).to(device)
         out += t.c * Z[:, None, None] * Y[None, :, None] * X[None, None, :]
     return out
+
+
+def normal_derivative(u, ax):
+    """du/d(axis ax) as a separable function: Neumann data of u on that axis' faces."""
+    out = []
+    for t in u.terms:
+        fs = [t.fx, t.fy, t.fz]
+        fs[ax] = Shifted(fs[ax], 1)
+        out.append(Term(t.c, *fs))
+    return Separable(out)
+
+
+def neumann_data_z_u():
+    """u_z(x, y, 0) = pi sin(pi x) sin(2 pi y) != 0, u = 0 on the other faces."""
+    return Separable([Term(1.0, Sin(math.pi), Sin(2 * math.pi), Sin(math.pi))])
+
+
+def neumann_data_y_u():
+    """u_y(x, 0, z) = (pi/2) sin(pi x) sin(2 pi z) != 0, u_y(x, 1, z) = 0."""
+    return Separable([Term(1.0, Sin(math.pi), Sin(math.pi / 2), Sin(2 * math.pi))])

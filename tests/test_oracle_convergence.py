@@ -12,16 +12,17 @@ import numpy as np
 import pytest
 
 import oracle
-from manufactured import (mixed_pattern_u, neumann_y_factor, neumann_z_u, source,
-                          sommerfeld_z_factor)
+from manufactured import (mixed_pattern_u, neumann_data_y_u, neumann_data_z_u, neumann_y_factor, neumann_z_u,
+                          normal_derivative, source, sommerfeld_z_factor)
 from oracle.functions import Separable, Sin, Term
 
 
-def errors(bc, k, u, ns=(15, 31, 63)):
+def errors(bc, k, u, ns=(15, 31, 63), data_faces=()):
     e6, e2 = [], []
     for n in ns:
         prob = oracle.Problem.cube(n, k, bc)
-        F = oracle.rhs(prob, source(u, k))
+        nd = {f: normal_derivative(u, f // 2) for f in data_faces}
+        F = oracle.rhs(prob, source(u, k), neumann=nd)
         U, info = oracle.solve(prob, F, "gmres", tol=1e-13, maxit=300)
         assert info.status == "ok"
         ex = u.deriv(prob.points(), (0, 0, 0))
@@ -44,6 +45,12 @@ CASES = {
     "mixed_pattern": ("DDNNSS", 10.0 + 0.1j, mixed_pattern_u, (58, 68)),
 }
 
+# nonzero Neumann data (eq. (3DN)): beta = du/dn of the manufactured solution
+DATA_CASES = {
+    "neumann_data_z": ("DDDDND", 10.0, neumann_data_z_u, (4,)),
+    "neumann_data_y": ("DDNNDD", 10.0, neumann_data_y_u, (2, 3)),
+}
+
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_sixth_order(name):
@@ -52,3 +59,10 @@ def test_sixth_order(name):
     assert lo <= r6[-1] <= hi, r6
     assert r6[0] > 40, r6
     assert all(3.6 <= r <= 4.4 for r in r2), r2
+
+
+@pytest.mark.parametrize("name", list(DATA_CASES))
+def test_sixth_order_with_neumann_data(name):
+    bc, k, ufun, faces = DATA_CASES[name]
+    r6, _ = errors(bc, k, ufun(), data_faces=faces)
+    assert 58 <= r6[-1] <= 70 and r6[0] > 55, r6

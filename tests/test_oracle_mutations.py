@@ -12,7 +12,7 @@ import oracle
 orhs = importlib.import_module("oracle.rhs")
 oscheme = importlib.import_module("oracle.scheme")
 from dense_assembly import dense_A
-from manufactured import mixed_pattern_u, neumann_z_u, source
+from manufactured import mixed_pattern_u, neumann_data_z_u, neumann_z_u, normal_derivative, source
 
 
 def _ratio(bc, k, u, ns=(15, 31)):
@@ -112,3 +112,29 @@ def test_wrong_preconditioner_end_row_caught(monkeypatch):
     rng = np.random.default_rng(0)
     r = rng.standard_normal(prob.shape) + 0j
     assert np.abs(oracle.apply_Ap(prob, oracle.apply_Pinv(prob, r)) - r).max() > 1e-3
+
+
+def test_neumann_data_high_order_terms_dropped_lowers_order(monkeypatch):
+    """Keeping only the leading beta term of eq. (3DN) (dropping its h^5/90
+    tangential-derivative terms) leaves a fourth-order scheme."""
+    u = neumann_data_z_u()
+
+    def ratio():
+        errs = []
+        for n in (15, 31):
+            prob = oracle.Problem.cube(n, 10.0, "DDDDND")
+            F = oracle.rhs(prob, source(u, 10.0), neumann={4: normal_derivative(u, 2)})
+            U, info = oracle.solve(prob, F, "gmres", tol=1e-13, maxit=300)
+            errs.append(np.abs(U - u.deriv(prob.points(), (0, 0, 0))).max())
+        return errs[0] / errs[1]
+
+    good = ratio()
+
+    def leading_only(prob, g, ax, side):
+        kap = prob.kappa
+        pts = orhs._face_points(prob, ax, side)
+        return (1.0 - kap / 6.0 + kap * kap / 120.0) * g.deriv(pts, (0, 0, 0))
+
+    monkeypatch.setattr(orhs, "_neumann_data_term", leading_only)
+    bad = ratio()
+    assert good > 55 and bad < 40, (good, bad)
