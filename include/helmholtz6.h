@@ -141,6 +141,22 @@ h6_status helmholtz6_rhs_separable(h6_plan plan, int nterms, const double* coef,
  * building the source part of F.  Enqueue only. */
 h6_status helmholtz6_rhs_dirichlet_z(h6_plan plan, int side, const void* g, void* F, void* hip_stream);
 
+/* Nonzero Neumann data beta = du/dn on a Neumann face (face 0..5: x low,
+ * x high, y low, y high, z low, z high; the derivative is taken along the
+ * positive axis direction on both faces of an axis).  Eq. (3DN): the ghost
+ * relation of the face carries -2h B with
+ *   B = (1 - kappa/6 + kappa^2/120) beta - (h^4/180)(beta_t1t1t2t2 + beta_t1t1t1t1
+ *       + beta_t2t2t2t2) - (k^2 h^4/180)(beta_t1t1 + beta_t2t2),
+ * so F += 2h B on a low face and F -= 2h B on a high face (added to F, which
+ * already holds the source terms).  beta = sum_{s < nterms} c_s T1_s(t1) T2_s(t2)
+ * over the face's tangential axes t1 < t2 (x face: y, z; y face: x, z; z
+ * face: x, y): coef as for helmholtz6_rhs_separable, t1 / t2 host complex128
+ * tables [(s * 5 + o) * n' + i] of derivative orders o = 0..4 at the unknown
+ * nodes of each tangential axis.  H6_ERR_ARG for a face that is not Neumann.
+ * Synchronises hip_stream before returning. */
+h6_status helmholtz6_rhs_neumann(h6_plan plan, int face, int nterms, const double* coef, const double* t1,
+                                 const double* t2, void* F, void* hip_stream);
+
 /* Solves A U = F.  U is the initial guess on entry (may be zero) and the
  * solution on return.  F and U must not alias.  GMRES/FGMRES: right
  * preconditioning, modified Gram-Schmidt Arnoldi, Givens least squares in FP64

@@ -717,6 +717,24 @@ h6_status helmholtz6_rhs_dirichlet_z(h6_plan P, int side, const void* g, void* F
   return H6_OK;
 }
 
+h6_status helmholtz6_rhs_neumann(h6_plan P, int face, int nterms, const double* coef, const double* t1,
+                                 const double* t2, void* F, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!F || face < 0 || face > 5 || nterms < 0 || nterms > 1024 || (nterms > 0 && (!coef || !t1 || !t2))) {
+    P->last_error = "bad rhs_neumann arguments";
+    return H6_ERR_ARG;
+  }
+  if (P->p.bc[face] != H6_NEUMANN) {
+    P->last_error = "Neumann data given for a face that is not Neumann";
+    return H6_ERR_ARG;
+  }
+  if (nterms == 0) return H6_OK;
+  H6_TRY_HIP(launch_rhs_neumann(P, face, nterms, coef, t1, t2, static_cast<double2*>(F),
+                                static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
 h6_status helmholtz6_solve(h6_plan P, const void* F, void* U, h6_solve_info* info,
                            void* hip_stream) {
   if (!P) return H6_ERR_ARG;

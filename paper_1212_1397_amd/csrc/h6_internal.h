@@ -198,6 +198,9 @@ hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* 
 hipError_t launch_rhs_separable(h6_plan P, int nterms, const double* coef, const double* const tab[3],
                                 double2* F, hipStream_t s);
 hipError_t launch_rhs_dirichlet_z(h6_plan P, int side, const double2* g, double2* F, hipStream_t s);
+// face 0..5; t1 / t2: host complex128 tables (nterms x 5 x n' of the tangential axes); synchronises s
+hipError_t launch_rhs_neumann(h6_plan P, int face, int nterms, const double* coef, const double* t1,
+                              const double* t2, double2* F, hipStream_t s);
 
 // Krylov helpers (double2 vectors of length P->N); reductions end in device doubles
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s);

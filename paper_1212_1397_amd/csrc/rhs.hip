@@ -2,7 +2,8 @@
 //  (a) a sum of Gaussian sources f = sum_s a_s exp(-|x - c_s|^2 / (2 sigma^2)),
 //  (b) a separable source f = sum_s c_s X_s(x) Y_s(y) Z_s(z) given by samples of
 //      each factor and its derivatives up to fourth order at the unknown nodes,
-// and (c) the plane term of nonhomogeneous Dirichlet data on a z face.
+// and (c) the plane term of nonhomogeneous Dirichlet data on a z face, and
+// (d) the data term of nonzero Neumann data on a Neumann face.
 //
 // Interior part, eq. (scheme) right side times h^2 (mixed fourth-derivative
 // coefficient h^4/180, the value that makes the scheme sixth order):
@@ -19,6 +20,11 @@
 // the face plane through the in-plane operator G of eq. (scheme)'s delta_z^2
 // term, G = I + (1 + kappa/30)/6 (D_x + D_y) + (1/30) D_x D_y (D = h^2 delta^2),
 // so F -= G g on that plane.
+// Neumann data beta = du/dn (n the face's axis, derivative along +n), eq.
+// (3DN): the ghost relation carries -2h B with
+//   B = (1 - kappa/6 + kappa^2/120) beta - (h^4/180)(beta_t1t1t2t2 + beta_t1^4 + beta_t2^4)
+//       - (k^2 h^4/180)(beta_t1t1 + beta_t2t2),
+// so the face's unknown plane gets F += 2h B (low face) or F -= 2h B (high face).
 //
 // Gaussian derivatives: d^n/dx^n exp(-t^2/2), t = (x - c)/sigma, equals
 // (-1/sigma)^n He_n(t) exp(-t^2/2) with the probabilists' Hermite polynomials.
@@ -259,6 +265,41 @@ RhsCoef rhs_coef(h6_plan P) {
   return a;
 }
 
+// Neumann data on face plane (axis ax, side): beta = sum_s coef[s] T1_s(t1) T2_s(t2)
+// from tables tab1 / tab2 ([(s * 5 + o) * n_t + i], o = derivative order).
+struct NeumannFace {
+  int n1, n2;                 // unknowns along the tangential axes t1 < t2
+  size_t s1, s2;              // strides of t1, t2 in the vector layout
+  size_t base;                // offset of the face's unknown plane
+  double2 a0, c4, c2;         // 2h (1 - kappa/6 + kappa^2/120), -2h h^4/180, -2h k^2 h^4/180 (signed)
+};
+
+__global__ __launch_bounds__(256) void neumann_data_kernel(NeumannFace fc, int nterms,
+                                                           const double2* __restrict__ coef,
+                                                           const double2* __restrict__ tab1,
+                                                           const double2* __restrict__ tab2,
+                                                           double2* __restrict__ F) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= fc.n1 * fc.n2) return;
+  const int i1 = idx % fc.n1, i2 = idx / fc.n1;
+  double2 d00 = make_double2(0, 0), d4 = make_double2(0, 0), d2 = make_double2(0, 0);
+  for (int s = 0; s < nterms; ++s) {
+    double2 a[5], b[5];
+    for (int o = 0; o < 5; ++o) {
+      a[o] = tab1[size_t(s * 5 + o) * fc.n1 + i1];
+      b[o] = tab2[size_t(s * 5 + o) * fc.n2 + i2];
+    }
+    const double2 c = coef[s];
+    d00 = ca(d00, cm(c, cm(a[0], b[0])));
+    d4 = ca(d4, cm(c, ca(ca(cm(a[2], b[2]), cm(a[4], b[0])), cm(a[0], b[4]))));
+    d2 = ca(d2, cm(c, ca(cm(a[2], b[0]), cm(a[0], b[2]))));
+  }
+  const double2 add = ca(ca(cm(fc.a0, d00), cm(fc.c4, d4)), cm(fc.c2, d2));
+  const size_t o = fc.base + size_t(i1) * fc.s1 + size_t(i2) * fc.s2;
+  const double2 f = F[o];
+  F[o] = make_double2(f.x + add.x, f.y + add.y);
+}
+
 }  // namespace
 
 hipError_t launch_rhs(h6_plan P, int nsrc, const double* centres, const double* amps,
@@ -334,6 +375,49 @@ hipError_t launch_rhs_dirichlet_z(h6_plan P, int side, const double2* g, double2
   const unsigned nb = unsigned((plane + 255) / 256);
   hipLaunchKernelGGL(dirichlet_plane_kernel, dim3(nb), dim3(256), 0, s, g, Fp, r, ca_, 1.0 / 30.0);
   return hipGetLastError();
+}
+
+hipError_t launch_rhs_neumann(h6_plan P, int face, int nterms, const double* coef, const double* t1,
+                              const double* t2, double2* F, hipStream_t s) {
+  const int ax = face / 2, side = face % 2;
+  const int ta = ax == 0 ? 1 : 0, tb = ax == 2 ? 1 : 2;       // tangential axes, increasing
+  const size_t stride[3] = {1, size_t(P->dims[0]), size_t(P->dims[0]) * P->dims[1]};
+  NeumannFace fc{};
+  fc.n1 = P->dims[ta];
+  fc.n2 = P->dims[tb];
+  fc.s1 = stride[ta];
+  fc.s2 = stride[tb];
+  fc.base = side == 0 ? 0 : stride[ax] * size_t(P->dims[ax] - 1);
+  const double h = P->p.h, h4 = h * h * h * h;
+  const cplx kap = P->kappa, k2 = P->k * P->k;
+  const double sg = side == 0 ? 2.0 * h : -2.0 * h;
+  fc.a0 = d2(sg * (1.0 - kap / 6.0 + kap * kap / 120.0));
+  fc.c4 = d2(cplx(-sg * h4 / 180.0));
+  fc.c2 = d2(-sg * k2 * h4 / 180.0);
+  const size_t total = size_t(nterms) * (1 + 5 * (size_t(fc.n1) + fc.n2));
+  hipError_t e = hipSuccess;
+  if (total * sizeof(double2) > P->sep_bytes) {
+    (void)hipFree(P->d_sep);
+    P->d_sep = nullptr;
+    P->sep_bytes = 0;
+    e = hipMalloc(&P->d_sep, total * sizeof(double2));
+    if (e != hipSuccess) return e;
+    P->sep_bytes = total * sizeof(double2);
+  }
+  double2* base = static_cast<double2*>(P->d_sep);
+  double2* d1 = base + nterms;
+  double2* dt2 = d1 + size_t(nterms) * 5 * fc.n1;
+  e = hipMemcpyAsync(base, coef, size_t(nterms) * sizeof(double2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d1, t1, size_t(nterms) * 5 * fc.n1 * sizeof(double2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dt2, t2, size_t(nterms) * 5 * fc.n2 * sizeof(double2), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  const unsigned nb = unsigned((size_t(fc.n1) * fc.n2 + 255) / 256);
+  hipLaunchKernelGGL(neumann_data_kernel, dim3(nb), dim3(256), 0, s, fc, nterms, base, d1, dt2, F);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
 }
 
 }  // namespace h6

@@ -29,7 +29,7 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
             "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune",
-            "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z")
+            "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z", "helmholtz6_rhs_neumann")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
                 "helmholtz6_learned_steps", "h6net_destroy")
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_rhs_separable.restype = ctypes.c_int
     lib.helmholtz6_rhs_dirichlet_z.argtypes = [vp, ip, vp, vp, vp]
     lib.helmholtz6_rhs_dirichlet_z.restype = ctypes.c_int
+    lib.helmholtz6_rhs_neumann.argtypes = [vp, ip, ip] + [ctypes.POINTER(ctypes.c_double)] * 3 + [vp, vp]
+    lib.helmholtz6_rhs_neumann.restype = ctypes.c_int
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
                  "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
@@ -226,6 +228,27 @@ class Plan:
             raise ValueError(f"g must be a contiguous complex128 CUDA tensor of shape {(self.dims[1], self.dims[0])}")
         self._check(_lib.helmholtz6_rhs_dirichlet_z(self._plan, int(side), ctypes.c_void_p(g.data_ptr()),
                                                    self._vec(F, "F"), _stream_handle(stream)))
+        return F
+
+    def rhs_neumann(self, face: int, coef, t1, t2, F, stream=None):
+        """F += the eq. (3DN) data term of beta = sum_s coef[s] T1_s T2_s on Neumann
+        face `face` (0..5); t1, t2: arrays (nterms, 5, n') of derivative orders
+        0..4 along the face's tangential axes (increasing axis order)."""
+        import numpy as np
+        ax = int(face) // 2
+        ta, tb = [a for a in range(3) if a != ax]
+        c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128).reshape(-1))
+        nt = c.shape[0]
+        tabs = []
+        for name, t, n in (("t1", t1, self.dims[ta]), ("t2", t2, self.dims[tb])):
+            a = np.ascontiguousarray(np.asarray(t, dtype=np.complex128))
+            if a.shape != (nt, 5, n):
+                raise ValueError(f"{name} must have shape {(nt, 5, n)}, got {a.shape}")
+            tabs.append(a)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(_lib.helmholtz6_rhs_neumann(self._plan, int(face), nt, c.ctypes.data_as(dp),
+                                               tabs[0].ctypes.data_as(dp), tabs[1].ctypes.data_as(dp),
+                                               self._vec(F, "F"), _stream_handle(stream)))
         return F
 
     def solve(self, F, U=None, method="gmres", restart=30, maxit=1000, tol=1e-10, history=512,

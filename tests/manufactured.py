@@ -87,3 +87,19 @@ def neumann_data_z_u():
 def neumann_data_y_u():
     """u_y(x, 0, z) = (pi/2) sin(pi x) sin(2 pi z) != 0, u_y(x, 1, z) = 0."""
     return Separable([Term(1.0, Sin(math.pi), Sin(math.pi / 2), Sin(2 * math.pi))])
+
+
+def face_tables(g, pts, ax, coord):
+    """Inputs of helmholtz6_rhs_neumann for data g (separable) on the face
+    axis ax = coord: per term the coefficient times the normal factor's value
+    on the face, and derivative tables (orders 0..4) along the two tangential
+    axes (increasing order) at the unknown nodes pts."""
+    import numpy as np
+    ta, tb = [a for a in range(3) if a != ax]
+    coef, t1, t2 = [], [], []
+    for t in g.terms:
+        fs = [t.fx, t.fy, t.fz]
+        coef.append(t.c * complex(np.asarray(fs[ax].d(np.array([coord]), 0))[0]))
+        t1.append(np.stack([fs[ta].d(pts[ta], o) for o in range(5)]))
+        t2.append(np.stack([fs[tb].d(pts[tb], o) for o in range(5)]))
+    return np.array(coef, dtype=np.complex128), np.stack(t1), np.stack(t2)

@@ -151,3 +151,8 @@ def test_grids_beyond_kernel_limits_rejected(n, precision):
 def test_set_graphs_rejects_unknown_mode():
     from paper_1212_1397_amd import helmholtz6 as h6
     assert h6._lib.helmholtz6_set_graphs(None, 1) == h6.H6_ERR_ARG
+
+
+def test_rhs_neumann_rejects_bad_arguments():
+    from paper_1212_1397_amd import helmholtz6 as h6
+    assert h6._lib.helmholtz6_rhs_neumann(None, 4, 1, None, None, None, None, None) == h6.H6_ERR_ARG

@@ -19,9 +19,10 @@ import pytest
 import torch
 
 import oracle
-from manufactured import (cuda_values, factor_tables, mixed_pattern_u, neumann_y_factor, source,
-                          table3_u, table5_u, sommerfeld_z_factor)
-from oracle.functions import Cos, Poly, Separable, Term
+from manufactured import (cuda_values, face_tables, factor_tables, mixed_pattern_u, neumann_data_y_u,
+                          neumann_data_z_u, neumann_y_factor, normal_derivative, source, table3_u, table5_u,
+                          sommerfeld_z_factor)
+from oracle.functions import Cos, Poly, Separable, Sin, Term
 
 pytestmark = pytest.mark.gpu
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
@@ -215,3 +216,62 @@ def test_psi_rows(h6, table):
         assert g > 0
         if table == "table4":
             assert abs(g - p) < 0.2
+
+
+def neumann_data_x_u():
+    return Separable([Term(0.8 + 0.3j, Sin(math.pi / 2), Sin(math.pi), Sin(2 * math.pi)),
+                      Term(0.4, Cos(math.pi) * Poly((0.5, 1.0)), Sin(2 * math.pi), Sin(math.pi))])
+
+
+NEUMANN_CASES = [
+    ("DDDDND", (10, 12, 13), 7.0, neumann_data_z_u, (4,)),
+    ("DDNNDD", (9, 11, 10), 5.0 + 0.2j, neumann_data_y_u, (2, 3)),
+    ("NNDDSS", (12, 9, 10), 6.0 + 0.1j, neumann_data_x_u, (0, 1)),
+]
+
+
+def gpu_rhs_with_neumann(plan, prob, u, k, faces):
+    coef, tx, ty, tz = factor_tables(source(u, k), prob.points())
+    F = plan.rhs_separable(coef, tx, ty, tz)
+    for face in faces:
+        ax, side = divmod(face, 2)
+        g = normal_derivative(u, ax)
+        c, t1, t2 = face_tables(g, prob.points(), ax, 0.0 if side == 0 else prob.length(ax))
+        plan.rhs_neumann(face, c, t1, t2, F)
+    return F
+
+
+@pytest.mark.parametrize("bc,n,k,ufun,faces", NEUMANN_CASES)
+def test_neumann_data_rhs_matches_oracle(h6, bc, n, k, ufun, faces):
+    """Nonzero Neumann data (eq. (3DN)) on z, y and x faces: device F equals the oracle's."""
+    h = 1.0 / (max(n) + 1)
+    prob = oracle.Problem(n, h, complex(k), tuple(bc))
+    u = ufun()
+    ref = oracle.rhs(prob, source(u, k), neumann={f: normal_derivative(u, f // 2) for f in faces})
+    plan = h6.Plan(n, h, k, bc)
+    F = gpu_rhs_with_neumann(plan, prob, u, k, faces).cpu().numpy()
+    err = np.abs(F - ref).max() / np.abs(ref).max()
+    print(f"{bc} faces {faces}: max |F_gpu - F_oracle| / max |F| = {err:.2e}", flush=True)
+    assert err < 1e-12
+    with pytest.raises(h6.H6Error):
+        plan.rhs_neumann(5 if bc[5] != "N" else 4 if bc[4] != "N" else 0, *face_tables(
+            normal_derivative(u, 2), prob.points(), 2, 0.0), torch.zeros_like(torch.from_numpy(ref)).cuda())
+
+
+def test_neumann_data_solution_is_sixth_order(h6):
+    """With nonzero u_z on the Neumann face, GPU solutions on F built on the
+    device converge at sixth order (error ratio about 64 per halving of h)."""
+    k = 10.0
+    u = neumann_data_z_u()
+    errs = []
+    for n in (15, 31, 63):
+        prob = oracle.Problem.cube(n, k, "DDDDND")
+        plan = h6.Plan(prob.n, prob.h, k, "DDDDND")
+        F = gpu_rhs_with_neumann(plan, prob, u, k, (4,))
+        U, info = plan.solve(F, method="gmres", restart=30, tol=1e-12, maxit=300)
+        assert info["status"] == "ok"
+        errs.append(float((U - cuda_values(u, prob.points())).abs().max()))
+        plan.close()
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    print(f"errors {errs}, ratios {r}", flush=True)
+    assert all(56 <= x <= 72 for x in r), r
