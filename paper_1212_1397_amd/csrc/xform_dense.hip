@@ -61,29 +61,47 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
   typename M::V acc4[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc4[t] = typename M::V{0, 0, 0, 0};
-  for (int q0 = 0; q0 < L; q0 += kKC) {
+  // staging of one K chunk in registers: 32 lines x 16 q of the data
+  // (contiguous along q) and 64 m x 16 q of W (padded: always in bounds);
+  // the next chunk's loads are issued before the current chunk's MFMAs
+  R xre[2], xim[2], wv4[4];
+  auto load = [&](int q0) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {                 // 32 lines x 16 q, contiguous along q
+    for (int j = 0; j < 2; ++j) {
       const int i = tid + 256 * j;
       const int ll = i / kKC, qq = i % kKC;
       const int line = line0 + ll, q = q0 + qq;
-      R re = 0, im = 0;
+      xre[j] = 0;
+      xim[j] = 0;
       if (line < nlines && q < L) {
         const Tin v = in[size_t(line) * L + q];
-        re = R(v.x);
-        im = R(v.y);
+        xre[j] = R(v.x);
+        xim[j] = R(v.y);
       }
-      const int wv = ll >> 3, li = ll & 7;
-      As[16 * wv + M::xrow(li, 0)][qq] = re;
-      As[16 * wv + M::xrow(li, 1)][qq] = im;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {                 // 64 m x 16 q of W (padded: in bounds)
+    for (int j = 0; j < 4; ++j) {
       const int i = tid + 256 * j;
-      const int mm = i / kKC, qq = i % kKC;
-      Ws[mm][qq] = W[size_t(m0 + mm) * Lq + q0 + qq];
+      wv4[j] = W[size_t(m0 + i / kKC) * Lq + q0 + i % kKC];
+    }
+  };
+  load(0);
+  for (int q0 = 0; q0 < L; q0 += kKC) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = tid + 256 * j;
+      const int ll = i / kKC, qq = i % kKC;
+      const int wv = ll >> 3, li = ll & 7;
+      As[16 * wv + M::xrow(li, 0)][qq] = xre[j];
+      As[16 * wv + M::xrow(li, 1)][qq] = xim[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = tid + 256 * j;
+      Ws[i / kKC][i % kKC] = wv4[j];
     }
     __syncthreads();
+    if (q0 + kKC < L) load(q0 + kKC);
 #pragma unroll
     for (int kk = 0; kk < kKC / 4; ++kk) {
       const R a = As[16 * w + (lane & 15)][4 * kk + (lane >> 4)];
@@ -138,17 +156,28 @@ __global__ __launch_bounds__(256) void dense_y_kernel(const R* __restrict__ in, 
   typename M::V acc4[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc4[t] = typename M::V{0, 0, 0, 0};
+  // one K chunk in registers (64 m x 16 q of W, 16 rows x 64 columns of the
+  // plane, contiguous along columns); the next chunk is loaded during the MFMAs
+  R wv4[4], xv4[4];
+  auto load = [&](int q0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = tid + 256 * j;
+      wv4[j] = W[size_t(m0 + i / kKC) * Lq + q0 + i % kKC];
+      const int q = q0 + i / kT, c = c0 + i % kT;
+      xv4[j] = (q < L && c < ncols) ? X[size_t(q) * ncols + c] : R(0);
+    }
+  };
+  load(0);
   for (int q0 = 0; q0 < L; q0 += kKC) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = tid + 256 * j;
-      const int mm = i / kKC, qq = i % kKC;
-      Ws[mm][qq] = W[size_t(m0 + mm) * Lq + q0 + qq];
-      const int qr = i / kT, cc = i % kT;        // 16 rows x 64 columns, contiguous along columns
-      const int q = q0 + qr, c = c0 + cc;
-      Xs[qr][cc] = (q < L && c < ncols) ? X[size_t(q) * ncols + c] : R(0);
+      Ws[i / kKC][i % kKC] = wv4[j];
+      Xs[i / kT][i % kT] = xv4[j];
     }
     __syncthreads();
+    if (q0 + kKC < L) load(q0 + kKC);
 #pragma unroll
     for (int kk = 0; kk < kKC / 4; ++kk) {
       const R a = Ws[16 * w + (lane & 15)][4 * kk + (lane >> 4)];
