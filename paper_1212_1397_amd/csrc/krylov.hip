@@ -154,9 +154,13 @@ __global__ __launch_bounds__(kThreads) void update_gram_kernel(double2* __restri
 // MGS coefficients of Arnoldi step j (one wave):
 //   nu_j = |q~_j|,  G_{j,i} = conj(<q~_i, q~_j>) / (nu_i nu_j)  (i < j),
 //   h_i = <q~_i, w~> / (nu_i nu_j) - sum_{l<i} G_{i,l} h_l,  c_i = nu_j h_i / nu_i.
-// The triangular recurrence runs over i; each inner sum is split over the
-// lanes and reduced in a fixed order.
+// For j < 64 the Gram rows are staged in LDS (packed lower triangle, loads
+// batched) and the recurrence runs column by column: lane i holds h_i, and
+// at step l the final h_l is broadcast by a lane shuffle and subtracted from
+// the lanes below.  Larger j: the recurrence runs over i, each inner sum split
+// over the lanes and reduced in a fixed order.
 constexpr int kCoefMax = 257;
+constexpr int kCoefFast = 64;
 __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __restrict__ dots,
                                                       const double* __restrict__ nrow,
                                                       const double* __restrict__ gram2,
@@ -166,9 +170,11 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
                                                       const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double2 h[kCoefMax];
+  __shared__ double2 Gt[kCoefFast * (kCoefFast - 1) / 2];   // rows 1..63, entry (r, c) at r(r-1)/2 + c
   const int t = threadIdx.x;
   const double nuj = sqrt(fmax(nrow[0], 0.0));
   if (t == 0) nu[j] = nuj;
+  const bool fast = j < kCoefFast;
   for (int i = t; i < j; i += 64) {
     double lx, ly;
     if (i < kGramMax) {
@@ -179,7 +185,53 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
       ly = gram2[2 * (i - kGramMax) + 1];
     }
     const double d = nu[i] * nuj;
-    G[size_t(j) * gdim + i] = make_double2(lx / d, -ly / d);
+    const double2 gv = make_double2(lx / d, -ly / d);
+    G[size_t(j) * gdim + i] = gv;
+    if (fast) Gt[j * (j - 1) / 2 + i] = gv;
+  }
+  if (fast) {
+    const int cnt = j * (j - 1) / 2;          // entries of rows 1 .. j-1
+    for (int e0 = 0; e0 < cnt; e0 += 4 * 64) {
+      double2 v[4];
+      int at[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {           // four loads in flight per lane
+        const int e = e0 + u * 64 + t;
+        at[u] = -1;
+        if (e < cnt) {
+          int r = int((1.0 + sqrt(1.0 + 8.0 * double(e))) * 0.5);
+          while (r * (r - 1) / 2 > e) --r;
+          while ((r + 1) * r / 2 <= e) ++r;
+          v[u] = G[size_t(r) * gdim + (e - r * (r - 1) / 2)];
+          at[u] = e;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (at[u] >= 0) Gt[at[u]] = v[u];
+    }
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    double nui = 1.0;
+    if (t <= j) {
+      nui = t == j ? nuj : nu[t];
+      const double d = nui * nuj;
+      acc = make_double2(dots[2 * t] / d, dots[2 * t + 1] / d);
+    }
+    for (int l = 0; l < j; ++l) {
+      const double hx = __shfl(acc.x, l, 64), hy = __shfl(acc.y, l, 64);   // h_l, final
+      if (t > l && t <= j) {
+        const double2 g = Gt[t * (t - 1) / 2 + l];
+        acc.x -= g.x * hx - g.y * hy;
+        acc.y -= g.x * hy + g.y * hx;
+      }
+    }
+    if (t <= j) {
+      hcol[t] = acc;
+      const double f = nuj / nui;
+      coef[t] = make_double2(f * acc.x, f * acc.y);
+    }
+    return;
   }
   __syncthreads();
   for (int i = 0; i <= j; ++i) {
