@@ -21,13 +21,17 @@ synchronisations.  The process prints one JSON line:
                        stream, recorded by the library),
   cpu_baseline         the FP64 CPU oracle running the same solver on a bounded
                        sample of the same problem (two iterations), scaled to
-                       the iteration count of the FP64 GPU solve,
+                       the iteration count of the FP64 GPU solve; `operators`:
+                       the oracle's apply_A and apply_Pinv on the 128^3 and
+                       256^3 workloads (one call each),
   extra                the other methods (plain FP64 GMRES and SKS, mixed
                        FGMRES) timed once each, the per-kernel breakdown, the
                        learned correction in mixed FGMRES(30) (committed
                        weights) with its network's matrix-core throughput, and
                        the 96-problem batch (batched + graphs + autotuned vs
-                       sequential plain solves).
+                       sequential plain solves), and `operators`: the GPU's
+                       apply_A and apply_Pinv (FP64 and mixed plans) on the
+                       128^3 and 256^3 workloads.
 """
 from __future__ import annotations
 
@@ -113,6 +117,60 @@ def run_cpu_baseline(w, method: str, iters: int):
                       f"{dt:.1f} s, scaled to the {iters} iterations of the FP64 GPU solve; "
                       f"numpy/scipy on one host thread",
             "sample_seconds": round(dt, 2)}
+
+
+OPERATOR_WORKLOADS = ("dns-128", "dns-256")
+
+
+def gpu_operator_times(reps: int = 10):
+    """Milliseconds per apply_A / apply_Pinv call on the GPU (average of `reps`
+    calls between two synchronisations, after one warm-up call)."""
+    import torch
+    from paper_1212_1397_amd import helmholtz6 as h6
+    from paper_1212_1397_amd.workloads import WORKLOADS
+    out = {}
+    for name in OPERATOR_WORKLOADS:
+        w = WORKLOADS[name]
+        res = {}
+        for prec in ("fp64", "mixed"):
+            plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=prec)
+            plan.autotune(TUNE_CACHE)
+            g = torch.Generator(device="cuda").manual_seed(5)
+            x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda", generator=g)
+            y = torch.empty_like(x)
+            times = {}
+            for op, fn in (("apply_A", plan.apply_A), ("apply_Pinv", plan.apply_Pinv)):
+                fn(x, y)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn(x, y)
+                torch.cuda.synchronize()
+                times[op + "_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 4)
+            res[prec] = times
+            plan.close()
+            del x, y
+        out[name] = res
+    return out
+
+
+def oracle_operator_times():
+    """Seconds of one apply_A / apply_Pinv call of the FP64 oracle on the host."""
+    import oracle
+    from paper_1212_1397_amd.workloads import WORKLOADS, random_field
+    out = {}
+    for name in OPERATOR_WORKLOADS:
+        w = WORKLOADS[name]
+        prob = oracle.Problem.cube(w.n, w.k, w.bc)
+        x = random_field(prob.shape, 5)
+        t0 = time.perf_counter()
+        oracle.apply_A(prob, x)
+        t1 = time.perf_counter()
+        oracle.apply_Pinv(prob, x)
+        t2 = time.perf_counter()
+        out[name] = {"apply_A_s": round(t1 - t0, 3), "apply_Pinv_s": round(t2 - t1, 3)}
+        del x
+    return out
 
 
 def main():
@@ -252,10 +310,14 @@ def main():
     if not args.no_extra and not args.no_batch:
         from paper_1212_1397_amd import batch
         extra["batch"] = batch.run()
+    if not args.no_extra:
+        extra["operators"] = gpu_operator_times()
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(w, "sks" if meth == "sks" else "gmres", fp64_iters or info["iters"])
+        if not args.no_extra:
+            cpu["operators"] = oracle_operator_times()
 
     out = {
         "metric": "s to 1e-8 resid @256^3: mixed/learned vs plain FP64 GPU; stencil+precond HBM GB/s",
