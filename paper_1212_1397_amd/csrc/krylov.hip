@@ -457,6 +457,15 @@ int reduction_blocks() {
   return blocks;
 }
 
+// the grid for vectors of n elements: at least 2048 elements per block (short
+// vectors get fewer blocks and fewer partial sums to reduce), at most the
+// resident wave above
+int reduction_blocks(size_t n) {
+  const size_t want = (n + 2047) / 2048;
+  const int full = reduction_blocks();
+  return want < size_t(full) ? int(want > 0 ? want : 1) : full;
+}
+
 // compile-time chunk counts 1..16
 #define H6_COUNTS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
@@ -464,7 +473,7 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
                              double* out, hipStream_t s, const int* skip) {
   // one grid size for all chunks (the partials of all 2m components are
   // reduced together)
-  const int nb = reduction_blocks();
+  const int nb = reduction_blocks(n);
   for (int i0 = 0; i0 < m; i0 += kDotChunk) {
     const int cnt = m - i0 < kDotChunk ? m - i0 : kDotChunk;
     switch (cnt) {
@@ -483,7 +492,7 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
 
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
                               double* partials, double* out, hipStream_t s, const int* skip) {
-  const int nb = reduction_blocks();
+  const int nb = reduction_blocks(n);
   const int mg = m < kGramChunk ? m : kGramChunk;
   if (mg < 1) return hipErrorInvalidValue;
   switch (mg) {
