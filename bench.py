@@ -31,7 +31,9 @@ synchronisations.  The process prints one JSON line:
                        the 96-problem batch (batched + graphs + autotuned vs
                        sequential plain solves), and `operators`: the GPU's
                        apply_A and apply_Pinv (FP64 and mixed plans) on the
-                       128^3 and 256^3 workloads.
+                       128^3 and 256^3 workloads, and `dense_transform`: the
+                       matrix-core transform passes at 128^3 (M = 129) in
+                       TFLOP/s against the FP32 matrix peak.
 """
 from __future__ import annotations
 
@@ -151,6 +153,42 @@ def gpu_operator_times(reps: int = 10):
             plan.close()
             del x, y
         out[name] = res
+    return out
+
+
+def dense_transform_roofline(reps: int = 20):
+    """The matrix-core dense transforms (every M without a fast path) on the
+    128^3 workload (M = 129), complex64 plan: average launch time of the x and
+    y passes inside apply_Pinv (library HIP events) and their throughput,
+    4 L flop per element (a real L x L matrix applied to re and im), against
+    the FP32 matrix-core peak."""
+    import torch
+    from paper_1212_1397_amd import helmholtz6 as h6
+    from paper_1212_1397_amd.workloads import WORKLOADS
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    g = torch.Generator(device="cuda").manual_seed(6)
+    x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    plan.apply_Pinv(x, y)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    for cls in ("xform_x", "xform_y"):
+        plan.kernel_time(cls, reset=True)
+    for _ in range(reps):
+        plan.apply_Pinv(x, y)
+    torch.cuda.synchronize()
+    N = plan.dims[0] * plan.dims[1] * plan.dims[2]
+    out = {"workload": w.name, "grid_unknowns": list(plan.dims), "precision": "complex64 (FP32 MFMA)",
+           "peak_tflops": 157.3}
+    for cls, L in (("xform_x", plan.dims[0]), ("xform_y", plan.dims[1])):
+        ms, n, _ = plan.kernel_time(cls)
+        us = ms * 1e3 / max(n, 1)
+        tf = 4.0 * L * N / (us * 1e-6) / 1e12
+        out[cls] = {"line_length": L, "avg_us": round(us, 2), "tflops": round(tf, 1),
+                    "frac": round(tf / 157.3, 4), "launches": n}
+    plan.profile(False)
+    plan.close()
     return out
 
 
@@ -312,6 +350,7 @@ def main():
         extra["batch"] = batch.run()
     if not args.no_extra:
         extra["operators"] = gpu_operator_times()
+        extra["dense_transform"] = dense_transform_roofline()
 
     cpu = None
     if not args.no_cpu_baseline:
