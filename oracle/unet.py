@@ -28,6 +28,13 @@ GMRES.  Definition (the one the GPU path implements):
   Re(k) h]; the correction is c = s (y_0 + i y_1).  (The scaling makes the
   map r -> c positively homogeneous of degree one.)
 * Loss of a training pair (r, target t): L = sum |c - t|^2 / sum |t|^2.
+* Operator-weighted loss with a linear operator A (the h^2-scaled operator of
+  eq. (scheme) on the pair's grid): L_A = sum |A (c - t)|^2 / sum |A t|^2, the
+  quantity a correction must lower to pass the solver's judge (t = e - A_p^{-1} r
+  gives A t = r - A A_p^{-1} r).  Its gradient uses A^H u = conj(A conj(u)),
+  exact when A is complex symmetric (Dirichlet faces); with Neumann or
+  Sommerfeld faces A is not symmetric in its closure rows and this is the
+  training gradient by definition (the GPU computes the same).
 
 Gradients are written out by hand (the adjoint of each step in reverse
 order); the tests pin them to central finite differences.
@@ -196,6 +203,22 @@ def loss_and_grads(params, r, k, h, target):
     diff = c - target
     L = float(np.sum(np.abs(diff) ** 2)) / den
     dy = np.stack([2.0 * s * diff.real, 2.0 * s * diff.imag]) / den
+    grads, _ = backward(params, cache, dy)
+    return L, grads
+
+
+def loss_and_grads_op(params, r, k, h, target, apply_A):
+    """Operator-weighted relative error L_A = |A (c - t)|^2 / |A t|^2 and its
+    parameter gradients (apply_A: vector -> A vector, complex symmetric A)."""
+    x, s = features(r, k, h)
+    y, cache = forward(params, x)
+    c = s * (y[0] + 1j * y[1])
+    At = apply_A(target)
+    den = float(np.sum(np.abs(At) ** 2))
+    u = apply_A(c - target)
+    L = float(np.sum(np.abs(u) ** 2)) / den
+    g = np.conj(apply_A(np.conj(u)))          # A^H u for complex symmetric A
+    dy = np.stack([2.0 * s * g.real, 2.0 * s * g.imag]) / den
     grads, _ = backward(params, cache, dy)
     return L, grads
 

@@ -145,3 +145,29 @@ def test_adam_first_step_closed_form():
     unet.adam_step(params, grads, state, lr=0.1)
     np.testing.assert_allclose(params["a"][0], [[1.0 - 0.1 * 0.3 / (0.3 + 1e-8), -2.0 + 0.1 * 4.0 / (4.0 + 1e-8)]])
     np.testing.assert_allclose(params["a"][1], [0.5 - 0.1 * 1e-3 / (1e-3 + 1e-8)])
+
+
+def test_operator_loss_gradients_finite_differences():
+    """L_A = |A (c - t)|^2 / |A t|^2 with the Dirichlet operator of eq. (scheme)
+    (complex symmetric there, so A^H u = conj(A conj(u)) is exact): parameter
+    gradients against central differences, and A = I reduces to the plain loss."""
+    import oracle
+    shape = (5, 6, 7)
+    params, r, t = small_problem(shape)
+    prob = oracle.Problem(tuple(reversed(shape)), 1.0 / 8, 30.0 + 0.0j, tuple("DDDDDD"))
+    A = lambda v: oracle.apply_A(prob, v)
+    k, h = prob.k, prob.h
+    L, grads = unet.loss_and_grads_op(params, r, k, h, t, A)
+    f = lambda: unet.loss_and_grads_op(params, r, k, h, t, A)[0]
+    rng = np.random.default_rng(13)
+    for name, _, _, _ in unet.LAYERS:
+        W, b = params[name]
+        idx = tuple(int(rng.integers(0, s)) for s in W.shape)
+        assert np.isclose(grads[name][0][idx], _fd(f, W, idx), rtol=1e-5, atol=1e-9), (name, idx)
+        j = (int(rng.integers(0, b.shape[0])),)
+        assert np.isclose(grads[name][1][j], _fd(f, b, j), rtol=1e-5, atol=1e-9), (name, j)
+    L0, g0 = unet.loss_and_grads(params, r, k, h, t)
+    L1, g1 = unet.loss_and_grads_op(params, r, k, h, t, lambda v: v)
+    assert np.isclose(L0, L1, rtol=1e-14)
+    for name in g0:
+        np.testing.assert_allclose(g1[name][0], g0[name][0], rtol=1e-12, atol=1e-15)
