@@ -75,6 +75,21 @@ h6_status h6net_gradients(h6_net net, const void* r, double kh, const void* t, f
 h6_status h6net_train_step(h6_net net, const void* r, double kh, const void* t, float lr,
                            double* loss, void* hip_stream);
 
+/* Operator-weighted loss of a pair (r, t) on a plan's grid (the quantity the
+ * solver's judge measures: with t = e - A_p^{-1} r, A t = r - A A_p^{-1} r):
+ *   L_A = sum |A (c(r) - t)|^2 / sum |A t|^2,  A = the plan's operator of
+ * eq. (scheme) (helmholtz6_apply_A), kh = Re(k) h of the plan.  The gradient
+ * takes the adjoint of A as conj(A conj(.)), exact for all-Dirichlet faces
+ * (A complex symmetric); with Neumann or Sommerfeld faces this defines the
+ * training gradient.  Same outputs and synchronisation as h6net_gradients /
+ * h6net_train_step; the net must have been created for the plan's dims
+ * (H6_ERR_ARG otherwise).  Three complex128 work vectors are allocated on
+ * first use. */
+h6_status h6net_gradients_op(h6_net net, h6_plan plan, const void* r, const void* t, float* grads,
+                             double* loss, void* hip_stream);
+h6_status h6net_train_step_op(h6_net net, h6_plan plan, const void* r, const void* t, float lr,
+                              double* loss, void* hip_stream);
+
 /* Attaches (net != NULL) or detaches (NULL) the network to a plan: flexible
  * GMRES solves of the plan then use z = A_p^{-1} q + c(q) for the Arnoldi
  * vectors of every restart cycle whose first step the correction does not

@@ -379,6 +379,37 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y,
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// b = a - t (complex128)
+__global__ void sub_kernel(const double2* __restrict__ a, const double2* __restrict__ t, double2* __restrict__ b,
+                           long long P) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double2 x = a[v], y = t[v];
+  b[v] = make_double2(x.x - y.x, x.y - y.y);
+}
+
+// b = conj(a)
+__global__ void conj_kernel(const double2* __restrict__ a, double2* __restrict__ b, long long P) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double2 x = a[v];
+  b[v] = make_double2(x.x, -x.y);
+}
+
+// operator-weighted loss: the output gradient from w = A conj(u), u = A (c - t):
+// dL/dc = 2 conj(w) / den, dY = s dL/dc (BF16, channels 0, 1)
+__global__ void op_grad_kernel(const double2* __restrict__ w, const double* __restrict__ nrm2,
+                               const double* __restrict__ den, long long P, bf16* __restrict__ dy) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double s = sqrt(*nrm2 / double(P));
+  const double dn = *den;
+  const double f = dn > 0.0 ? 2.0 * s / dn : 0.0;
+  const double2 x = w[v];
+  dy[v * 16] = f2bf(float(f * x.x));
+  dy[v * 16 + 1] = f2bf(float(-f * x.y));
+}
+
 __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, long long n, float lr, float c1, float c2) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -435,7 +466,9 @@ struct h6_net_s {
   h6::bf16 *dB3 = nullptr, *dT3 = nullptr, *dPl2 = nullptr;
   float* part = nullptr;
   float* bpart = nullptr;
-  // scalars: [0] |r|^2, [1] |t|^2, [2] loss numerator
+  // operator-weighted loss: three complex128 work vectors (allocated on first use)
+  double2* opbuf = nullptr;
+  // scalars: [0] |r|^2, [1] |t|^2 (or |A t|^2), [2] loss numerator
   double* d_scal = nullptr;
   double* partials = nullptr;
   double* h_scal = nullptr;     // pinned
@@ -610,6 +643,35 @@ hipError_t loss_backward(h6_net N, const double2* t, hipStream_t s) {
   return backward(N, s);
 }
 
+// operator-weighted loss |A (c - t)|^2 / |A t|^2 of the current forward
+// output (A: the plan's operator); gradients into N->grad.  The adjoint is
+// taken as conj(A conj(.)), exact for complex symmetric A (Dirichlet faces).
+hipError_t op_loss_backward(h6_net N, h6_plan plan, const double2* t, hipStream_t s) {
+  const long long P = N->g1.P();
+  hipError_t e = hipSuccess;
+  if (!N->opbuf) {
+    if ((e = dalloc(N, &N->opbuf, size_t(3 * P))) != hipSuccess) return e;
+  }
+  double2* b0 = N->opbuf;
+  double2* b1 = b0 + P;
+  double2* b2 = b1 + P;
+  const unsigned nb = nblk(P);
+  // |A t|^2
+  if ((e = launch_stencil(plan, t, b2, nullptr, nullptr, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_norm2(b2, size_t(P), N->partials, N->d_scal + 1, s)) != hipSuccess) return e;
+  // u = A (c - t), |u|^2
+  hipLaunchKernelGGL(output_kernel, dim3(nb), dim3(256), 0, s, N->Y, N->d_scal, P, static_cast<void*>(b0), 0);
+  hipLaunchKernelGGL(sub_kernel, dim3(nb), dim3(256), 0, s, b0, t, b0, P);
+  if ((e = launch_stencil(plan, b0, b1, nullptr, nullptr, nullptr, s)) != hipSuccess) return e;
+  if ((e = launch_norm2(b1, size_t(P), N->partials, N->d_scal + 2, s)) != hipSuccess) return e;
+  // w = A conj(u)
+  hipLaunchKernelGGL(conj_kernel, dim3(nb), dim3(256), 0, s, b1, b0, P);
+  if ((e = launch_stencil(plan, b0, b2, nullptr, nullptr, nullptr, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(op_grad_kernel, dim3(nb), dim3(256), 0, s, b2, N->d_scal, N->d_scal + 1, P, N->dY);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return backward(N, s);
+}
+
 }  // namespace
 }  // namespace h6
 
@@ -714,6 +776,52 @@ h6_status h6net_train_step(h6_net N, const void* r, double kh, const void* t, fl
   if (alloc_training(N) != hipSuccess) return H6_ERR_ALLOC;
   if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess ||
       loss_backward(N, static_cast<const double2*>(t), s) != hipSuccess)
+    return H6_ERR_HIP;
+  N->adam_t += 1;
+  const float c1 = float(1.0 / (1.0 - std::pow(0.9, N->adam_t)));
+  const float c2 = float(1.0 / (1.0 - std::pow(0.999, N->adam_t)));
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(N->np)), dim3(256), 0, s, N->w32, N->grad, N->m, N->v, N->np,
+                     lr, c1, c2);
+  if (pack_all(N, s) != hipSuccess) return H6_ERR_HIP;
+  if (loss) {
+    if (hipMemcpyAsync(N->h_scal, N->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return H6_ERR_HIP;
+    *loss = N->h_scal[1] > 0.0 ? N->h_scal[2] / N->h_scal[1] : 0.0;
+  }
+  return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
+}
+
+static bool op_args_ok(h6_net N, h6_plan plan) {
+  return N && plan && net_matches(N, plan->dims);
+}
+
+h6_status h6net_gradients_op(h6_net N, h6_plan plan, const void* r, const void* t, float* grads, double* loss,
+                             void* hip_stream) {
+  if (!op_args_ok(N, plan) || !r || !t) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (alloc_training(N) != hipSuccess) return H6_ERR_ALLOC;
+  const double kh = plan->k.real() * plan->p.h;
+  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess ||
+      op_loss_backward(N, plan, static_cast<const double2*>(t), s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (hipMemcpyAsync(N->h_scal, N->d_scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (grads && hipMemcpyAsync(grads, N->grad, size_t(N->np) * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return H6_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return H6_ERR_HIP;
+  if (loss) *loss = N->h_scal[1] > 0.0 ? N->h_scal[2] / N->h_scal[1] : 0.0;
+  return H6_OK;
+}
+
+h6_status h6net_train_step_op(h6_net N, h6_plan plan, const void* r, const void* t, float lr, double* loss,
+                              void* hip_stream) {
+  if (!op_args_ok(N, plan) || !r || !t) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (alloc_training(N) != hipSuccess) return H6_ERR_ALLOC;
+  const double kh = plan->k.real() * plan->p.h;
+  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess ||
+      op_loss_backward(N, plan, static_cast<const double2*>(t), s) != hipSuccess)
     return H6_ERR_HIP;
   N->adam_t += 1;
   const float c1 = float(1.0 / (1.0 - std::pow(0.9, N->adam_t)));

@@ -31,8 +31,8 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune",
             "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z", "helmholtz6_rhs_neumann")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
-                "h6net_forward", "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
-                "helmholtz6_learned_steps", "h6net_destroy")
+                "h6net_forward", "h6net_gradients", "h6net_train_step", "h6net_gradients_op",
+                "h6net_train_step_op", "helmholtz6_attach_net", "helmholtz6_learned_steps", "h6net_destroy")
 # layers of the correction network: (name, Cin, Cout), in parameter order
 NET_LAYERS = (("e1a", 3, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32), ("b3a", 32, 64),
               ("b3b", 64, 64), ("d2a", 96, 32), ("d2b", 32, 32), ("d1a", 48, 16), ("d1b", 16, 16),
@@ -105,12 +105,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.h6net_forward.argtypes = [vp, vp, ctypes.c_double, vp, vp]
     lib.h6net_gradients.argtypes = [vp, vp, ctypes.c_double, vp, fp, dp, vp]
     lib.h6net_train_step.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_float, dp, vp]
+    lib.h6net_gradients_op.argtypes = [vp, vp, vp, vp, fp, dp, vp]
+    lib.h6net_train_step_op.argtypes = [vp, vp, vp, vp, ctypes.c_float, dp, vp]
     lib.helmholtz6_attach_net.argtypes = [vp, vp]
     lib.helmholtz6_learned_steps.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.h6net_destroy.argtypes = [vp]
     lib.h6net_destroy.restype = None
     for name in ("h6net_create", "h6net_set_params", "h6net_get_params", "h6net_forward",
-                 "h6net_gradients", "h6net_train_step", "helmholtz6_attach_net",
+                 "h6net_gradients", "h6net_train_step", "h6net_gradients_op", "h6net_train_step_op",
+                 "helmholtz6_attach_net",
                  "helmholtz6_learned_steps"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -381,6 +384,25 @@ class Net:
         self._check(_lib.h6net_train_step(self._net, self._vec(r, "r"), float(kh), self._vec(t, "t"),
                                           float(lr), ctypes.byref(loss) if want_loss else None,
                                           _stream_handle(stream)), "train_step")
+        return loss.value if want_loss else None
+
+    def gradients_op(self, plan, r, t, stream=None):
+        """(operator-weighted loss |A (c - t)|^2 / |A t|^2, flat float32
+        gradients) of the pair (r, t) on plan's grid, without an update."""
+        import numpy as np
+        g = np.empty(self.count, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(_lib.h6net_gradients_op(self._net, plan._plan, self._vec(r, "r"), self._vec(t, "t"),
+                                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            ctypes.byref(loss), _stream_handle(stream)), "gradients_op")
+        return loss.value, g
+
+    def train_step_op(self, plan, r, t, lr: float, want_loss: bool = True, stream=None):
+        """One Adam step on the operator-weighted loss of (r, t) on plan's grid."""
+        loss = ctypes.c_double()
+        self._check(_lib.h6net_train_step_op(self._net, plan._plan, self._vec(r, "r"), self._vec(t, "t"),
+                                             float(lr), ctypes.byref(loss) if want_loss else None,
+                                             _stream_handle(stream)), "train_step_op")
         return loss.value if want_loss else None
 
     def close(self):

@@ -7,10 +7,15 @@ Algorithm 1 on the complex64-preconditioned plan): for a problem A U = F with
 reference solution U* (flexible GMRES to 1e-11) and SKS iterates U_j, the
 residual r_j = F - A U_j and error e_j = U* - U_j satisfy A e_j = r_j; the
 network is trained to output t_j = e_j - A_p^{-1} r_j, what the plain
-preconditioner misses.
+preconditioner misses.  Two losses: "plain", |c(r) - t|^2 / |t|^2, and
+"operator", |A (c(r) - t)|^2 / |A t|^2.  Since A t = r - A A_p^{-1} r, the
+operator loss is the squared ratio of the residual of the corrected
+preconditioner to that of the plain one, the quantity by which the flexible
+solver accepts or rejects a correction.
 
     python -m paper_1212_1397_amd.learned train --out weights.npz [--n 128] [--problems 16]
                                               [--iters 8] [--steps 1500] [--seed 4]
+                                              [--loss plain|operator] [--init weights.npz]
     python -m paper_1212_1397_amd.learned eval  --weights weights.npz [--workload dns-256]
     python -m paper_1212_1397_amd.learned speed [--workload dns-256]
 """
@@ -39,8 +44,9 @@ def problem(n: int, seed: int):
     return kr * (1 + 0.01j), random_sources(nsrc, seed + 1000, h), h
 
 
-def make_pairs(n: int, nproblems: int, iters: int, seed: int, log=print):
-    """[(r, t, kh)] on the GPU from plain solves of `nproblems` seeded problems."""
+def make_pairs(n: int, nproblems: int, iters: int, seed: int, log=print, keep_plans: bool = False):
+    """[(r, t, kh, plan)] on the GPU from plain solves of `nproblems` seeded
+    problems; plan is the problem's (open) plan if keep_plans, else None."""
     pairs = []
     for p in range(nproblems):
         k, (centres, amps, sigma), h = problem(n, seed + p)
@@ -55,23 +61,28 @@ def make_pairs(n: int, nproblems: int, iters: int, seed: int, log=print):
                 Uj, _ = plan.solve(F, method="sks", tol=0.0, maxit=j)
             r = F - plan.apply_A(Uj)
             t = (Us - Uj) - plan.apply_Pinv(r)
-            pairs.append((r, t, kh))
+            pairs.append((r, t, kh, plan if keep_plans else None))
         log(f"problem {p}: k = {k:.2f}, reference {info['iters']} FGMRES steps "
             f"(rel resid {info['rel_resid']:.1e}), {iters} pairs")
-        plan.close()
+        if not keep_plans:
+            plan.close()
     return pairs
 
 
-def train(net: h6.Net, pairs, steps: int, lr0: float = 1e-3, seed: int = 0, log=print):
-    """Adam over randomly drawn pairs with a cosine learning-rate decay; returns the loss history."""
+def train(net: h6.Net, pairs, steps: int, lr0: float = 1e-3, seed: int = 0, log=print, loss: str = "plain"):
+    """Adam over randomly drawn pairs with a cosine learning-rate decay; returns
+    the loss history.  loss = "operator" needs pairs made with keep_plans."""
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.perf_counter()
     for s in range(steps):
         lr = lr0 * 0.5 * (1 + np.cos(np.pi * s / steps)) + 1e-5
-        r, t, kh = pairs[int(rng.integers(len(pairs)))]
+        r, t, kh, plan = pairs[int(rng.integers(len(pairs)))]
         want = s % 25 == 0 or s == steps - 1
-        L = net.train_step(r, kh, t, lr, want_loss=want)
+        if loss == "operator":
+            L = net.train_step_op(plan, r, t, lr, want_loss=want)
+        else:
+            L = net.train_step(r, kh, t, lr, want_loss=want)
         if want:
             hist.append((s, L))
             log(f"step {s}: loss {L:.4f} lr {lr:.2e} ({time.perf_counter() - t0:.1f} s)")
@@ -79,13 +90,18 @@ def train(net: h6.Net, pairs, steps: int, lr0: float = 1e-3, seed: int = 0, log=
     return hist, time.perf_counter() - t0
 
 
-def pair_losses(net: h6.Net, pairs):
+def pair_losses(net: h6.Net, pairs, operator: bool = False):
     """Per pair (|c(r) - t|, |t|): the error of the corrected preconditioner
-    A_p^{-1} r + c(r) against e, and that of the plain one (t = e - A_p^{-1} r)."""
+    A_p^{-1} r + c(r) against e, and that of the plain one (t = e - A_p^{-1} r);
+    with operator, (|A (c - t)|, |A t|): the residuals of the two
+    preconditioners (pairs made with keep_plans)."""
     out = []
-    for r, t, kh in pairs:
+    for r, t, kh, plan in pairs:
         c = net.forward(r, kh)
-        out.append((float(torch.linalg.norm(c - t)), float(torch.linalg.norm(t))))
+        if operator:
+            out.append((float(torch.linalg.norm(plan.apply_A(c - t))), float(torch.linalg.norm(plan.apply_A(t)))))
+        else:
+            out.append((float(torch.linalg.norm(c - t)), float(torch.linalg.norm(t))))
     return out
 
 
@@ -167,6 +183,8 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=4)
     t.add_argument("--holdout", type=int, default=2)
+    t.add_argument("--loss", choices=("plain", "operator"), default="plain")
+    t.add_argument("--init", default=None, help="start from these weights (.npz) instead of a seeded init")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--workload", default="dns-256")
@@ -175,20 +193,31 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.cmd == "train":
-        pairs = make_pairs(args.n, args.problems, args.iters, args.seed, log)
-        held = make_pairs(args.n, args.holdout, args.iters, args.seed + 10_000, log)
+        op = args.loss == "operator"
+        pairs = make_pairs(args.n, args.problems, args.iters, args.seed, log, keep_plans=op)
+        held = make_pairs(args.n, args.holdout, args.iters, args.seed + 10_000, log, keep_plans=True)
         dims = tuple(pairs[0][0].shape[::-1])
         net = h6.Net(dims)
-        net.set_params(h6.pack_net_params(init_net_params(h6.NET_LAYERS, args.seed)))
-        hist, secs = train(net, pairs, args.steps, args.lr, args.seed, log)
-        ev = pair_losses(net, held)
-        ratio = float(np.mean([a / b for a, b in ev]))
-        log(f"held-out pairs: mean |c - t| / |t| = {ratio:.4f} (1 = no gain over the plain preconditioner)")
+        if args.init:
+            net.set_params(np.load(args.init)["params"])
+        else:
+            net.set_params(h6.pack_net_params(init_net_params(h6.NET_LAYERS, args.seed)))
+        before = [a / b for a, b in pair_losses(net, held, operator=True)]
+        hist, secs = train(net, pairs, args.steps, args.lr, args.seed, log, loss=args.loss)
+        ratio = float(np.mean([a / b for a, b in pair_losses(net, held)]))
+        ratio_op = [a / b for a, b in pair_losses(net, held, operator=True)]
+        log(f"held-out pairs: mean |c - t| / |t| = {ratio:.4f}; mean |A (c - t)| / |A t| = "
+            f"{np.mean(ratio_op):.4f} (before training {np.mean(before):.4f}; 1 = no gain)")
         params = net.get_params()
-        np.savez(args.out, params=params, loss=np.array(hist), heldout_ratio=ratio, train_seconds=secs,
+        np.savez(args.out, params=params, loss=np.array(hist), heldout_ratio=ratio,
+                 heldout_op_ratio=float(np.mean(ratio_op)), train_seconds=secs, loss_kind=args.loss,
                  n=args.n, problems=args.problems, iters=args.iters, steps=args.steps, seed=args.seed)
+        for _, _, _, plan in pairs + held:
+            if plan is not None:
+                plan.close()
         res = solve_compare(WORKLOADS["dns-128"], params, log)
-        print(json.dumps({"train_seconds": round(secs, 2), "heldout_ratio": ratio,
+        print(json.dumps({"loss": args.loss, "train_seconds": round(secs, 2), "heldout_ratio": ratio,
+                          "heldout_op_ratio": [round(x, 4) for x in ratio_op],
                           "final_loss": hist[-1][1], "dns-128": res}))
     elif args.cmd == "eval":
         params = np.load(args.weights)["params"]

@@ -109,6 +109,42 @@ def test_gradients_match_oracle(h6, regime):
         assert eW < tol and eb < tol, name
 
 
+@pytest.mark.parametrize("bc,precision", [("DDDDDD", "fp64"), ("DDNNSS", "mixed")])
+def test_operator_gradients_match_oracle(h6, bc, precision):
+    """Operator-weighted loss |A (c - t)|^2 / |A t|^2: loss and gradients
+    against the oracle with its own A (the gradient uses conj(A conj(.)) on
+    both sides, so the comparison holds for every face type)."""
+    import oracle
+    n, h, k = (12, 10, 9), 1.0 / 13, 30.0 + 0.3j
+    p = params_for_test(out_scale=100.0, bias=1.0, wscale=0.3)
+    plan = h6.Plan(n, h, k, bc, precision=precision)
+    dims = plan.dims
+    net = h6.Net(dims)
+    net.set_params(h6.pack_net_params(p))
+    shape = (dims[2], dims[1], dims[0])
+    r = random_field(shape, 6)
+    t = 0.3 * random_field(shape, 7)
+    prob = oracle.Problem(n, h, k, tuple(bc))
+    assert prob.shape == shape
+    A = lambda v: oracle.apply_A(prob, v)
+    loss, g = net.gradients_op(plan, torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda())
+    L_ref, grads = unet.loss_and_grads_op(oracle_params(p), r, k, h, t, A)
+    print(f"{bc}: op loss gpu {loss:.6e} oracle {L_ref:.6e}", flush=True)
+    assert abs(loss - L_ref) / L_ref < 1e-2
+    gg = h6.unpack_net_params(g)
+    for name, _, _, _ in unet.LAYERS:
+        eW = rel(gg[name][0], grads[name][0])
+        eb = rel(gg[name][1], grads[name][1])
+        print(f"  {name}: dW rel err {eW:.2e}, db rel err {eb:.2e}", flush=True)
+        assert eW < 3e-2 and eb < 3e-2, name
+    l0 = net.train_step_op(plan, torch.from_numpy(r).cuda(), torch.from_numpy(t).cuda(), 1e-3)
+    assert abs(l0 - loss) / loss < 1e-6
+    other = h6.Net((dims[0] + 1, dims[1], dims[2]))
+    z = torch.zeros(other.shape, dtype=torch.complex128, device="cuda")
+    with pytest.raises(h6.H6Error):
+        other.gradients_op(plan, z, z)
+
+
 def test_adam_step_and_loss_decrease(h6):
     dims = (12, 10, 9)
     p = params_for_test(out_scale=100.0)
