@@ -294,7 +294,6 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->d_lambda_x);
   (void)hipFree(P->d_lambda_y);
   for (auto& a : P->ax) (void)hipFree(a.wmat);
-  (void)hipFree(P->d_tri);
   (void)hipFree(P->d_cstart);
   for (void* w : P->w_pc) (void)hipFree(w);
   (void)hipFree(P->V);
@@ -390,11 +389,16 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
       free_plan(P);
       return H6_ERR_ARG;
     }
-  std::vector<double2> tri(3 * P->dims[2]);
-  for (int l = 0; l < P->dims[2]; ++l) {
-    tri[l] = make_double2(sub[l].real(), sub[l].imag());
-    tri[P->dims[2] + l] = make_double2(diag[l].real(), diag[l].imag());
-    tri[2 * P->dims[2] + l] = make_double2(sup[l].real(), sup[l].imag());
+  {
+    const int L = P->dims[2];
+    for (int l = 0; l < L; ++l)           // inner rows are (1, -2, 1)
+      if ((l > 0 && l < L - 1) && (sub[l] != 1.0 || sup[l] != 1.0 || diag[l] != -2.0)) {
+        err = "internal: z tridiagonal inner row";
+        free_plan(P);
+        return H6_ERR_ARG;
+      }
+    const double o0 = L > 1 ? sup[0].real() : 1.0, ol = L > 1 ? sub[L - 1].real() : 1.0;
+    P->zends = ZEnds{diag[0].real(), diag[0].imag(), 1.0 / o0, diag[L - 1].real(), diag[L - 1].imag(), 1.0 / ol};
   }
   hipError_t e = hipSuccess;
   std::vector<StencilTable> st(1, P->stencil);
@@ -403,7 +407,6 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   if (e == hipSuccess) e = upload(&P->d_lambda_y, ly, s);
   for (int a = 0; a < 2 && e == hipSuccess; ++a)
     e = p->precision == H6_MIXED ? build_dense<float>(P->ax[a], s) : build_dense<double>(P->ax[a], s);
-  if (e == hipSuccess) e = upload(&P->d_tri, tri, s);
   if (e == hipSuccess) {
     if (p->precision == H6_MIXED) {
       std::vector<float2> cf(cstart.size());

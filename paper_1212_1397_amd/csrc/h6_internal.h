@@ -59,6 +59,18 @@ struct AxisXform {
   void* rader_mem = nullptr;   // one device allocation holding the tables
 };
 
+// End rows of T_z for the z solver.  T_z is tridiag(1, -2, 1) inside; row 0
+// and row n'z - 1 carry an off-diagonal of 1 or 2 and a main-diagonal term on
+// Sommerfeld faces.  Dividing those two rows by their off-diagonal makes every
+// off-diagonal 1 (the Thomas quantities c' and d' do not change under row
+// scaling); the solver then needs only the two scaled end rows:
+//   row 0:      s0 ((b0_re + i b0_im) + shift) x_0 + x_1 = s0 r_0,
+//   row n'z-1:  x_{n'z-2} + sl ((bl_re + i bl_im) + shift) x_{n'z-1} = sl r_{n'z-1}.
+struct ZEnds {
+  double b0_re, b0_im, s0;
+  double bl_re, bl_im, sl;
+};
+
 struct Timing {
   bool enabled = false;
   double ms[KC_COUNT] = {0};
@@ -97,7 +109,7 @@ struct h6_plan_s {
   h6::StencilTable* d_stencil = nullptr;
   double* d_lambda_x = nullptr;     // transverse eigenvalues per mode
   double* d_lambda_y = nullptr;
-  double2* d_tri = nullptr;         // z tridiagonal: sub, diag, sup (3 * n'z complex)
+  h6::ZEnds zends{};                // end rows of the z tridiagonal (scaled form)
   void* d_cstart = nullptr;         // Thomas c' entering each z segment: [z_segments(n'z)][n'x n'y], complex
                                     // (double2, or float2 in mixed plans)
 

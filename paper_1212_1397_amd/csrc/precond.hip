@@ -52,22 +52,6 @@ __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename
   return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Partitioned Gaussian elimination without pivoting (the Thomas algorithm
-// with its recurrences re-associated) on T_z + shift I, one transverse mode per
-// line.  A workgroup owns kLanes consecutive modes (lanes) and splits every
-// z line into kSegs segments of S <= kSmax rows, one thread each, rows held in
-// registers.  Thomas' recurrences are
-//   c'_i = c_i / m_i,  m_i = b_i - a_i c'_{i-1}        (data independent),
-//   d'_i = (d_i - a_i d'_{i-1}) / m_i                   (affine in d'_{i-1}),
-//   x_i  = d'_i - c'_i x_{i+1}                           (affine in x_{i+1}).
-// The c' value entering each segment depends only on the matrix, so the plan
-// stores it (cstart[seg][mode], computed in FP64 at setup with the pivot
-// check).  Each thread replays c' over its rows, composes the two affine maps
-// over its segment, and the segment maps are chained in order through LDS.
-// HBM traffic: one read and one write of the vector plus the small cstart table.
-// launch shapes: kLanes modes x kSegs segments = 512 threads; 32 x 16 up to
-// n'z = 272 (256-byte row segments), 16 x 32 above (n'z <= 544)
-
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T csub(typename C2<R>::T a, typename C2<R>::T b) {
   return mk<R>(a.x - b.x, a.y - b.y);
@@ -93,18 +77,37 @@ __device__ __forceinline__ typename C2<R>::T crecip(typename C2<R>::T b) {
   return mk<R>(b.x * d, -b.y * d);
 }
 
+// Partitioned Gaussian elimination without pivoting (the Thomas algorithm
+// with its recurrences re-associated) on T_z + shift I, one transverse mode per
+// line.  With the end rows scaled as described at ZEnds, every off-diagonal is
+// 1 and the main diagonal is b = shift - 2 except on rows 0 and n'z - 1, so
+// Thomas' recurrences read
+//   p_i = 1 / (b_i - c'_{i-1}),  c'_i = p_i                 (data independent),
+//   d'_i = p_i (d_i - d'_{i-1})                            (affine in d'_{i-1}),
+//   x_i  = d'_i - p_i x_{i+1}                               (affine in x_{i+1}).
+// A workgroup owns kLanes consecutive modes (lanes) and splits every z line
+// into kSegs segments of S <= kSmax rows, one thread each, rows held in
+// registers.  The c' value entering each segment depends only on the matrix,
+// so the plan stores it (cstart[seg][mode], computed in FP64 at setup with the
+// pivot check).  Each thread replays c' over its rows and composes both affine
+// maps over its segment: their linear parts are the same product of -p_i, so
+// one product serves the forward and the backward chain.  The segment maps are
+// chained in order through LDS.  Row 0 of the system never sees the value
+// entering from above (it is zero) and row n'z - 1 never sees the one from
+// below, so their missing off-diagonal needs no special case.
+// HBM traffic: one read and one write of the vector plus the small cstart table.
+// launch shapes: kLanes modes x kSegs segments = 512 threads; 32 x 16 up to
+// n'z = 272 (256-byte row segments), 16 x 32 above (n'z <= 544)
+
 template <typename R, int kLanes, int kSegs, int kSmax>
 __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
     const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
-    const double2* __restrict__ tri, const typename C2<R>::T* __restrict__ cstart,
-    const double* __restrict__ lx, const double* __restrict__ ly, double kap_re, double kap_im,
-    int nx, int ny, int nz, const int* __restrict__ skip) {
+    const typename C2<R>::T* __restrict__ cstart, const double* __restrict__ lx,
+    const double* __restrict__ ly, double kap_re, double kap_im, ZEnds ends, int nx, int ny, int nz,
+    const int* __restrict__ skip) {
   if (skip && *skip) return;
   using T2 = typename C2<R>::T;
-  constexpr int kThr = kLanes * kSegs;
-  constexpr int kTabPer = (3 * kMaxZ + kThr - 1) / kThr;
   __shared__ T2 sh[2][kSegs][kLanes];
-  __shared__ T2 tz[kTabPer * kThr];  // sub-, main and super-diagonal of T_z (main without the shift)
   const int tid = threadIdx.x;
   const int lane = tid % kLanes;
   const int seg = tid / kLanes;
@@ -116,71 +119,63 @@ __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
   const size_t stride = size_t(nx) * ny;
   const int S = (nz + kSegs - 1) / kSegs;
   const int r0 = min(seg * S, nz), cnt = min(S, nz - r0);
+  // the last row sits in segment segL at offset uL (the same for every thread)
+  const int segL = (nz - 1) / S, uL = nz - 1 - segL * S;
+  const bool first = seg == 0, last = seg == segL;
   const T2 one = mk<R>(1, 0), zero = mk<R>(0, 0);
 
-  // All global reads are issued up front and unconditionally (clamped
-  // indices): first the matrix (it is written to LDS first, so waiting for it
-  // leaves the vector loads in flight), then the start value of c', the
-  // transverse eigenvalues and this thread's rows of the vector.
-  double2 tv[kTabPer];
-#pragma unroll
-  for (int k = 0; k < kTabPer; ++k) tv[k] = tri[min(tid + k * kThr, 3 * nz - 1)];
+  // global reads up front, with clamped indices
   const T2 cst = cstart[size_t(seg) * nmodes + mc];
   const double lxi = lx[i], lyj = ly[j];
-  T2 d[kSmax], ip[kSmax];     // right-hand side, then d'; inverse pivots 1/m_i
+  T2 d[kSmax], p[kSmax];     // right-hand side, then d'; inverse pivots p_i
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) d[u] = in[mc + size_t(min(r0 + u, nz - 1)) * stride];
-#pragma unroll
-  for (int k = 0; k < kTabPer; ++k) tz[tid + k * kThr] = cvt<T2>(tv[k]);   // entries past 3 n'z unused
-  __syncthreads();
-  const T2 shift = mk<R>(R(kap_re + lxi + lyj), R(kap_im));
 
-  // The off-diagonals of T_z are real (1 inside, 0 or 2 on the end rows):
-  // a and c scale complex values by real factors.
   auto scl = [](T2 v, R f) { return mk<R>(v.x * f, v.y * f); };
-  // local pass: c' from the stored start value, inverse pivots, and the
-  // affine map d'_{last} = A d'_{r0-1} + B
-  T2 cprev = cst, A = one, B = zero;
+  const T2 shift = mk<R>(R(kap_re + lxi + lyj), R(kap_im));
+  const T2 bM = cadd<R>(mk<R>(-2, 0), shift);
+  const T2 bF = scl(cadd<R>(mk<R>(R(ends.b0_re), R(ends.b0_im)), shift), R(ends.s0));
+  const T2 bL = scl(cadd<R>(mk<R>(R(ends.bl_re), R(ends.bl_im)), shift), R(ends.sl));
+  if (first) d[0] = scl(d[0], R(ends.s0));
+#pragma unroll
+  for (int u = 0; u < kSmax; ++u)
+    if (u == uL && last) d[u] = scl(d[u], R(ends.sl));
+
+  // local pass: inverse pivots from the stored c', and the affine map
+  // d'_{last} = Q d'_{r0-1} + B
+  T2 cprev = cst, Q = one, B = zero;
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
-      const int r = r0 + u;
-      const R a = tz[r].x, c = tz[2 * nz + r].x;
-      const T2 b = cadd<R>(tz[nz + r], shift);
-      ip[u] = crecip<R>(csub<R>(b, scl(cprev, a)));
-      const T2 al = scl(ip[u], -a);
-      A = cmulr<R>(al, A);
-      B = cadd<R>(cmulr<R>(al, B), cmulr<R>(d[u], ip[u]));
-      cprev = scl(ip[u], c);
+      T2 b = bM;
+      if (u == 0 && first) b = bF;
+      if (u == uL && last) b = bL;
+      p[u] = crecip<R>(csub<R>(b, cprev));
+      Q = cmulr<R>(mk<R>(-p[u].x, -p[u].y), Q);
+      B = cmulr<R>(p[u], csub<R>(d[u], B));
+      cprev = p[u];
     } else {
-      ip[u] = zero;
+      p[u] = zero;
     }
   }
-  sh[0][seg][lane] = A;
+  sh[0][seg][lane] = Q;
   sh[1][seg][lane] = B;
   __syncthreads();
   T2 dprev = zero;
   for (int s2 = 0; s2 < seg; ++s2) dprev = cadd<R>(cmulr<R>(sh[0][s2][lane], dprev), sh[1][s2][lane]);
-  // replay d', then compose the back substitution x_{r0} = C x_{r0+cnt} + D
+  // replay d', then compose the back substitution x_{r0} = Q x_{r0+cnt} + D
 #pragma unroll
   for (int u = 0; u < kSmax; ++u) {
     if (u < cnt) {
-      const R a = tz[r0 + u].x;
-      d[u] = cmulr<R>(csub<R>(d[u], scl(dprev, a)), ip[u]);
+      d[u] = cmulr<R>(p[u], csub<R>(d[u], dprev));
       dprev = d[u];
     }
   }
-  T2 C = one, D = zero;
+  T2 D = zero;
 #pragma unroll
-  for (int u = kSmax - 1; u >= 0; --u) {
-    if (u < cnt) {
-      const T2 ncp = scl(ip[u], -tz[2 * nz + r0 + u].x);     // -c'_u
-      D = cadd<R>(d[u], cmulr<R>(ncp, D));
-      C = cmulr<R>(ncp, C);
-    }
-  }
+  for (int u = kSmax - 1; u >= 0; --u)
+    if (u < cnt) D = csub<R>(d[u], cmulr<R>(p[u], D));
   __syncthreads();
-  sh[0][seg][lane] = C;
   sh[1][seg][lane] = D;
   __syncthreads();
   T2 x = zero;
@@ -188,7 +183,7 @@ __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
 #pragma unroll
   for (int u = kSmax - 1; u >= 0; --u) {
     if (u < cnt) {
-      x = csub<R>(d[u], cmulr<R>(scl(ip[u], tz[2 * nz + r0 + u].x), x));
+      x = csub<R>(d[u], cmulr<R>(p[u], x));
       if (active) out[mode + size_t(r0 + u) * stride] = x;
     }
   }
@@ -232,8 +227,8 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
     const double kr = P->kappa.real(), ki = P->kappa.imag();
     const T2* cst = static_cast<const T2*>(P->d_cstart);
     auto go = [&](auto kern, int lanes) {
-      hipLaunchKernelGGL(kern, dim3((nx * ny + lanes - 1) / lanes), dim3(512), 0, s, w1, w0, P->d_tri, cst,
-                         P->d_lambda_x, P->d_lambda_y, kr, ki, nx, ny, nz, P->skip);
+      hipLaunchKernelGGL(kern, dim3((nx * ny + lanes - 1) / lanes), dim3(512), 0, s, w1, w0, cst,
+                         P->d_lambda_x, P->d_lambda_y, kr, ki, P->zends, nx, ny, nz, P->skip);
     };
     if (z_segments(nz, sizeof(R) == 4) == 16) {
       if (nz <= 16 * 5) go(tridiag_z_kernel<R, 32, 16, 5>, 32);
