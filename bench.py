@@ -211,6 +211,24 @@ def oracle_operator_times():
     return out
 
 
+def device_copy_gbs(x, reps: int = 10) -> float:
+    """Measured device-to-device copy bandwidth (read + write bytes / time) of
+    a vector the size of the workload's, the practical ceiling that the
+    kernels' HBM fractions are also quoted against."""
+    import torch
+    a = torch.empty_like(x)
+    a.copy_(x)                                   # warm-up
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        a.copy_(x)
+    t1.record()
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a
+    return round(2 * x.numel() * x.element_size() / (1e-3 * ms) / 1e9, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,13 +315,18 @@ def main():
             rec["gbs"] = round(nbytes / (1e-3 * ms) / 1e9, 1)
             rec["frac_hbm"] = round(rec["gbs"] / HBM_PEAK_GBS, 4)
         kernels[c] = rec
+    copy_gbs = device_copy_gbs(F)
+    for rec in kernels.values():
+        if "gbs" in rec:
+            rec["frac_copy"] = round(rec["gbs"] / copy_gbs, 4)
     bw = {c: r for c, r in kernels.items() if "gbs" in r}
     dom = max(bw, key=lambda c: bw[c]["ms_total"])
     roofline = {"bound": "hbm", "kernel": dom, "achieved": bw[dom]["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": bw[dom]["frac_hbm"],
                 "traffic": measured_traffic(w.name, args.method, dom),
                 "alg_bytes_per_launch": bw[dom]["alg_bytes_per_launch"],
-                "avg_launch_us": bw[dom]["avg_us"]}
+                "avg_launch_us": bw[dom]["avg_us"],
+                "copy_gbs": copy_gbs, "frac_of_copy": bw[dom]["frac_copy"]}
 
     extra = {"kernels": kernels}
     fp64_name = "fp64-sks" if meth == "sks" else "fp64-gmres"
