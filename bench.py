@@ -361,7 +361,10 @@ def main():
             d = np.load(wpath)
             res = learned.solve_compare(w, d["params"], log=lambda m: None)
             f_s, f_tf = learned.speed(plan.dims, reps=3)
-            res.update({"heldout_error_ratio": float(d["heldout_ratio"]),
+            res.update({"training_loss": str(d["loss_kind"]) if "loss_kind" in d.files else "plain",
+                        "heldout_error_ratio": float(d["heldout_ratio"]),
+                        "heldout_residual_ratio": (float(d["heldout_op_ratio"])
+                                                   if "heldout_op_ratio" in d.files else None),
                         "forward_ms": round(1e3 * f_s, 3),
                         "roofline": {"bound": "mfma", "kernel": "conv (BF16 MFMA, whole forward pass)",
                                      "achieved": round(f_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
