@@ -18,14 +18,20 @@ synchronisations.  The process prints one JSON line:
   roofline             the kernel class with the largest share of that solve's
                        time: its algorithmic HBM bytes per launch over its
                        average launch duration (HIP events on the solve's
-                       stream, recorded by the library),
+                       stream, recorded by the library); `copy_gbs`: a
+                       device-to-device copy of a vector of the same size,
+                       measured beside it, and `frac_of_copy`,
   cpu_baseline         the FP64 CPU oracle running the same solver on a bounded
                        sample of the same problem (two iterations), scaled to
                        the iteration count of the FP64 GPU solve; `operators`:
                        the oracle's apply_A and apply_Pinv on the 128^3 and
                        256^3 workloads (one call each),
   extra                the other methods (plain FP64 GMRES and SKS, mixed
-                       FGMRES) timed once each, the per-kernel breakdown, the
+                       FGMRES) timed once each with every solution's relative
+                       difference from the plain FP64 GMRES one, the median
+                       and minimum of the K timed solves, the per-kernel
+                       breakdown (with counter-measured GB/s where a current
+                       counter summary is committed), the
                        learned correction in mixed FGMRES(30) (committed
                        weights) with its network's matrix-core throughput, and
                        the 96-problem batch (batched + graphs + autotuned vs
@@ -287,11 +293,16 @@ def main():
     for _ in range(args.warmup):
         info = one_solve(plan, meth)
     torch.cuda.synchronize()
+    per_step = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         info = one_solve(plan, meth)
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    solutions = {args.method: U.clone()}
     print(f"# timed {args.steps} solves: {dt * 1e3:.2f} ms/solve, {info['iters']} iterations, "
           f"rel resid {info['rel_resid']:.3e}", file=sys.stderr, flush=True)
 
@@ -328,7 +339,14 @@ def main():
                 "avg_launch_us": bw[dom]["avg_us"],
                 "copy_gbs": copy_gbs, "frac_of_copy": bw[dom]["frac_copy"]}
 
-    extra = {"kernels": kernels}
+    for c, rec in kernels.items():
+        tb = measured_traffic(w.name, args.method, c) if "gbs" in rec else None
+        if tb:
+            rec["traffic_bytes_per_launch"] = tb
+            rec["traffic_gbs"] = round(tb * rec["launches"] / (1e-3 * rec["ms_total"]) / 1e9, 1)
+    per_step.sort()
+    extra = {"kernels": kernels, "ms_per_step_median": round(1e3 * per_step[len(per_step) // 2], 3),
+             "ms_per_step_min": round(1e3 * per_step[0], 3)}
     fp64_name = "fp64-sks" if meth == "sks" else "fp64-gmres"
     fp64_iters = info["iters"] if args.method == fp64_name else None
     if not args.no_extra:
@@ -345,8 +363,18 @@ def main():
             torch.cuda.synchronize()
             others[name] = {"s": round(time.perf_counter() - t1, 6), "iters": i2["iters"],
                             "rel_resid": i2["rel_resid"]}
+            solutions[name] = U.clone()
             if name == fp64_name:
                 fp64_iters = i2["iters"]
+        # every solution against the plain FP64 GMRES one (whose agreement with
+        # the FP64 oracle is established by the parity tests on smaller grids)
+        ref = solutions["fp64-gmres"]
+        nref = float(torch.linalg.norm(ref))
+        for name, Us in solutions.items():
+            if name != "fp64-gmres":
+                d = float(torch.linalg.norm(Us - ref)) / nref
+                (others[name] if name in others else extra.setdefault("headline", {}))["rel_diff_vs_fp64_gmres"] = d
+        del solutions, ref
         extra["methods"] = others
         if "fp64-gmres" in others:
             extra["speedup_vs_fp64_gmres"] = round(others["fp64-gmres"]["s"] / dt, 3)
