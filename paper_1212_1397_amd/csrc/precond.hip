@@ -33,20 +33,6 @@ __device__ __forceinline__ typename C2<R>::T mk(R a, R b) {
   return v;
 }
 
-template <typename Tdst, typename Tsrc>
-__device__ __forceinline__ Tdst cvt(Tsrc v) {
-  Tdst d;
-  d.x = v.x;
-  d.y = v.y;
-  return d;
-}
-
-template <typename R>
-__device__ __forceinline__ typename C2<R>::T cdiv(typename C2<R>::T a, typename C2<R>::T b) {
-  const R d = b.x * b.x + b.y * b.y;
-  return mk<R>((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
-
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T cmulr(typename C2<R>::T a, typename C2<R>::T b) {
   return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
