@@ -68,6 +68,9 @@ def test_network_rejects_bad_arguments():
     assert not out.value
     assert h6._lib.h6net_forward(None, None, 0.0, None, None) == h6.H6_ERR_ARG
     assert h6._lib.helmholtz6_attach_net(None, None) == h6.H6_ERR_ARG
+    loss = ctypes.c_double()
+    assert h6._lib.h6net_gradients_op(None, None, None, None, None, ctypes.byref(loss), None) == h6.H6_ERR_ARG
+    assert h6._lib.h6net_train_step_op(None, None, None, None, 1e-3, ctypes.byref(loss), None) == h6.H6_ERR_ARG
 
 
 def test_pack_unpack_roundtrip():
