@@ -124,6 +124,9 @@ struct h6_plan_s {
   double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
   double2* d_scal = nullptr;                   // device scalars: reduction results, coefficients (kScal entries)
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
+  double* h_parts = nullptr;   // coherent pinned host array of residual-norm partials (SKS), mapped:
+  double* d_parts = nullptr;   //   its device address; one entry per stencil workgroup
+  int parts_cap = 0;
   double2* d_gram = nullptr;  int gram_dim = 0;  // Gram matrix <q_i, q_l> of the Arnoldi basis (gram_dim^2)
   void* d_sep = nullptr;  size_t sep_bytes = 0;  // separable-source tables (helmholtz6_rhs_separable)
   hipEvent_t ev_sync = nullptr;                // host waits on scalars copied back mid-stream
@@ -193,6 +196,8 @@ hipError_t launch_pinv_f32out(h6_plan P, const double2* r, float2* z, hipStream_
 hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s);
 // r = F - A U stored in complex64 (FP64 arithmetic and |r|^2 partials), for
 // callers that only hand r to a complex64 preconditioner
+// workgroups of a stencil launch on this plan (one residual-norm partial each)
+int stencil_workgroups(h6_plan P);
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
                                double* partials, int* nparts, hipStream_t s);
 // Dense (matrix-core) transforms along x / y with the axis' basis matrices

@@ -81,6 +81,16 @@ h6_status ensure(h6_plan P, int method, int m) {
     }
   }
   if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m, zb);
+  if (e == hipSuccess && method == H6_SKS && P->parts_cap < stencil_workgroups(P)) {
+    if (P->h_parts) (void)hipHostFree(P->h_parts);
+    P->h_parts = P->d_parts = nullptr;
+    P->parts_cap = 0;
+    const int n = stencil_workgroups(P);
+    e = hipHostMalloc(reinterpret_cast<void**>(&P->h_parts), sizeof(double) * size_t(n),
+                      hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&P->d_parts), P->h_parts, 0);
+    if (e == hipSuccess) P->parts_cap = n;
+  }
   if (e == hipSuccess && P->use_graphs == 2 && (method == H6_GMRES || method == H6_FGMRES) &&
       P->givens_dim < m) {
     (void)hipFree(P->d_givens);
@@ -466,16 +476,30 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
 // device stays busy during the convergence test.  In mixed plans r is stored
 // in complex64 by the residual kernel (its norm is taken in FP64 first): the
 // preconditioner's first pass would round it to complex64 on load anyway.
+// The residual kernel writes its per-workgroup partial sums of |r|^2 straight
+// into coherent pinned host memory, and the host adds them in workgroup
+// order after the wait: no reduction kernel and no copy per iteration.
 h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
   h6_plan P = c.P;
   const bool mixed = P->p.precision == H6_MIXED;
   float2* r32 = reinterpret_cast<float2*>(P->r);
+  int nparts = 0;
+  if (!P->d_parts || stencil_workgroups(P) > P->parts_cap) {
+    P->last_error = "internal: residual partials exceed their host array";
+    return H6_ERR_HIP;
+  }
   auto resid = [&]() -> h6_status {
-    if (!mixed) return residual_async(c, F, U, P->r);
-    int nparts = 0;
-    H6_TRY_HIP(launch_resid_f32out(P, U, r32, F, P->partials, &nparts, c.s));
-    H6_TRY_HIP(launch_reduce_sum(P->partials, nparts, c.dev + kNorm, c.s));
-    return fetch_async(c, kNorm, 1);
+    if (mixed)
+      H6_TRY_HIP(launch_resid_f32out(P, U, r32, F, P->d_parts, &nparts, c.s));
+    else
+      H6_TRY_HIP(launch_stencil(P, U, P->r, F, P->d_parts, &nparts, c.s));
+    H6_TRY_HIP(hipEventRecord(P->ev_sync, c.s));
+    return H6_OK;
+  };
+  auto resid_norm2 = [&]() {
+    double a = 0.0;
+    for (int i = 0; i < nparts; ++i) a += P->h_parts[i];
+    return a;
   };
   auto pinv = [&](int part) -> hipError_t {
     return mixed ? launch_pinv_acc_f32in(P, r32, U, c.s, part) : launch_pinv_acc(P, P->r, U, c.s, part);
@@ -489,7 +513,7 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
     if (more) H6_TRY_HIP(pinv(PINV_FIRST));
     st = wait(c);
     if (st != H6_OK) return st;
-    info->rel_resid = std::sqrt(c.host[kNorm]) / normF;
+    info->rel_resid = std::sqrt(resid_norm2()) / normF;
     if (info->iters > 0) record(info, nh, info->rel_resid);
     if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
     if (!std::isfinite(info->rel_resid) || (info->iters > 0 && info->rel_resid > 1e4)) {

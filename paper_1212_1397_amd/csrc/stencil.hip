@@ -238,6 +238,11 @@ hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStrea
   return stencil_impl(P, x, y, static_cast<const double2*>(nullptr), nullptr, nullptr, s);
 }
 
+int stencil_workgroups(h6_plan P) {
+  const int tz = P->stencil_tz == 8 || P->stencil_tz == 32 ? P->stencil_tz : 16;
+  return ((P->dims[0] + kTX - 1) / kTX) * ((P->dims[1] + kTY - 1) / kTY) * ((P->dims[2] + tz - 1) / tz);
+}
+
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
                                double* partials, int* nparts, hipStream_t s) {
   return stencil_impl(P, U, r, F, partials, nparts, s);
