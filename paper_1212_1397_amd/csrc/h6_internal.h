@@ -175,8 +175,10 @@ __device__ __forceinline__ int xcd_remap(int bid, int nwg) {
 }
 
 // kernel launchers (stream-ordered, no synchronisation)
+// With F (residual form, y = F - A x): |y|^2 per workgroup into partials and,
+// when fpartials is given, |F|^2 per workgroup into fpartials.
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
-                          double* partials, int* nparts, hipStream_t s);
+                          double* partials, int* nparts, hipStream_t s, double* fpartials = nullptr);
 // Preconditioner passes: PINV_FIRST is the forward x transform of r alone,
 // PINV_REST the remaining passes (forward y, z solves, inverse y and x) on the
 // plan's workspace, so a caller can enqueue the first pass before it waits on
@@ -199,7 +201,7 @@ hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStrea
 // workgroups of a stencil launch on this plan (one residual-norm partial each)
 int stencil_workgroups(h6_plan P);
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
-                               double* partials, int* nparts, hipStream_t s);
+                               double* partials, int* nparts, hipStream_t s, double* fpartials = nullptr);
 // Dense (matrix-core) transforms along x / y with the axis' basis matrices
 // (xform_dense.hip); acc != 0: out += result
 template <typename R, typename Tin, typename Tout>

@@ -86,7 +86,7 @@ h6_status ensure(h6_plan P, int method, int m) {
     P->h_parts = P->d_parts = nullptr;
     P->parts_cap = 0;
     const int n = stencil_workgroups(P);
-    e = hipHostMalloc(reinterpret_cast<void**>(&P->h_parts), sizeof(double) * size_t(n),
+    e = hipHostMalloc(reinterpret_cast<void**>(&P->h_parts), 2 * sizeof(double) * size_t(n),
                       hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&P->d_parts), P->h_parts, 0);
     if (e == hipSuccess) P->parts_cap = n;
@@ -470,6 +470,17 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
   }
 }
 
+// F = 0: the solution is U = 0 (whatever the initial guess)
+h6_status zero_solution(Ctx& c, double2* U, h6_solve_info* info) {
+  h6_plan P = c.P;
+  H6_TRY_HIP(hipMemsetAsync(U, 0, c.N * sizeof(double2), c.s));
+  H6_TRY_HIP(hipStreamSynchronize(c.s));
+  info->iters = 0;
+  info->rel_resid = 0.0;
+  info->history_len = 0;
+  return H6_OK;
+}
+
 // SKS, Algorithm 1, in correction form: U += A_p^{-1} r (the update is made
 // by the last inverse transform pass), r = F - A U.  The first
 // preconditioner pass of r is enqueued before the host waits for |r|, so the
@@ -478,8 +489,10 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
 // preconditioner's first pass would round it to complex64 on load anyway.
 // The residual kernel writes its per-workgroup partial sums of |r|^2 straight
 // into coherent pinned host memory, and the host adds them in workgroup
-// order after the wait: no reduction kernel and no copy per iteration.
-h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double normF) {
+// order after the wait: no reduction kernel and no copy per iteration.  The
+// first residual pass also sums |F|^2 (it reads F anyway), which replaces
+// the separate norm pass of the other solvers.
+h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info) {
   h6_plan P = c.P;
   const bool mixed = P->p.precision == H6_MIXED;
   float2* r32 = reinterpret_cast<float2*>(P->r);
@@ -488,32 +501,39 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
     P->last_error = "internal: residual partials exceed their host array";
     return H6_ERR_HIP;
   }
-  auto resid = [&]() -> h6_status {
+  double* d_fparts = P->d_parts + P->parts_cap;
+  auto resid = [&](bool with_f) -> h6_status {
+    double* fp = with_f ? d_fparts : nullptr;
     if (mixed)
-      H6_TRY_HIP(launch_resid_f32out(P, U, r32, F, P->d_parts, &nparts, c.s));
+      H6_TRY_HIP(launch_resid_f32out(P, U, r32, F, P->d_parts, &nparts, c.s, fp));
     else
-      H6_TRY_HIP(launch_stencil(P, U, P->r, F, P->d_parts, &nparts, c.s));
+      H6_TRY_HIP(launch_stencil(P, U, P->r, F, P->d_parts, &nparts, c.s, fp));
     H6_TRY_HIP(hipEventRecord(P->ev_sync, c.s));
     return H6_OK;
   };
-  auto resid_norm2 = [&]() {
-    double a = 0.0;
-    for (int i = 0; i < nparts; ++i) a += P->h_parts[i];
-    return a;
+  auto host_sum = [&](const double* a) {
+    double t = 0.0;
+    for (int i = 0; i < nparts; ++i) t += a[i];
+    return t;
   };
   auto pinv = [&](int part) -> hipError_t {
     return mixed ? launch_pinv_acc_f32in(P, r32, U, c.s, part) : launch_pinv_acc(P, P->r, U, c.s, part);
   };
   int nh = 0;
-  h6_status st = resid();
+  h6_status st = resid(true);
   if (st != H6_OK) return st;
   info->iters = 0;
+  double normF = -1.0;
   while (true) {
     const bool more = info->iters < info->maxit;
     if (more) H6_TRY_HIP(pinv(PINV_FIRST));
     st = wait(c);
     if (st != H6_OK) return st;
-    info->rel_resid = std::sqrt(resid_norm2()) / normF;
+    if (normF < 0.0) {
+      normF = std::sqrt(host_sum(P->h_parts + P->parts_cap));
+      if (normF == 0.0) return zero_solution(c, U, info);
+    }
+    info->rel_resid = std::sqrt(host_sum(P->h_parts)) / normF;
     if (info->iters > 0) record(info, nh, info->rel_resid);
     if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
     if (!std::isfinite(info->rel_resid) || (info->iters > 0 && info->rel_resid > 1e4)) {
@@ -522,7 +542,7 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, double 
     }
     if (!more) { info->history_len = nh; return H6_NOT_CONVERGED; }
     H6_TRY_HIP(pinv(PINV_REST));
-    st = resid();
+    st = resid(false);
     if (st != H6_OK) return st;
     info->iters += 1;
   }
@@ -597,19 +617,13 @@ h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info
     s = P->gstream;
   }
   Ctx c{P, s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
+  info->iters = 0;
+  if (info->method == H6_SKS) return sks(c, F, U, info);    // |F| from its first residual pass
   double normF2 = 0.0;
   st = norm2(c, F, &normF2);
   if (st != H6_OK) return st;
   const double normF = std::sqrt(normF2);
-  info->iters = 0;
-  if (normF == 0.0) {
-    H6_TRY_HIP(hipMemsetAsync(U, 0, P->N * sizeof(double2), s));
-    H6_TRY_HIP(hipStreamSynchronize(s));
-    info->rel_resid = 0.0;
-    info->history_len = 0;
-    return H6_OK;
-  }
-  if (info->method == H6_SKS) return sks(c, F, U, info, normF);
+  if (normF == 0.0) return zero_solution(c, U, info);
   if (info->method == H6_CHEBYSHEV) return chebyshev(c, F, U, info, normF);
   return gmres(c, F, U, info, normF);
 }

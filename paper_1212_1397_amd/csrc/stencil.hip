@@ -48,7 +48,8 @@ __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_doub
 template <bool RESID, typename Tin, typename Tout, int kTZ>
 __global__ __launch_bounds__(kThreads) void stencil_kernel(
     const Tin* __restrict__ x, Tout* __restrict__ y, const double2* __restrict__ F,
-    double* __restrict__ partials, const StencilTable* __restrict__ W, int nx, int ny, int nz,
+    double* __restrict__ partials, double* __restrict__ fpartials, const StencilTable* __restrict__ W,
+    int nx, int ny, int nz,
     int xmir, int ymir, int zlo_cl, int zhi_cl, int ntx, int nty, int nwg, const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double2 tile[2][kLY][kLX];
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
   double2 acc_a[2], acc_b[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) acc_a[s] = acc_b[s] = make_double2(0.0, 0.0);
-  double nrm = 0.0;
+  double nrm = 0.0, fnrm = 0.0;   // |r|^2 and (fpartials != nullptr) |F|^2 of this workgroup's rows
 
   // planes stream through two register sets (loads issued two planes ahead)
   // into the double-buffered LDS tile
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
             const double2 f = F[o];
             out = make_double2(f.x - out.x, f.y - out.y);
             nrm = fma(out.x, out.x, fma(out.y, out.y, nrm));
+            fnrm = fma(f.x, f.x, fma(f.y, f.y, fnrm));
           }
           Tout yo;
           yo.x = out.x;           // complex64 output: rounded after the FP64 norm
@@ -191,6 +193,17 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
       for (int i = 0; i < kThreads / 64; ++i) t += red[i];
       partials[blockIdx.x] = t;
     }
+    if (fpartials) {
+      for (int o = 32; o > 0; o >>= 1) fnrm += __shfl_down(fnrm, o, 64);
+      __syncthreads();
+      if ((tid & 63) == 0) red[tid >> 6] = fnrm;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; ++i) t += red[i];
+        fpartials[blockIdx.x] = t;
+      }
+    }
   }
 }
 
@@ -198,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void stencil_kernel(
 
 template <typename Tin, typename Tout, int kTZ>
 hipError_t stencil_launch(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
-                          int* nparts, hipStream_t s) {
+                          int* nparts, hipStream_t s, double* fpartials) {
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
   const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY, ntz = (nz + kTZ - 1) / kTZ;
   const int nwg = ntx * nty * ntz;
@@ -208,11 +221,11 @@ hipError_t stencil_launch(h6_plan P, const Tin* x, Tout* y, const double2* F, do
   timing_begin(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, &ev);
   if (resid)
     hipLaunchKernelGGL((stencil_kernel<true, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y, F,
-                       partials, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
+                       partials, fpartials, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror, P->zlo_closure,
                        P->zhi_closure, ntx, nty, nwg, P->skip);
   else
     hipLaunchKernelGGL((stencil_kernel<false, Tin, Tout, kTZ>), dim3(nwg), dim3(kThreads), 0, s, x, y,
-                       nullptr, nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
+                       nullptr, nullptr, nullptr, P->d_stencil, nx, ny, nz, P->xmirror, P->ymirror,
                        P->zlo_closure, P->zhi_closure, ntx, nty, nwg, P->skip);
   timing_end(P, resid ? KC_STENCIL_RESID : KC_STENCIL, s, ev,
              double(P->N) * (sizeof(Tin) + sizeof(Tout) + (resid ? sizeof(double2) : 0)));
@@ -223,15 +236,15 @@ hipError_t stencil_launch(h6_plan P, const Tin* x, Tout* y, const double2* F, do
 // the plan's z-chunk depth (set by the autotuner; 16 by default)
 template <typename Tin, typename Tout>
 hipError_t stencil_impl(h6_plan P, const Tin* x, Tout* y, const double2* F, double* partials,
-                        int* nparts, hipStream_t s) {
-  if (P->stencil_tz == 8) return stencil_launch<Tin, Tout, 8>(P, x, y, F, partials, nparts, s);
-  if (P->stencil_tz == 32) return stencil_launch<Tin, Tout, 32>(P, x, y, F, partials, nparts, s);
-  return stencil_launch<Tin, Tout, 16>(P, x, y, F, partials, nparts, s);
+                        int* nparts, hipStream_t s, double* fpartials = nullptr) {
+  if (P->stencil_tz == 8) return stencil_launch<Tin, Tout, 8>(P, x, y, F, partials, nparts, s, fpartials);
+  if (P->stencil_tz == 32) return stencil_launch<Tin, Tout, 32>(P, x, y, F, partials, nparts, s, fpartials);
+  return stencil_launch<Tin, Tout, 16>(P, x, y, F, partials, nparts, s, fpartials);
 }
 
 hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2* F,
-                          double* partials, int* nparts, hipStream_t s) {
-  return stencil_impl(P, x, y, F, partials, nparts, s);
+                          double* partials, int* nparts, hipStream_t s, double* fpartials) {
+  return stencil_impl(P, x, y, F, partials, nparts, s, fpartials);
 }
 
 hipError_t launch_stencil_f32in(h6_plan P, const float2* x, double2* y, hipStream_t s) {
@@ -244,8 +257,8 @@ int stencil_workgroups(h6_plan P) {
 }
 
 hipError_t launch_resid_f32out(h6_plan P, const double2* U, float2* r, const double2* F,
-                               double* partials, int* nparts, hipStream_t s) {
-  return stencil_impl(P, U, r, F, partials, nparts, s);
+                               double* partials, int* nparts, hipStream_t s, double* fpartials) {
+  return stencil_impl(P, U, r, F, partials, nparts, s, fpartials);
 }
 
 }  // namespace h6

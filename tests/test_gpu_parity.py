@@ -196,5 +196,12 @@ def test_solver_status_codes():
     Z = torch.zeros_like(F)
     U, info = plan.solve(Z, method="gmres")
     assert info["status"] == "ok" and info["iters"] == 0 and float(U.abs().max()) == 0.0
+    # SKS takes |F| from its first residual pass: F = 0 still returns U = 0,
+    # whatever the initial guess, in both precisions
+    U0 = to_gpu(random_field(prob.shape, seed=2))
+    for prec in ("fp64", "mixed"):
+        pl = h6.Plan(prob.n, prob.h, prob.k, "DDDDDD", precision=prec)
+        U, info = pl.solve(Z, U0.clone(), method="sks")
+        assert info["status"] == "ok" and info["iters"] == 0 and float(U.abs().max()) == 0.0, prec
     with pytest.raises(ValueError):
         plan.apply_A(F[:, :, :-1].contiguous())
