@@ -307,6 +307,7 @@ void free_plan(h6_plan P) {
   if (P->ev_sync) (void)hipEventDestroy(P->ev_sync);
   if (P->h_pinned) (void)hipHostFree(P->h_pinned);
   if (P->h_parts) (void)hipHostFree(P->h_parts);
+  if (P->h_step) (void)hipHostFree(P->h_step);
   for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
   for (auto& pe : P->timing.pending) {
     (void)hipEventDestroy(pe.a);

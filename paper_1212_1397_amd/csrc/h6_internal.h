@@ -124,6 +124,8 @@ struct h6_plan_s {
   double* partials = nullptr;                  // per-block partial sums (2 * kMaxPartials doubles)
   double2* d_scal = nullptr;                   // device scalars: reduction results, coefficients (kScal entries)
   double2* h_pinned = nullptr;                 // pinned host mirror of d_scal
+  double* h_step = nullptr;    // coherent pinned host array for the Arnoldi step's Hessenberg column
+  double* d_step = nullptr;    //   and |w|^2 (written by the device), and its device address
   double* h_parts = nullptr;   // coherent pinned host array of residual-norm partials (SKS), mapped:
   double* d_parts = nullptr;   //   its device address; one entry per stencil workgroup
   int parts_cap = 0;
@@ -228,18 +230,21 @@ hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hi
 // skip (all Arnoldi-step launchers): device flag; when nonzero the kernels return at once
 hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n, double* partials,
                              double* out, hipStream_t s, const int* skip = nullptr);
-// w -= sum_{i<m} c_i q_i; out[0] = |w|^2, out[1+2i..2+2i] = <q_i, w> for i < min(m, kGramMax)
+// w -= sum_{i<m} c_i q_i; out[0] = |w|^2, out[1+2i..2+2i] = <q_i, w> for i < min(m, kGramMax);
+// hnorm (optional, host-mapped coherent memory): a copy of out[0] for the host
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
-                              double* partials, double* out, hipStream_t s, const int* skip = nullptr);
+                              double* partials, double* out, hipStream_t s, const int* skip = nullptr,
+                              double* hnorm = nullptr);
 // MGS coefficients of Arnoldi step j on the device (one workgroup), from the
 // block dots <q~_i, w~> (dots, i <= j), the norm / Gram row of the last update
 // pass (nrow: |q~_j|^2, <q~_i, q~_j> for i < min(j, kGramMax)) and the extra
 // Gram entries i = kGramMax .. j-1 (gram2): stores nu_j, row j of the Gram
 // matrix G (ld gdim), the Hessenberg column h (hcol) and the update
-// coefficients c_i = nu_j h_i / nu_i (coef).
+// coefficients c_i = nu_j h_i / nu_i (coef).  hmirror (optional, host-mapped
+// coherent memory): a copy of the Hessenberg column for the host.
 hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
                            double* nu, double2* G, int gdim, double2* hcol, double2* coef,
-                           hipStream_t s, const int* skip = nullptr);
+                           hipStream_t s, const int* skip = nullptr, double2* hmirror = nullptr);
 // out = |a - b|^2 (device double)
 hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
                              hipStream_t s);

@@ -167,7 +167,8 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
                                                       double* __restrict__ nu, double2* __restrict__ G,
                                                       int gdim, double2* __restrict__ hcol,
                                                       double2* __restrict__ coef,
-                                                      const int* __restrict__ skip) {
+                                                      const int* __restrict__ skip,
+                                                      double2* __restrict__ hmirror) {
   if (skip && *skip) return;
   __shared__ double2 h[kCoefMax];
   __shared__ double2 Gt[kCoefFast * (kCoefFast - 1) / 2];   // rows 1..63, entry (r, c) at r(r-1)/2 + c
@@ -228,6 +229,7 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
     }
     if (t <= j) {
       hcol[t] = acc;
+      if (hmirror) hmirror[t] = acc;
       const double f = nuj / nui;
       coef[t] = make_double2(f * acc.x, f * acc.y);
     }
@@ -251,6 +253,7 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
       const double2 hv = make_double2(dots[2 * i] / d - ax, dots[2 * i + 1] / d - ay);
       h[i] = hv;
       hcol[i] = hv;
+      if (hmirror) hmirror[i] = hv;
       const double f = nuj / nui;
       coef[i] = make_double2(f * hv.x, f * hv.y);
     }
@@ -261,7 +264,8 @@ __global__ __launch_bounds__(64) void mgs_coef_kernel(int j, const double* __res
 // out[c] = sum_b partials[c * nblocks + b], one block per component
 __global__ __launch_bounds__(kThreads) void reduce_cols_kernel(const double* __restrict__ partials,
                                                                int nblocks, double* __restrict__ out,
-                                                               const int* __restrict__ skip) {
+                                                               const int* __restrict__ skip,
+                                                               double* __restrict__ hout0) {
   if (skip && *skip) return;
   __shared__ double s[kThreads];
   double a = 0.0;
@@ -273,7 +277,10 @@ __global__ __launch_bounds__(kThreads) void reduce_cols_kernel(const double* __r
     if (threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = s[0];
+    if (hout0 && blockIdx.x == 0) hout0[0] = s[0];
+  }
 }
 
 // out (+)= sum_i y_i V_i, V_i = V + i * n (FP64 arithmetic).  Vectors are
@@ -411,17 +418,17 @@ constexpr int kGramChunk = kGramMax;
 
 hipError_t launch_mgs_coef(int j, const double* dots, const double* nrow, const double* gram2,
                            double* nu, double2* G, int gdim, double2* hcol, double2* coef,
-                           hipStream_t s, const int* skip) {
+                           hipStream_t s, const int* skip, double2* hmirror) {
   if (j < 0 || j >= kCoefMax || j >= gdim) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mgs_coef_kernel, dim3(1), dim3(64), 0, s, j, dots, nrow, gram2, nu, G, gdim,
-                     hcol, coef, skip);
+                     hcol, coef, skip, hmirror);
   return hipGetLastError();
 }
 
 hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* out, hipStream_t s) {
   hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, n, partials);
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out,
-                     static_cast<const int*>(nullptr));
+                     static_cast<const int*>(nullptr), static_cast<double*>(nullptr));
   return hipGetLastError();
 }
 
@@ -429,13 +436,13 @@ hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, doubl
                              hipStream_t s) {
   hipLaunchKernelGGL(diff_norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, b, n, partials);
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, kRedBlocks, out,
-                     static_cast<const int*>(nullptr));
+                     static_cast<const int*>(nullptr), static_cast<double*>(nullptr));
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_sum(const double* partials, int nparts, double* out, hipStream_t s) {
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, out,
-                     static_cast<const int*>(nullptr));
+                     static_cast<const int*>(nullptr), static_cast<double*>(nullptr));
   return hipGetLastError();
 }
 
@@ -486,12 +493,14 @@ hipError_t launch_block_dots(const double2* Q, int m, const double2* w, size_t n
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(2 * m), dim3(kThreads), 0, s, partials, nb, out, skip);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(2 * m), dim3(kThreads), 0, s, partials, nb, out, skip,
+                     static_cast<double*>(nullptr));
   return hipGetLastError();
 }
 
 hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, int m, size_t n,
-                              double* partials, double* out, hipStream_t s, const int* skip) {
+                              double* partials, double* out, hipStream_t s, const int* skip,
+                              double* hnorm) {
   const int nb = reduction_blocks(n);
   const int mg = m < kGramChunk ? m : kGramChunk;
   if (mg < 1) return hipErrorInvalidValue;
@@ -504,7 +513,8 @@ hipError_t launch_update_gram(double2* w, const double2* Q, const double2* c, in
 #undef H6_UPD
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out, skip);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1 + 2 * mg), dim3(kThreads), 0, s, partials, nb, out, skip,
+                     hnorm);
   return hipGetLastError();
 }
 

@@ -43,6 +43,10 @@ constexpr int kJudge = 4600;    // 2 doubles: |q - A z|^2 without / with the lea
 constexpr int kCycEst = 5000;   // whole-cycle graphs: m doubles of per-step residual estimates (host)
 constexpr int kCycInt = 5300;   // steps done (an int in one double slot, host)
 constexpr int kPrm = 5400;      // (steps allowed, ||F||, tol) for the device Givens steps
+// host-mapped step mirror (P->h_step): the Hessenberg column (2 (m + 1) doubles
+// from 0) and |w~|^2 (at kStepNorm), written by the step's own kernels
+constexpr int kStepNorm = 2 * 258;
+constexpr int kStepMirror = kStepNorm + 8;
 
 struct Ctx {
   h6_plan P;
@@ -81,6 +85,11 @@ h6_status ensure(h6_plan P, int method, int m) {
     }
   }
   if (e == hipSuccess && method == H6_FGMRES) e = grow(&P->Z, &P->Z_cols, m, zb);
+  if (e == hipSuccess && (method == H6_GMRES || method == H6_FGMRES) && !P->h_step) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&P->h_step), sizeof(double) * kStepMirror,
+                      hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&P->d_step), P->h_step, 0);
+  }
   if (e == hipSuccess && method == H6_SKS && P->parts_cap < stencil_workgroups(P)) {
     if (P->h_parts) (void)hipHostFree(P->h_parts);
     P->h_parts = P->d_parts = nullptr;
@@ -337,8 +346,9 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
         return launch_stencil(P, static_cast<const double2*>(z), out, nullptr, nullptr, nullptr, c.s);
       };
       // the device part of the step after z_j = A_p^{-1} q_j and w = A z_j:
-      // inner products, MGS coefficients, update with the Gram row, and the
-      // copies of h and |w~|^2 to the pinned mirror
+      // inner products, MGS coefficients, update with the Gram row; the
+      // coefficient and update kernels also write h and |w~|^2 into the
+      // host-mapped step mirror (no copies)
       auto orthogonalise = [&]() -> hipError_t {
         hipError_t e;
         hipEvent_t ev;
@@ -352,17 +362,15 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
         timing_end(P, KC_MGS_DOTS, c.s, ev,
                    double(N) * sizeof(double2) * ((j + 2) + (j > kGramMax ? j - kGramMax + 1 : 0)));
         if ((e = launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu, P->d_gram,
-                                 P->gram_dim, dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s)) !=
-            hipSuccess)
+                                 P->gram_dim, dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s, nullptr,
+                                 reinterpret_cast<double2*>(P->d_step))) != hipSuccess)
           return e;
         timing_begin(P, KC_MGS_UPDATE, c.s, &ev);
-        if ((e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s)) != hipSuccess)
+        if ((e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s, nullptr,
+                                    P->d_step + kStepNorm)) != hipSuccess)
           return e;
         timing_end(P, KC_MGS_UPDATE, c.s, ev, double(N) * sizeof(double2) * (j + 3));
-        if ((e = hipMemcpyAsync(c.host + kHcol, c.dev + kHcol, sizeof(double) * 2 * (j + 1),
-                                hipMemcpyDeviceToHost, c.s)) != hipSuccess)
-          return e;
-        return hipMemcpyAsync(c.host + kNorm, c.dev + kNorm, sizeof(double), hipMemcpyDeviceToHost, c.s);
+        return hipSuccess;
       };
       if (graphs) {
         // the whole step is one captured graph per step index, replayed
@@ -414,8 +422,8 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
       }
       st = wait(c);
       if (st != H6_OK) return st;
-      nu[j + 1] = std::sqrt(std::max(c.host[kNorm], 0.0));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = cplx(c.host[kHcol + 2 * i], c.host[kHcol + 2 * i + 1]);
+      nu[j + 1] = std::sqrt(std::max(P->h_step[kStepNorm], 0.0));
+      for (int i = 0; i <= j; ++i) Hij(i, j) = cplx(P->h_step[2 * i], P->h_step[2 * i + 1]);
       const double hn = nu[j + 1] / nu[j];
       // previous rotations on column j
       for (int i = 0; i < j; ++i) {
