@@ -68,6 +68,30 @@ def test_graph_restart_cycles(h6):
     assert i1["iters"] == i0["iters"] and torch.equal(U1, U0)
 
 
+def test_sks_after_stencil_depth_change(h6, tmp_path):
+    """SKS keeps one residual partial per stencil workgroup in host memory;
+    a later change of the stencil's z depth (more workgroups) must grow that
+    array before the next solve: same iterates for z depths 32, 8, 16."""
+    w = WORKLOADS["dns-128"]
+    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
+    F = plan.rhs_gaussians(*gaussian_sources(w))
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    nx, ny, nz = plan.dims
+    ref = None
+    for tz in (32, 8, 16):
+        path = os.path.join(tmp_path, f"tune_tz{tz}.txt")
+        with open(path, "w") as f:
+            f.write(f"h6tune2 {arch} {nx} {ny} {nz} 1 tz={tz} xfast=0 yfast=0 xlines=4 ylines=16\n")
+        plan.autotune(path)
+        U, info = plan.solve(F, method="sks", tol=w.tol, maxit=200)
+        assert info["status"] == "ok", (tz, info)
+        if ref is None:
+            ref = (U.clone(), info["iters"])
+        else:
+            assert info["iters"] == ref[1], tz
+            assert float(torch.linalg.norm(U - ref[0]) / torch.linalg.norm(ref[0])) < 1e-12, tz
+
+
 def test_autotune_keeps_results_and_caches(h6, tmp_path):
     w = WORKLOADS["dns-256"]
     plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
