@@ -142,6 +142,183 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(View in, const bf
     }
 }
 
+// The same convolution with the input tile staged in LDS (for CIN <= 48): a
+// workgroup owns a 16 x 4 x 4 block of output voxels (wave w: z offset w,
+// row tile m: y offset m, 16 voxels along x) and first copies the block's
+// input with its one-voxel halo, 18 x 6 x 6 voxels of CIN channels, into LDS
+// (zero outside the grid); every A fragment of the 27 taps is then an LDS
+// read instead of a global one (each input voxel is read from L2 about 2.5
+// times instead of 27).  Weights are staged per tap as in conv_kernel.
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+
+template <int CIN, int COUTP>
+__global__ __launch_bounds__(256) void conv_tile_kernel(View in, const bf16* __restrict__ W,
+                                                        const float* __restrict__ bias, View out,
+                                                        float* __restrict__ out32, int cout, int relu,
+                                                        Grid3 g, int ntx, int nty) {
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
+  constexpr int RS = CIN + 4;
+  constexpr int WN = COUTP * CIN;
+  constexpr int HV = kHX * kHY * kHZ;                 // halo voxels
+  __shared__ __attribute__((aligned(16))) bf16 xs[KC][HV][16];
+  __shared__ __attribute__((aligned(16))) bf16 ws[2][COUTP * RS];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
+  const int i = l & 15, kq = l >> 4;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+  // input block with halo: 8-byte pieces, channel-chunk fastest within a voxel
+  for (int idx = tid; idx < HV * KC * 4; idx += 256) {
+    const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
+    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+    s4 val = s4{0, 0, 0, 0};
+    if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
+      const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
+      val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
+    }
+    *reinterpret_cast<s4*>(&xs[kc][hv][4 * q]) = val;
+  }
+  auto stage = [&](int tap, int b) {
+    for (int idx = tid; idx < WN / 4; idx += 256) {
+      const int row = (4 * idx) / CIN, col = (4 * idx) % CIN;
+      *reinterpret_cast<s4*>(&ws[b][row * RS + col]) =
+          *reinterpret_cast<const s4*>(W + (size_t)tap * WN + 4 * idx);
+    }
+  };
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+  stage(0, 0);
+  __syncthreads();
+  for (int tap = 0; tap < 27; ++tap) {
+    const int b = tap & 1;
+    if (tap + 1 < 27) stage(tap + 1, b ^ 1);
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      s4 a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
+        a[m] = *reinterpret_cast<const s4*>(&xs[kc][hv][4 * kq]);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const s4 bf = *reinterpret_cast<const s4*>(&ws[b][(t * 16 + i) * RS + 16 * kc + 4 * kq]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int oz = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int oy = y0 + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ox = x0 + 4 * kq + e;
+        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
+        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
+        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (out32)
+          out32[vo * 2 + co] = val;
+        else
+          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      }
+    }
+  }
+}
+
+// conv_tile_kernel with the channel chunks outermost (for wide inputs and
+// narrow outputs, CIN = 48, COUTP = 16): one 16-channel chunk of the input
+// block and that chunk's weights for all 27 taps are in LDS at a time
+// (38 KB instead of 65 KB), so twice as many workgroups fit on a CU.
+template <int CIN, int COUTP>
+__global__ __launch_bounds__(256) void conv_tile_co_kernel(View in, const bf16* __restrict__ W,
+                                                           const float* __restrict__ bias, View out,
+                                                           float* __restrict__ out32, int cout, int relu,
+                                                           Grid3 g, int ntx, int nty) {
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
+  constexpr int RS = 16 + 4;                          // LDS row stride (bf16) of a weight chunk
+  constexpr int HV = kHX * kHY * kHZ;
+  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
+  __shared__ __attribute__((aligned(16))) bf16 wk[27][COUTP * RS];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
+  const int i = l & 15, kq = l >> 4;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < KC; ++kc) {
+    for (int idx = tid; idx < HV * 4; idx += 256) {
+      const int q = idx & 3, hv = idx >> 2;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      s4 val = s4{0, 0, 0, 0};
+      if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
+        const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
+        val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
+      }
+      *reinterpret_cast<s4*>(&xs[hv][4 * q]) = val;
+    }
+    // weights W[tap][co][ci], ci in this chunk: 4 bf16 per piece
+    for (int idx = tid; idx < 27 * COUTP * 4; idx += 256) {
+      const int q = idx & 3, co = (idx >> 2) % COUTP, tap = (idx >> 2) / COUTP;
+      *reinterpret_cast<s4*>(&wk[tap][co * RS + 4 * q]) =
+          *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
+    }
+    __syncthreads();
+    for (int tap = 0; tap < 27; ++tap) {
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      s4 a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
+        a[m] = *reinterpret_cast<const s4*>(&xs[hv][4 * kq]);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const s4 bf = *reinterpret_cast<const s4*>(&wk[tap][(t * 16 + i) * RS + 4 * kq]);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int oz = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int oy = y0 + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ox = x0 + 4 * kq + e;
+        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
+        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
+        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (out32)
+          out32[vo * 2 + co] = val;
+        else
+          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      }
+    }
+  }
+}
+
 constexpr int kWgTile = 64;      // voxels per weight-gradient tile
 constexpr int kWgStride = 68;    // LDS row stride (bf16) of the transposed tiles
 
@@ -490,11 +667,30 @@ hipError_t dalloc(h6_net N, T** p, size_t count) {
 
 unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+#define H6_CONV_TILE_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(16, 48) X(32, 96) X(32, 16)
+
 #define H6_CONV_CASES(X) \
   X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(16, 48) X(32, 96) X(64, 32) X(32, 16)
 
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s) {
+  if (cinp <= 48) {
+    const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
+    const unsigned tgrid = unsigned(ntx) * nty * ntz;
+#define H6_CONVT(CI, CO)                                                                             \
+  if (cinp == CI && coutp == CO) {                                                                   \
+    hipLaunchKernelGGL((conv_tile_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
+                       out32, cout, relu, g, ntx, nty);                                              \
+    return hipGetLastError();                                                                        \
+  }
+    if (cinp == 48 && coutp == 16) {
+      hipLaunchKernelGGL((conv_tile_co_kernel<48, 16>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,
+                         out32, cout, relu, g, ntx, nty);
+      return hipGetLastError();
+    }
+    H6_CONV_TILE_CASES(H6_CONVT)
+#undef H6_CONVT
+  }
   const unsigned grid = unsigned((g.P() + 16 * kConvMT * kConvWaves - 1) / (16 * kConvMT * kConvWaves));
 #define H6_CONV(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                  \
