@@ -167,17 +167,30 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(View in, const bf16* __r
   const int i = l & 15, kq = l >> 4;
   const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
   const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  // input block with halo: 8-byte pieces, channel-chunk fastest within a voxel
-  for (int idx = tid; idx < HV * KC * 4; idx += 256) {
-    const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
-    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-    s4 val = s4{0, 0, 0, 0};
-    if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
-      const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
-      val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
+  // input block with halo: 8-byte pieces, channel-chunk fastest within a
+  // voxel; every global load is issued before the first LDS store
+  {
+    constexpr int NPIECE = HV * KC * 4, NPER = (NPIECE + 255) / 256;
+    s4 val[NPER];
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int idx = tid + 256 * k;
+      const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
+      const long long v = inside ? gx + (long long)g.X * (gy + (long long)g.Y * gz) : 0;
+      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 16 * kc + 4 * q : 0));
+      if (!inside) val[k] = s4{0, 0, 0, 0};
     }
-    *reinterpret_cast<s4*>(&xs[kc][hv][4 * q]) = val;
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < NPIECE) {
+        const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
+        *reinterpret_cast<s4*>(&xs[kc][hv][4 * q]) = val[k];
+      }
+    }
   }
   auto stage = [&](int tap, int b) {
     for (int idx = tid; idx < WN / 4; idx += 256) {
@@ -667,6 +680,10 @@ hipError_t dalloc(h6_net N, T** p, size_t count) {
 
 unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// layers on the LDS-tiled kernels (the chunk-outer form where one input chunk
+// and all 27 taps of its weights fit beside each other); the rest read their
+// activations through L1 (conv_kernel)
+#define H6_CONV_CO_CASES(X) X(48, 16) X(96, 32) X(64, 32)
 #define H6_CONV_TILE_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(16, 48) X(32, 96) X(32, 16)
 
 #define H6_CONV_CASES(X) \
@@ -674,23 +691,25 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s) {
-  if (cinp <= 48) {
-    const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
-    const unsigned tgrid = unsigned(ntx) * nty * ntz;
+  // LDS-tiled kernels: 16 x 4 x 4 output blocks
+  const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
+  const unsigned tgrid = unsigned(ntx) * nty * ntz;
+#define H6_CONVCO(CI, CO)                                                                            \
+  if (cinp == CI && coutp == CO) {                                                                   \
+    hipLaunchKernelGGL((conv_tile_co_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out, \
+                       out32, cout, relu, g, ntx, nty);                                              \
+    return hipGetLastError();                                                                        \
+  }
+  H6_CONV_CO_CASES(H6_CONVCO)
+#undef H6_CONVCO
 #define H6_CONVT(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                   \
     hipLaunchKernelGGL((conv_tile_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
                        out32, cout, relu, g, ntx, nty);                                              \
     return hipGetLastError();                                                                        \
   }
-    if (cinp == 48 && coutp == 16) {
-      hipLaunchKernelGGL((conv_tile_co_kernel<48, 16>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,
-                         out32, cout, relu, g, ntx, nty);
-      return hipGetLastError();
-    }
-    H6_CONV_TILE_CASES(H6_CONVT)
+  H6_CONV_TILE_CASES(H6_CONVT)
 #undef H6_CONVT
-  }
   const unsigned grid = unsigned((g.P() + 16 * kConvMT * kConvWaves - 1) / (16 * kConvMT * kConvWaves));
 #define H6_CONV(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                  \
