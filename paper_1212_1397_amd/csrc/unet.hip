@@ -457,24 +457,6 @@ __global__ void features_kernel(const double2* __restrict__ r, const double* __r
   d[2] = f2bf(ms > 0.0 ? kh : 0.f);
 }
 
-// 2x2x2 average pool (extent ceil(n/2), divisor 8) of C channels
-__global__ void pool_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
-  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= go.P() * C) return;
-  const int c = int(idx % C);
-  const long long vo = idx / C;
-  const int x = int(vo % go.X), y = int((vo / go.X) % go.Y), z = int(vo / ((long long)go.X * go.Y));
-  float s = 0.f;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int d = 0; d < 2; ++d) {
-        const int xi = 2 * x + d, yi = 2 * y + b, zi = 2 * z + a;
-        if (xi < gi.X && yi < gi.Y && zi < gi.Z)
-          s += bf2f(in.p[(xi + (long long)gi.X * (yi + (long long)gi.Y * zi)) * in.cs + in.coff + c]);
-      }
-  out.p[vo * out.cs + out.coff + c] = f2bf(s * 0.125f);
-}
-
 // gradient of the pool, added to din: din[v] += dout[v / 2] / 8
 __global__ void pool_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -487,15 +469,50 @@ __global__ void pool_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C)
   *d = f2bf(bf2f(*d) + 0.125f * bf2f(dout.p[vo * dout.cs + dout.coff + c]));
 }
 
-// nearest-neighbour upsampling: out[v] = in[v / 2]
-__global__ void up_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
+// forward 2x2x2 average pool (extent ceil(n/2), divisor 8) and nearest-
+// neighbour upsampling (out[v] = in[v / 2]), 8 channels (16 bytes) per
+// thread: the views' channel offsets and strides are multiples of 16
+// channels, so every access is a 16-byte aligned load or store
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__global__ void pool8_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= go.P() * C) return;
-  const int c = int(idx % C);
-  const long long v = idx / C;
+  const int C8 = C / 8;
+  if (idx >= go.P() * C8) return;
+  const int c = 8 * int(idx % C8);
+  const long long vo = idx / C8;
+  const int x = int(vo % go.X), y = int((vo / go.X) % go.Y), z = int(vo / ((long long)go.X * go.Y));
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int d = 0; d < 2; ++d) {
+        const int xi = 2 * x + d, yi = 2 * y + b, zi = 2 * z + a;
+        if (xi < gi.X && yi < gi.Y && zi < gi.Z) {
+          const u4v w = *reinterpret_cast<const u4v*>(
+              in.p + (xi + (long long)gi.X * (yi + (long long)gi.Y * zi)) * in.cs + in.coff + c);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            s[2 * k] += bf2f(bf16(w[k] & 0xffffu));
+            s[2 * k + 1] += bf2f(bf16(w[k] >> 16));
+          }
+        }
+      }
+  u4v o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = unsigned(f2bf(s[2 * k] * 0.125f)) | (unsigned(f2bf(s[2 * k + 1] * 0.125f)) << 16);
+  *reinterpret_cast<u4v*>(out.p + vo * out.cs + out.coff + c) = o;
+}
+
+__global__ void up8_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int C8 = C / 8;
+  if (idx >= go.P() * C8) return;
+  const int c = 8 * int(idx % C8);
+  const long long v = idx / C8;
   const int x = int(v % go.X), y = int((v / go.X) % go.Y), z = int(v / ((long long)go.X * go.Y));
   const long long vi = (x / 2) + (long long)gi.X * ((y / 2) + (long long)gi.Y * (z / 2));
-  out.p[v * out.cs + out.coff + c] = in.p[vi * in.cs + in.coff + c];
+  *reinterpret_cast<u4v*>(out.p + v * out.cs + out.coff + c) =
+      *reinterpret_cast<const u4v*>(in.p + vi * in.cs + in.coff + c);
 }
 
 // gradient of the upsampling: din[v] = sum of dout over the children of v
@@ -755,19 +772,19 @@ hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s) {
 #define TRY(x) if ((e = (x)) != hipSuccess) return e
   TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s));
   TRY(layer_fwd(N, E1B, vw(N->T1, 16), vw(N->C1, 48, 32), nullptr, g1, s));
-  hipLaunchKernelGGL(pool_kernel, dim3(nblk(g2.P() * 16)), dim3(256), 0, s, vw(N->C1, 48, 32), g1,
+  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g2.P() * 2)), dim3(256), 0, s, vw(N->C1, 48, 32), g1,
                      vw(N->Pl1, 16), g2, 16);
   TRY(layer_fwd(N, E2A, vw(N->Pl1, 16), vw(N->T2, 32), nullptr, g2, s));
   TRY(layer_fwd(N, E2B, vw(N->T2, 32), vw(N->C2, 96, 64), nullptr, g2, s));
-  hipLaunchKernelGGL(pool_kernel, dim3(nblk(g3.P() * 32)), dim3(256), 0, s, vw(N->C2, 96, 64), g2,
+  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g3.P() * 4)), dim3(256), 0, s, vw(N->C2, 96, 64), g2,
                      vw(N->Pl2, 32), g3, 32);
   TRY(layer_fwd(N, B3A, vw(N->Pl2, 32), vw(N->T3, 64), nullptr, g3, s));
   TRY(layer_fwd(N, B3B, vw(N->T3, 64), vw(N->B3, 64), nullptr, g3, s));
-  hipLaunchKernelGGL(up_kernel, dim3(nblk(g2.P() * 64)), dim3(256), 0, s, vw(N->B3, 64), g3,
+  hipLaunchKernelGGL(up8_kernel, dim3(nblk(g2.P() * 8)), dim3(256), 0, s, vw(N->B3, 64), g3,
                      vw(N->C2, 96, 0), g2, 64);
   TRY(layer_fwd(N, D2A, vw(N->C2, 96), vw(N->T2b, 32), nullptr, g2, s));
   TRY(layer_fwd(N, D2B, vw(N->T2b, 32), vw(N->D2, 32), nullptr, g2, s));
-  hipLaunchKernelGGL(up_kernel, dim3(nblk(g1.P() * 32)), dim3(256), 0, s, vw(N->D2, 32), g2,
+  hipLaunchKernelGGL(up8_kernel, dim3(nblk(g1.P() * 4)), dim3(256), 0, s, vw(N->D2, 32), g2,
                      vw(N->C1, 48, 0), g1, 32);
   TRY(layer_fwd(N, D1A, vw(N->C1, 48), vw(N->T1b, 16), nullptr, g1, s));
   TRY(layer_fwd(N, D1B, vw(N->T1b, 16), vw(N->D1, 16), nullptr, g1, s));
