@@ -332,6 +332,98 @@ __global__ __launch_bounds__(256) void conv_tile_co_kernel(View in, const bf16* 
   }
 }
 
+// conv_tile_co_kernel on v_mfma_f32_16x16x32_bf16 (K = 32 per instruction):
+// the K dimension pairs two taps of one 16-channel chunk, lanes 0-31 taking
+// the first tap's channels and lanes 32-63 the second's (A[l%16][8(l/16)+e],
+// B[8(l/16)+e][l%16]; 16-byte LDS reads), so the 27 taps of a chunk take 14
+// instructions per row tile (the last pairs tap 26 with zeros).
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4w __attribute__((ext_vector_type(4)));
+
+template <int CIN, int COUTP>
+__global__ __launch_bounds__(256) void conv_x32_kernel(View in, const bf16* __restrict__ W,
+                                                       const float* __restrict__ bias, View out,
+                                                       float* __restrict__ out32, int cout, int relu,
+                                                       Grid3 g, int ntx, int nty) {
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
+  constexpr int RS = 16 + 8;                          // weight row stride (bf16): 16-byte aligned rows
+  constexpr int HV = kHX * kHY * kHZ;
+  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
+  __shared__ __attribute__((aligned(16))) bf16 wk[27][COUTP * RS];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
+  const int i = l & 15, half = (l >> 4) & 1, second = l >> 5;   // channel half, tap of the pair
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int kc = 0; kc < KC; ++kc) {
+    for (int idx = tid; idx < HV * 4; idx += 256) {
+      const int q = idx & 3, hv = idx >> 2;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      s4 val = s4{0, 0, 0, 0};
+      if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
+        const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
+        val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
+      }
+      *reinterpret_cast<s4*>(&xs[hv][4 * q]) = val;
+    }
+    for (int idx = tid; idx < 27 * COUTP * 4; idx += 256) {
+      const int q = idx & 3, co = (idx >> 2) % COUTP, tap = (idx >> 2) / COUTP;
+      *reinterpret_cast<s4*>(&wk[tap][co * RS + 4 * q]) =
+          *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
+    }
+    __syncthreads();
+    for (int tp = 0; tp < 27; tp += 2) {
+      const int tap = tp + second;                       // this lane's tap of the pair
+      const bool real = tap < 27;
+      const int tc = real ? tap : 26;
+      const int dz = tc / 9 - 1, dy = (tc / 3) % 3 - 1, dx = tc % 3 - 1;
+      bf8v a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
+        u4w w = *reinterpret_cast<const u4w*>(&xs[hv][8 * half]);
+        if (!real) w = u4w{0u, 0u, 0u, 0u};
+        a[m] = __builtin_bit_cast(bf8v, w);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        u4w wb = *reinterpret_cast<const u4w*>(&wk[tc][(t * 16 + i) * RS + 8 * half]);
+        if (!real) wb = u4w{0u, 0u, 0u, 0u};
+        const bf8v bfr = __builtin_bit_cast(bf8v, wb);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bfr, acc[m][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int oz = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int oy = y0 + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ox = x0 + 4 * (l >> 4) + e;
+        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
+        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
+        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (out32)
+          out32[vo * 2 + co] = val;
+        else
+          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      }
+    }
+  }
+}
+
 constexpr int kWgTile = 64;      // voxels per weight-gradient tile
 constexpr int kWgStride = 68;    // LDS row stride (bf16) of the transposed tiles
 
@@ -697,10 +789,14 @@ hipError_t dalloc(h6_net N, T** p, size_t count) {
 
 unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
-// layers on the LDS-tiled kernels (the chunk-outer form where one input chunk
-// and all 27 taps of its weights fit beside each other); the rest read their
-// activations through L1 (conv_kernel)
-#define H6_CONV_CO_CASES(X) X(48, 16) X(96, 32) X(64, 32)
+// layers on the LDS-tiled kernels: the chunk-outer form (one input chunk and
+// all 27 taps of its weights in LDS) on the K = 32 matrix instruction for
+// 48 -> 16 (2.51 ms against 3.14 ms with K = 16; for 16 -> 16 the per-tap form
+// with more workgroups per CU is faster: 0.93 ms against 1.19 ms), on K = 16
+// for 96 -> 32 and 64 -> 32; the per-tap form for the other narrow layers; the
+// rest read their activations through L1 (conv_kernel)
+#define H6_CONV_X32_CASES(X) X(48, 16)
+#define H6_CONV_CO_CASES(X) X(96, 32) X(64, 32)
 #define H6_CONV_TILE_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(16, 48) X(32, 96) X(32, 16)
 
 #define H6_CONV_CASES(X) \
@@ -719,6 +815,14 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
   }
   H6_CONV_CO_CASES(H6_CONVCO)
 #undef H6_CONVCO
+#define H6_CONVX(CI, CO)                                                                             \
+  if (cinp == CI && coutp == CO) {                                                                   \
+    hipLaunchKernelGGL((conv_x32_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,    \
+                       out32, cout, relu, g, ntx, nty);                                              \
+    return hipGetLastError();                                                                        \
+  }
+  H6_CONV_X32_CASES(H6_CONVX)
+#undef H6_CONVX
 #define H6_CONVT(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                   \
     hipLaunchKernelGGL((conv_tile_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
