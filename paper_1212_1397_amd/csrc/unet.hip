@@ -424,6 +424,101 @@ __global__ __launch_bounds__(256) void conv_x32_kernel(View in, const bf16* __re
   }
 }
 
+// conv_tile_kernel for 16 input channels on the K = 32 instruction: two taps
+// per instruction (lanes 0-31 the first tap's channels, 32-63 the second's),
+// the weights of a tap pair double-buffered in LDS.
+template <int COUTP>
+__global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16* __restrict__ W,
+                                                            const float* __restrict__ bias, View out,
+                                                            float* __restrict__ out32, int cout, int relu,
+                                                            Grid3 g, int ntx, int nty) {
+  constexpr int NT = COUTP / 16, MT = 4;
+  constexpr int RS = 16 + 8;                          // weight row stride (bf16): 16-byte aligned rows
+  constexpr int HV = kHX * kHY * kHZ;
+  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
+  __shared__ __attribute__((aligned(16))) bf16 ws[2][2][COUTP * RS];
+  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
+  const int i = l & 15, half = (l >> 4) & 1, second = l >> 5;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+  {
+    constexpr int NPIECE = HV * 4, NPER = (NPIECE + 255) / 256;
+    s4 val[NPER];
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int idx = tid + 256 * k;
+      const int q = idx & 3, hv = idx >> 2;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
+      const long long v = inside ? gx + (long long)g.X * (gy + (long long)g.Y * gz) : 0;
+      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 4 * q : 0));
+      if (!inside) val[k] = s4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int idx = tid + 256 * k;
+      if (idx < NPIECE) *reinterpret_cast<s4*>(&xs[idx >> 2][4 * (idx & 3)]) = val[k];
+    }
+  }
+  // weights of taps tp, tp + 1 (zero past tap 26): W[tap][co][ci], 16 channels
+  auto stage = [&](int tp, int b) {
+    for (int idx = tid; idx < 2 * COUTP * 4; idx += 256) {
+      const int q = idx & 3, co = (idx >> 2) % COUTP, u = (idx >> 2) / COUTP, tap = tp + u;
+      s4 val = s4{0, 0, 0, 0};
+      if (tap < 27) val = *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * 16 + 4 * q);
+      *reinterpret_cast<s4*>(&ws[b][u][co * RS + 4 * q]) = val;
+    }
+  };
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+  stage(0, 0);
+  __syncthreads();
+  for (int tp = 0; tp < 27; tp += 2) {
+    const int b = (tp >> 1) & 1;
+    if (tp + 2 < 27) stage(tp + 2, b ^ 1);
+    const int tc = tp + second < 27 ? tp + second : 26;     // tap 27 reads tap 26's input, zero weights
+    const int dz = tc / 9 - 1, dy = (tc / 3) % 3 - 1, dx = tc % 3 - 1;
+    bf8v a[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
+      a[m] = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w*>(&xs[hv][8 * half]));
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf8v bfr = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w*>(&ws[b][second][(t * 16 + i) * RS + 8 * half]));
+#pragma unroll
+      for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bfr, acc[m][t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int oz = z0 + wave;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int oy = y0 + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ox = x0 + 4 * (l >> 4) + e;
+        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
+        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
+        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
+        if (relu) val = fmaxf(val, 0.f);
+        if (out32)
+          out32[vo * 2 + co] = val;
+        else
+          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      }
+    }
+  }
+}
+
 constexpr int kWgTile = 64;      // voxels per weight-gradient tile
 constexpr int kWgStride = 68;    // LDS row stride (bf16) of the transposed tiles
 
@@ -791,11 +886,12 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 // layers on the LDS-tiled kernels: the chunk-outer form (one input chunk and
 // all 27 taps of its weights in LDS) on the K = 32 matrix instruction for
-// 48 -> 16 (2.51 ms against 3.14 ms with K = 16; for 16 -> 16 the per-tap form
-// with more workgroups per CU is faster: 0.93 ms against 1.19 ms), on K = 16
-// for 96 -> 32 and 64 -> 32; the per-tap form for the other narrow layers; the
-// rest read their activations through L1 (conv_kernel)
+// 48 -> 16 and on K = 16 for 96 -> 32 and 64 -> 32; the per-tap-pair K = 32
+// form for 16 input channels (more workgroups per CU than the chunk-outer
+// one); the per-tap K = 16 form for the other narrow layers; the rest read
+// their activations through L1 (conv_kernel)
 #define H6_CONV_X32_CASES(X) X(48, 16)
+#define H6_CONV_TILE_X32_CASES(X) X(16, 16) X(16, 32) X(16, 48)
 #define H6_CONV_CO_CASES(X) X(96, 32) X(64, 32)
 #define H6_CONV_TILE_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(16, 48) X(32, 96) X(32, 16)
 
@@ -823,6 +919,14 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
   }
   H6_CONV_X32_CASES(H6_CONVX)
 #undef H6_CONVX
+#define H6_CONVTX(CI, CO)                                                                            \
+  if (cinp == CI && coutp == CO) {                                                                   \
+    hipLaunchKernelGGL((conv_tile_x32_kernel<CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
+                       out32, cout, relu, g, ntx, nty);                                              \
+    return hipGetLastError();                                                                        \
+  }
+  H6_CONV_TILE_X32_CASES(H6_CONVTX)
+#undef H6_CONVTX
 #define H6_CONVT(CI, CO)                                                                             \
   if (cinp == CI && coutp == CO) {                                                                   \
     hipLaunchKernelGGL((conv_tile_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
