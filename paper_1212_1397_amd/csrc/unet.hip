@@ -893,7 +893,7 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 #define H6_CONV_X32_CASES(X) X(48, 16)
 #define H6_CONV_TILE_X32_CASES(X) X(16, 16) X(16, 32) X(16, 48)
 #define H6_CONV_CO_CASES(X) X(96, 32) X(64, 32)
-#define H6_CONV_TILE_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(16, 48) X(32, 96) X(32, 16)
+#define H6_CONV_TILE_CASES(X) X(32, 32) X(32, 64) X(32, 96) X(32, 16)
 
 #define H6_CONV_CASES(X) \
   X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(16, 48) X(32, 96) X(64, 32) X(32, 16)
