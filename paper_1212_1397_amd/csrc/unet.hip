@@ -1,14 +1,18 @@
 // Learned correction network (see include/h6net.h for the definition):
 // BF16 activations and weights, FP32 accumulation on the matrix cores.
 //
-// Convolutions are implicit GEMMs with v_mfma_f32_16x16x16bf16_1k:
-//   forward / input gradient: rows = voxels (flattened x-fastest index; a wave
-//     owns four 16-voxel tiles), columns = output channels, k = (tap, input
-//     channel), the tap's weights staged in LDS;
-//   weight gradient: rows = output channels, columns = input channels,
-//     k = voxels, one tap per workgroup, deterministic two-stage reduction.
-// Operand lane layout of the instruction (lane l, element e = 0..3):
-//   A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16], D[4 (l / 16) + e][l % 16].
+// Convolutions are implicit GEMMs on the matrix cores:
+//   forward / input gradient (v_mfma_f32_16x16x32_bf16): rows = voxels (a
+//     wave owns four 16-voxel rows of a 16 x 4 x 4 block), columns = output
+//     channels, k = two taps x 16 channels of one input chunk, the input
+//     block and a tap pair's weights staged in LDS;
+//   weight gradient (v_mfma_f32_16x16x16bf16_1k): rows = output channels,
+//     columns = input channels, k = voxels, one tap per workgroup,
+//     deterministic two-stage reduction.
+// Operand lane layouts (lane l; K = 16: e = 0..3, K = 32: e = 0..7):
+//   K = 16: A[l % 16][4 (l / 16) + e], B[4 (l / 16) + e][l % 16];
+//   K = 32: A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16];
+//   both:   D[4 (l / 16) + e][l % 16] (e = 0..3).
 // Activations are channels-last: element (v, c) of a view at p[v * cs + coff + c],
 // so the skip concatenations are two producers writing channel ranges of one
 // buffer.  The input-gradient convolution is the forward kernel with the
@@ -46,393 +50,32 @@ struct View {           // channels-last BF16 view
   int cs, coff;
 };
 
-constexpr int kConvWaves = 4;
-constexpr int kConvMT = 4;       // 16-voxel row tiles per wave: a workgroup owns 256 voxels
-
-// out[v][co] = act(b[co] + sum_{tap, ci} W[tap][co][ci] in[v + tap][ci]), CIN and
-// COUTP multiples of 16; writes co < cout (BF16 view, or FP32 [v][2] when out32).
-// The weights of one tap (COUTP x CIN) are staged in LDS, double-buffered over
-// the taps, and every B fragment read from LDS feeds kConvMT matrix
-// instructions (one per row tile of the wave); A fragments come from global
-// memory (L1/L2: each input voxel is read by 27 taps).
-template <int CIN, int COUTP>
-__global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(View in, const bf16* __restrict__ W,
-                                                               const float* __restrict__ bias, View out,
-                                                               float* __restrict__ out32, int cout,
-                                                               int relu, Grid3 g) {
-  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = kConvMT;
-  constexpr int RS = CIN + 4;                        // LDS row stride (bf16): fewer bank conflicts
-  constexpr int WN = COUTP * CIN;                    // weights of one tap
-  __shared__ __attribute__((aligned(16))) bf16 ws[2][COUTP * RS];
-  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
-  const int i = l & 15, kq = l >> 4;
-  const long long P = g.P();
-  const long long v0 = ((long long)blockIdx.x * kConvWaves + wave) * (16 * MT);
-  int xs[MT], ys[MT], zs[MT];
-  bool vok[MT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const long long v = v0 + 16 * m + i;
-    vok[m] = v < P;
-    const long long vc = vok[m] ? v : 0;
-    xs[m] = int(vc % g.X);
-    ys[m] = int((vc / g.X) % g.Y);
-    zs[m] = int(vc / ((long long)g.X * g.Y));
-  }
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  auto stage = [&](int tap, int b) {
-    for (int idx = tid; idx < WN / 4; idx += 64 * kConvWaves) {
-      const int row = (4 * idx) / CIN, col = (4 * idx) % CIN;
-      *reinterpret_cast<s4*>(&ws[b][row * RS + col]) =
-          *reinterpret_cast<const s4*>(W + (size_t)tap * WN + 4 * idx);
-    }
-  };
-  stage(0, 0);
-  __syncthreads();
-  for (int tap = 0; tap < 27; ++tap) {
-    const int b = tap & 1;
-    if (tap + 1 < 27) stage(tap + 1, b ^ 1);
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    const bf16* src[MT];
-    bool ok[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      ok[m] = vok[m] && xs[m] + dx >= 0 && xs[m] + dx < g.X && ys[m] + dy >= 0 && ys[m] + dy < g.Y &&
-              zs[m] + dz >= 0 && zs[m] + dz < g.Z;
-      const long long nv = ok[m] ? v0 + 16 * m + i + dx + (long long)g.X * (dy + (long long)g.Y * dz) : 0;
-      src[m] = in.p + nv * in.cs + in.coff + 4 * kq;
-    }
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      s4 a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        a[m] = *reinterpret_cast<const s4*>(src[m] + 16 * kc);
-        if (!ok[m]) a[m] = s4{0, 0, 0, 0};
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const s4 bf = *reinterpret_cast<const s4*>(&ws[b][(t * 16 + i) * RS + 16 * kc + 4 * kq]);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + i;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const long long vo = v0 + 16 * m + 4 * kq + e;
-        if (vo >= P || co >= cout) continue;
-        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
-        if (relu) val = fmaxf(val, 0.f);
-        if (out32)
-          out32[vo * 2 + co] = val;
-        else
-          out.p[vo * out.cs + out.coff + co] = f2bf(val);
-      }
-    }
-}
-
-// The same convolution with the input tile staged in LDS (for CIN <= 48): a
-// workgroup owns a 16 x 4 x 4 block of output voxels (wave w: z offset w,
-// row tile m: y offset m, 16 voxels along x) and first copies the block's
-// input with its one-voxel halo, 18 x 6 x 6 voxels of CIN channels, into LDS
-// (zero outside the grid); every A fragment of the 27 taps is then an LDS
-// read instead of a global one (each input voxel is read from L2 about 2.5
-// times instead of 27).  Weights are staged per tap as in conv_kernel.
+// Convolution out[v][co] = act(b[co] + sum_{tap, ci} W[tap][co][ci] in[v + tap][ci])
+// (zero outside the grid), CIN and COUTP multiples of 16; writes co < cout (BF16
+// view, or FP32 [v][2] when out32).  A workgroup owns a 16 x 4 x 4 block of
+// output voxels (wave w: z offset w, row tile m: y offset m, 16 voxels along x)
+// and stages the block's input with its one-voxel halo, 18 x 6 x 6 voxels of
+// one 16-channel chunk, in LDS (each input voxel is read from L2 about 2.5
+// times instead of once per tap).
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 
-template <int CIN, int COUTP>
-__global__ __launch_bounds__(256) void conv_tile_kernel(View in, const bf16* __restrict__ W,
-                                                        const float* __restrict__ bias, View out,
-                                                        float* __restrict__ out32, int cout, int relu,
-                                                        Grid3 g, int ntx, int nty) {
-  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
-  constexpr int RS = CIN + 4;
-  constexpr int WN = COUTP * CIN;
-  constexpr int HV = kHX * kHY * kHZ;                 // halo voxels
-  __shared__ __attribute__((aligned(16))) bf16 xs[KC][HV][16];
-  __shared__ __attribute__((aligned(16))) bf16 ws[2][COUTP * RS];
-  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
-  const int i = l & 15, kq = l >> 4;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
-  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  // input block with halo: 8-byte pieces, channel-chunk fastest within a
-  // voxel; every global load is issued before the first LDS store
-  {
-    constexpr int NPIECE = HV * KC * 4, NPER = (NPIECE + 255) / 256;
-    s4 val[NPER];
-#pragma unroll
-    for (int k = 0; k < NPER; ++k) {
-      const int idx = tid + 256 * k;
-      const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
-      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
-      const long long v = inside ? gx + (long long)g.X * (gy + (long long)g.Y * gz) : 0;
-      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 16 * kc + 4 * q : 0));
-      if (!inside) val[k] = s4{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int k = 0; k < NPER; ++k) {
-      const int idx = tid + 256 * k;
-      if (idx < NPIECE) {
-        const int q = idx & 3, kc = (idx >> 2) % KC, hv = (idx >> 2) / KC;
-        *reinterpret_cast<s4*>(&xs[kc][hv][4 * q]) = val[k];
-      }
-    }
-  }
-  auto stage = [&](int tap, int b) {
-    for (int idx = tid; idx < WN / 4; idx += 256) {
-      const int row = (4 * idx) / CIN, col = (4 * idx) % CIN;
-      *reinterpret_cast<s4*>(&ws[b][row * RS + col]) =
-          *reinterpret_cast<const s4*>(W + (size_t)tap * WN + 4 * idx);
-    }
-  };
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  stage(0, 0);
-  __syncthreads();
-  for (int tap = 0; tap < 27; ++tap) {
-    const int b = tap & 1;
-    if (tap + 1 < 27) stage(tap + 1, b ^ 1);
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      s4 a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
-        a[m] = *reinterpret_cast<const s4*>(&xs[kc][hv][4 * kq]);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const s4 bf = *reinterpret_cast<const s4*>(&ws[b][(t * 16 + i) * RS + 16 * kc + 4 * kq]);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  const int oz = z0 + wave;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int oy = y0 + m;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + i;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ox = x0 + 4 * kq + e;
-        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
-        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
-        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
-        if (relu) val = fmaxf(val, 0.f);
-        if (out32)
-          out32[vo * 2 + co] = val;
-        else
-          out.p[vo * out.cs + out.coff + co] = f2bf(val);
-      }
-    }
-  }
-}
-
-// conv_tile_kernel with the channel chunks outermost (for wide inputs and
-// narrow outputs, CIN = 48, COUTP = 16): one 16-channel chunk of the input
-// block and that chunk's weights for all 27 taps are in LDS at a time
-// (38 KB instead of 65 KB), so twice as many workgroups fit on a CU.
-template <int CIN, int COUTP>
-__global__ __launch_bounds__(256) void conv_tile_co_kernel(View in, const bf16* __restrict__ W,
-                                                           const float* __restrict__ bias, View out,
-                                                           float* __restrict__ out32, int cout, int relu,
-                                                           Grid3 g, int ntx, int nty) {
-  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
-  constexpr int RS = 16 + 4;                          // LDS row stride (bf16) of a weight chunk
-  constexpr int HV = kHX * kHY * kHZ;
-  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
-  __shared__ __attribute__((aligned(16))) bf16 wk[27][COUTP * RS];
-  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
-  const int i = l & 15, kq = l >> 4;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
-  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < KC; ++kc) {
-    for (int idx = tid; idx < HV * 4; idx += 256) {
-      const int q = idx & 3, hv = idx >> 2;
-      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      s4 val = s4{0, 0, 0, 0};
-      if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
-        const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
-        val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
-      }
-      *reinterpret_cast<s4*>(&xs[hv][4 * q]) = val;
-    }
-    // weights W[tap][co][ci], ci in this chunk: 4 bf16 per piece
-    for (int idx = tid; idx < 27 * COUTP * 4; idx += 256) {
-      const int q = idx & 3, co = (idx >> 2) % COUTP, tap = (idx >> 2) / COUTP;
-      *reinterpret_cast<s4*>(&wk[tap][co * RS + 4 * q]) =
-          *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
-    }
-    __syncthreads();
-    for (int tap = 0; tap < 27; ++tap) {
-      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-      s4 a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
-        a[m] = *reinterpret_cast<const s4*>(&xs[hv][4 * kq]);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const s4 bf = *reinterpret_cast<const s4*>(&wk[tap][(t * 16 + i) * RS + 4 * kq]);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bf, acc[m][t], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  const int oz = z0 + wave;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int oy = y0 + m;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + i;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ox = x0 + 4 * kq + e;
-        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
-        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
-        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
-        if (relu) val = fmaxf(val, 0.f);
-        if (out32)
-          out32[vo * 2 + co] = val;
-        else
-          out.p[vo * out.cs + out.coff + co] = f2bf(val);
-      }
-    }
-  }
-}
-
-// conv_tile_co_kernel on v_mfma_f32_16x16x32_bf16 (K = 32 per instruction):
-// the K dimension pairs two taps of one 16-channel chunk, lanes 0-31 taking
-// the first tap's channels and lanes 32-63 the second's (A[l%16][8(l/16)+e],
-// B[8(l/16)+e][l%16]; 16-byte LDS reads), so the 27 taps of a chunk take 14
-// instructions per row tile (the last pairs tap 26 with zeros).
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4w __attribute__((ext_vector_type(4)));
 
+// The tiled convolution on the K = 32 instruction: two taps per instruction
+// (lanes 0-31 the first tap's channels of a 16-channel chunk, 32-63 the
+// second's), the input block of one chunk in LDS at a time and the weights of
+// one tap pair of that chunk double-buffered beside it (24-39 KB of LDS).
+// Steps s = (chunk, pair) run in order; the input block is restaged between
+// chunks.
 template <int CIN, int COUTP>
-__global__ __launch_bounds__(256) void conv_x32_kernel(View in, const bf16* __restrict__ W,
-                                                       const float* __restrict__ bias, View out,
-                                                       float* __restrict__ out32, int cout, int relu,
-                                                       Grid3 g, int ntx, int nty) {
-  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
-  constexpr int RS = 16 + 8;                          // weight row stride (bf16): 16-byte aligned rows
-  constexpr int HV = kHX * kHY * kHZ;
-  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
-  __shared__ __attribute__((aligned(16))) bf16 wk[27][COUTP * RS];
-  const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
-  const int i = l & 15, half = (l >> 4) & 1, second = l >> 5;   // channel half, tap of the pair
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
-  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int kc = 0; kc < KC; ++kc) {
-    for (int idx = tid; idx < HV * 4; idx += 256) {
-      const int q = idx & 3, hv = idx >> 2;
-      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      s4 val = s4{0, 0, 0, 0};
-      if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
-        const long long v = gx + (long long)g.X * (gy + (long long)g.Y * gz);
-        val = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + 16 * kc + 4 * q);
-      }
-      *reinterpret_cast<s4*>(&xs[hv][4 * q]) = val;
-    }
-    for (int idx = tid; idx < 27 * COUTP * 4; idx += 256) {
-      const int q = idx & 3, co = (idx >> 2) % COUTP, tap = (idx >> 2) / COUTP;
-      *reinterpret_cast<s4*>(&wk[tap][co * RS + 4 * q]) =
-          *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
-    }
-    __syncthreads();
-    for (int tp = 0; tp < 27; tp += 2) {
-      const int tap = tp + second;                       // this lane's tap of the pair
-      const bool real = tap < 27;
-      const int tc = real ? tap : 26;
-      const int dz = tc / 9 - 1, dy = (tc / 3) % 3 - 1, dx = tc % 3 - 1;
-      bf8v a[MT];
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
-        u4w w = *reinterpret_cast<const u4w*>(&xs[hv][8 * half]);
-        if (!real) w = u4w{0u, 0u, 0u, 0u};
-        a[m] = __builtin_bit_cast(bf8v, w);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        u4w wb = *reinterpret_cast<const u4w*>(&wk[tc][(t * 16 + i) * RS + 8 * half]);
-        if (!real) wb = u4w{0u, 0u, 0u, 0u};
-        const bf8v bfr = __builtin_bit_cast(bf8v, wb);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bfr, acc[m][t], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-  const int oz = z0 + wave;
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int oy = y0 + m;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + i;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ox = x0 + 4 * (l >> 4) + e;
-        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
-        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
-        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
-        if (relu) val = fmaxf(val, 0.f);
-        if (out32)
-          out32[vo * 2 + co] = val;
-        else
-          out.p[vo * out.cs + out.coff + co] = f2bf(val);
-      }
-    }
-  }
-}
-
-// conv_tile_kernel for 16 input channels on the K = 32 instruction: two taps
-// per instruction (lanes 0-31 the first tap's channels, 32-63 the second's),
-// the weights of a tap pair double-buffered in LDS.
-template <int COUTP>
 __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16* __restrict__ W,
                                                             const float* __restrict__ bias, View out,
                                                             float* __restrict__ out32, int cout, int relu,
                                                             Grid3 g, int ntx, int nty) {
-  constexpr int NT = COUTP / 16, MT = 4;
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
+  constexpr int NP = 14, NS = KC * NP;               // tap pairs per chunk, steps
   constexpr int RS = 16 + 8;                          // weight row stride (bf16): 16-byte aligned rows
   constexpr int HV = kHX * kHY * kHZ;
   __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
@@ -441,7 +84,8 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   const int i = l & 15, half = (l >> 4) & 1, second = l >> 5;
   const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
   const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  {
+  // input block with halo of chunk kc: every global load issued before the first LDS store
+  auto stage_x = [&](int kc) {
     constexpr int NPIECE = HV * 4, NPER = (NPIECE + 255) / 256;
     s4 val[NPER];
 #pragma unroll
@@ -452,7 +96,7 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
       const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
       const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
       const long long v = inside ? gx + (long long)g.X * (gy + (long long)g.Y * gz) : 0;
-      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 4 * q : 0));
+      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 16 * kc + 4 * q : 0));
       if (!inside) val[k] = s4{0, 0, 0, 0};
     }
 #pragma unroll
@@ -460,13 +104,14 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
       const int idx = tid + 256 * k;
       if (idx < NPIECE) *reinterpret_cast<s4*>(&xs[idx >> 2][4 * (idx & 3)]) = val[k];
     }
-  }
-  // weights of taps tp, tp + 1 (zero past tap 26): W[tap][co][ci], 16 channels
-  auto stage = [&](int tp, int b) {
+  };
+  // weights of step st: taps 2p, 2p + 1 (zero past tap 26), channels of chunk kc
+  auto stage_w = [&](int st, int b) {
+    const int kc = st / NP, tp = 2 * (st % NP);
     for (int idx = tid; idx < 2 * COUTP * 4; idx += 256) {
       const int q = idx & 3, co = (idx >> 2) % COUTP, u = (idx >> 2) / COUTP, tap = tp + u;
       s4 val = s4{0, 0, 0, 0};
-      if (tap < 27) val = *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * 16 + 4 * q);
+      if (tap < 27) val = *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
       *reinterpret_cast<s4*>(&ws[b][u][co * RS + 4 * q]) = val;
     }
   };
@@ -475,11 +120,13 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  stage(0, 0);
+  stage_x(0);
+  stage_w(0, 0);
   __syncthreads();
-  for (int tp = 0; tp < 27; tp += 2) {
-    const int b = (tp >> 1) & 1;
-    if (tp + 2 < 27) stage(tp + 2, b ^ 1);
+  for (int st = 0; st < NS; ++st) {
+    const int b = st & 1, p = st % NP;
+    if (st + 1 < NS) stage_w(st + 1, b ^ 1);
+    const int tp = 2 * p;
     const int tc = tp + second < 27 ? tp + second : 26;     // tap 27 reads tap 26's input, zero weights
     const int dz = tc / 9 - 1, dy = (tc / 3) % 3 - 1, dx = tc % 3 - 1;
     bf8v a[MT];
@@ -495,6 +142,10 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
       for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bfr, acc[m][t], 0, 0, 0);
     }
     __syncthreads();
+    if (KC > 1 && p == NP - 1 && st + 1 < NS) {      // next chunk: restage the input block
+      stage_x(st / NP + 1);
+      __syncthreads();
+    }
   }
   const int oz = z0 + wave;
 #pragma unroll
@@ -884,63 +535,18 @@ hipError_t dalloc(h6_net N, T** p, size_t count) {
 
 unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
-// layers on the LDS-tiled kernels: the chunk-outer form (one input chunk and
-// all 27 taps of its weights in LDS) on the K = 32 matrix instruction for
-// 48 -> 16 and on K = 16 for 96 -> 32 and 64 -> 32; the per-tap-pair K = 32
-// form for 16 input channels (more workgroups per CU than the chunk-outer
-// one); the per-tap K = 16 form for the other narrow layers; the rest read
-// their activations through L1 (conv_kernel)
-#define H6_CONV_X32_CASES(X) X(48, 16)
-#define H6_CONV_TILE_X32_CASES(X) X(16, 16) X(16, 32) X(16, 48)
-#define H6_CONV_CO_CASES(X) X(96, 32) X(64, 32)
-#define H6_CONV_TILE_CASES(X) X(32, 32) X(32, 64) X(32, 96) X(32, 16)
-
 #define H6_CONV_CASES(X) \
-  X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16) X(16, 48) X(32, 96) X(64, 32) X(32, 16)
+  X(16, 16) X(16, 32) X(16, 48) X(48, 16) X(96, 32) X(64, 32) X(32, 32) X(32, 64) X(32, 96) X(32, 16) X(64, 64)
 
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s) {
-  // LDS-tiled kernels: 16 x 4 x 4 output blocks
   const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
-  const unsigned tgrid = unsigned(ntx) * nty * ntz;
-#define H6_CONVCO(CI, CO)                                                                            \
+  const unsigned grid = unsigned(ntx) * nty * ntz;
+#define H6_CONV(CI, CO)                                                                              \
   if (cinp == CI && coutp == CO) {                                                                   \
-    hipLaunchKernelGGL((conv_tile_co_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out, \
+    hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO>), dim3(grid), dim3(256), 0, s, in, W, bias, out, \
                        out32, cout, relu, g, ntx, nty);                                              \
     return hipGetLastError();                                                                        \
-  }
-  H6_CONV_CO_CASES(H6_CONVCO)
-#undef H6_CONVCO
-#define H6_CONVX(CI, CO)                                                                             \
-  if (cinp == CI && coutp == CO) {                                                                   \
-    hipLaunchKernelGGL((conv_x32_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,    \
-                       out32, cout, relu, g, ntx, nty);                                              \
-    return hipGetLastError();                                                                        \
-  }
-  H6_CONV_X32_CASES(H6_CONVX)
-#undef H6_CONVX
-#define H6_CONVTX(CI, CO)                                                                            \
-  if (cinp == CI && coutp == CO) {                                                                   \
-    hipLaunchKernelGGL((conv_tile_x32_kernel<CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
-                       out32, cout, relu, g, ntx, nty);                                              \
-    return hipGetLastError();                                                                        \
-  }
-  H6_CONV_TILE_X32_CASES(H6_CONVTX)
-#undef H6_CONVTX
-#define H6_CONVT(CI, CO)                                                                             \
-  if (cinp == CI && coutp == CO) {                                                                   \
-    hipLaunchKernelGGL((conv_tile_kernel<CI, CO>), dim3(tgrid), dim3(256), 0, s, in, W, bias, out,   \
-                       out32, cout, relu, g, ntx, nty);                                              \
-    return hipGetLastError();                                                                        \
-  }
-  H6_CONV_TILE_CASES(H6_CONVT)
-#undef H6_CONVT
-  const unsigned grid = unsigned((g.P() + 16 * kConvMT * kConvWaves - 1) / (16 * kConvMT * kConvWaves));
-#define H6_CONV(CI, CO)                                                                             \
-  if (cinp == CI && coutp == CO) {                                                                  \
-    hipLaunchKernelGGL((conv_kernel<CI, CO>), dim3(grid), dim3(64 * kConvWaves), 0, s, in, W, bias, \
-                       out, out32, cout, relu, g);                                                  \
-    return hipGetLastError();                                                                       \
   }
   H6_CONV_CASES(H6_CONV)
 #undef H6_CONV
