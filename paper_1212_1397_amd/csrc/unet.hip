@@ -248,6 +248,104 @@ __global__ __launch_bounds__(256) void wgrad_kernel(View dz, View xin, float* __
   if (tap == 13 && tid < COUTP) bpart[(size_t)gi * COUTP + tid] = bsum;
 }
 
+// Weight gradient with all 27 taps in one workgroup (layers with at most
+// three 16 x 16 channel tiles): a workgroup walks 16 x 4 x 4 voxel blocks
+// (grid-stride), stages the block's output gradient transposed (dzT[co][v])
+// and its input with the one-voxel halo (xh[hv][ci]) in LDS once, and every
+// wave accumulates the products of its taps (w, w + 4, ...) over the block's
+// 256 voxels: dW[tap][co][ci] += sum_v dz[v][co] x[v + tap][ci] (rows co,
+// columns ci, k = voxels).  Partials per workgroup, summed in order by
+// wgrad_reduce_kernel; bias partials sum dz over the same voxels.
+constexpr int kWgTileGroups = 512;
+
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(256) void wgrad_tile_kernel(View dz, View xin, float* __restrict__ part,
+                                                         float* __restrict__ bpart, Grid3 g, int ntx,
+                                                         int nty, int nblocks) {
+  constexpr int NA = COUTP / 16, NB = CINP / 16, NPAIR = NA * NB;
+  constexpr int HV = kHX * kHY * kHZ, NV = kTX * kTY * kTZ;
+  constexpr int DS = NV + 4;                          // dzT row stride (bf16)
+  constexpr int NTT = 7;                              // taps per wave (27 = 4 x 7 - 1)
+  __shared__ __attribute__((aligned(16))) bf16 dzT[COUTP * DS];
+  __shared__ __attribute__((aligned(16))) bf16 xh[HV * CINP];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, i = l & 15, kq = l >> 4;
+  f4 acc[NTT][NPAIR];
+#pragma unroll
+  for (int tt = 0; tt < NTT; ++tt)
+#pragma unroll
+    for (int q = 0; q < NPAIR; ++q) acc[tt][q] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
+    const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
+    __syncthreads();                                  // the previous block's reads are done
+    for (int idx = tid; idx < NV * (COUTP / 4); idx += 256) {
+      const int v = idx / (COUTP / 4), cq = idx % (COUTP / 4);
+      const int gx = x0 + (v & 15), gy = y0 + ((v >> 4) & 3), gz = z0 + (v >> 6);
+      s4 a = s4{0, 0, 0, 0};
+      if (gx < g.X && gy < g.Y && gz < g.Z) {
+        const long long gv = gx + (long long)g.X * (gy + (long long)g.Y * gz);
+        a = *reinterpret_cast<const s4*>(dz.p + gv * dz.cs + dz.coff + 4 * cq);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dzT[(4 * cq + e) * DS + v] = bf16(a[e]);
+    }
+    for (int idx = tid; idx < HV * (CINP / 4); idx += 256) {
+      const int hv = idx / (CINP / 4), cq = idx % (CINP / 4);
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      s4 a = s4{0, 0, 0, 0};
+      if (gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z) {
+        const long long gv = gx + (long long)g.X * (gy + (long long)g.Y * gz);
+        a = *reinterpret_cast<const s4*>(xin.p + gv * xin.cs + xin.coff + 4 * cq);
+      }
+      *reinterpret_cast<s4*>(&xh[hv * CINP + 4 * cq]) = a;
+    }
+    __syncthreads();
+    if (tid < COUTP)
+      for (int v = 0; v < NV; ++v) bsum += bf2f(dzT[tid * DS + v]);
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) {
+      const int t = wave + 4 * tt;
+      if (t < 27) {
+        const int dxt = t % 3 - 1, dyt = (t / 3) % 3 - 1, dzt = t / 9 - 1;
+#pragma unroll 2
+        for (int kc = 0; kc < NV / 16; ++kc) {       // one x row of the block: y = kc & 3, z = kc >> 2
+          const int hrow = kHX * (((kc & 3) + 1 + dyt) + kHY * ((kc >> 2) + 1 + dzt)) + 1 + dxt;
+          s4 a[NA], b[NB];
+#pragma unroll
+          for (int ta = 0; ta < NA; ++ta)
+            a[ta] = *reinterpret_cast<const s4*>(&dzT[(ta * 16 + i) * DS + kc * 16 + 4 * kq]);
+#pragma unroll
+          for (int tb = 0; tb < NB; ++tb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b[tb][e] = short(xh[(hrow + 4 * kq + e) * CINP + tb * 16 + i]);
+#pragma unroll
+          for (int ta = 0; ta < NA; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < NB; ++tb)
+              acc[tt][ta * NB + tb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ta], b[tb], acc[tt][ta * NB + tb], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const int gi = blockIdx.x;
+#pragma unroll
+  for (int tt = 0; tt < NTT; ++tt) {
+    const int t = wave + 4 * tt;
+    if (t < 27) {
+      float* dst = part + ((size_t)gi * 27 + t) * COUTP * CINP;
+#pragma unroll
+      for (int ta = 0; ta < NA; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NB; ++tb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dst[(ta * 16 + 4 * kq + e) * CINP + tb * 16 + i] = acc[tt][ta * NB + tb][e];
+    }
+  }
+  if (tid < COUTP) bpart[(size_t)gi * COUTP + tid] = bsum;
+}
+
 // grad (parameter layout) of one layer from the partials, summed over the
 // G workgroup rows in order.
 __global__ void wgrad_reduce_kernel(const float* __restrict__ part, const float* __restrict__ bpart,
@@ -553,10 +651,26 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
   return hipErrorInvalidValue;
 }
 
+#define H6_WGRAD_TILE_CASES(X) X(16, 16) X(16, 32) X(48, 16)
 #define H6_WGRAD_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16)
 
+// weight-gradient partials of one layer; *groups = the number of partial rows
 hipError_t wgrad(View dz, View xin, int cinp, int coutp, float* part, float* bpart, Grid3 g,
-                 hipStream_t s) {
+                 hipStream_t s, int* groups) {
+  {
+    const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
+    const int nblocks = ntx * nty * ntz;
+#define H6_WGT(CI, CO)                                                                               \
+  if (cinp == CI && coutp == CO) {                                                                   \
+    hipLaunchKernelGGL((wgrad_tile_kernel<CI, CO>), dim3(kWgTileGroups), dim3(256), 0, s, dz, xin,   \
+                       part, bpart, g, ntx, nty, nblocks);                                           \
+    *groups = kWgTileGroups;                                                                         \
+    return hipGetLastError();                                                                        \
+  }
+    H6_WGRAD_TILE_CASES(H6_WGT)
+#undef H6_WGT
+  }
+  *groups = kWgGroups;
 #define H6_WG(CI, CO)                                                                              \
   if (cinp == CI && coutp == CO) {                                                                 \
     hipLaunchKernelGGL((wgrad_kernel<CI, CO>), dim3(27, kWgGroups), dim3(256), 0, s, dz, xin, part, \
@@ -617,10 +731,11 @@ hipError_t layer_bwd(h6_net N, int L, View act, View gout, View xin, View gin, G
   if (d.relu)
     hipLaunchKernelGGL(relu_back_kernel, dim3(nblk(g.P() * d.cout)), dim3(256), 0, s, gout, act, g.P(),
                        d.cout);
-  if ((e = wgrad(gout, xin, cinp, coutp, N->part, N->bpart, g, s)) != hipSuccess) return e;
+  int G = 0;
+  if ((e = wgrad(gout, xin, cinp, coutp, N->part, N->bpart, g, s, &G)) != hipSuccess) return e;
   const long long nw = (long long)d.cout * d.cin * 27;
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nblk(nw + d.cout)), dim3(256), 0, s, N->part, N->bpart,
-                     kWgGroups, d.cin, d.cout, cinp, coutp, N->grad + N->off[L], N->grad + N->off[L] + nw);
+                     G, d.cin, d.cout, cinp, coutp, N->grad + N->off[L], N->grad + N->off[L] + nw);
   if (gin.p)
     return conv(gout, coutp, N->wb[L], cinp, nullptr, gin, nullptr, cinp, 0, g, s);
   return hipGetLastError();
@@ -671,8 +786,10 @@ hipError_t alloc_training(h6_net N) {
   A(&N->dY, p1 * 16); A(&N->dD1, p1 * 16); A(&N->dT1b, p1 * 16); A(&N->dC1, p1 * 48); A(&N->dT1, p1 * 16);
   A(&N->dD2, p2 * 32); A(&N->dT2b, p2 * 32); A(&N->dC2, p2 * 96); A(&N->dT2, p2 * 32); A(&N->dPl1, p2 * 16);
   A(&N->dB3, p3 * 64); A(&N->dT3, p3 * 64); A(&N->dPl2, p3 * 32);
+  // partial rows: kWgGroups of up to 96 x 64 channels, or kWgTileGroups of up to 768 channel pairs
+  static_assert(size_t(kWgTileGroups) * 27 * 768 <= size_t(kWgGroups) * 27 * 96 * 64, "wgrad partials");
   if (e == hipSuccess) e = dalloc(N, &N->part, size_t(kWgGroups) * 27 * 96 * 64);
-  if (e == hipSuccess) e = dalloc(N, &N->bpart, size_t(kWgGroups) * 64);
+  if (e == hipSuccess) e = dalloc(N, &N->bpart, size_t(kWgTileGroups) * 64);
   if (e == hipSuccess) e = dalloc(N, &N->m, size_t(N->np));
   if (e == hipSuccess) e = dalloc(N, &N->v, size_t(N->np));
   return e;
