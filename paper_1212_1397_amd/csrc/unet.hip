@@ -652,6 +652,15 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
 }
 
 #define H6_WGRAD_TILE_CASES(X) X(16, 16) X(16, 32) X(48, 16)
+#define H6_WGT_PAIRS(CI, CO) (CI) * (CO),
+constexpr int kWgTilePairs[] = {H6_WGRAD_TILE_CASES(H6_WGT_PAIRS)};
+#undef H6_WGT_PAIRS
+// Largest channel-pair count of the tiled cases: sizes their partial rows.
+constexpr size_t wgrad_tile_pairs_max() {
+  size_t m = 0;
+  for (int p : kWgTilePairs) m = size_t(p) > m ? size_t(p) : m;
+  return m;
+}
 #define H6_WGRAD_CASES(X) X(16, 16) X(16, 32) X(32, 32) X(32, 64) X(64, 64) X(96, 32) X(48, 16)
 
 // weight-gradient partials of one layer; *groups = the number of partial rows
@@ -786,8 +795,9 @@ hipError_t alloc_training(h6_net N) {
   A(&N->dY, p1 * 16); A(&N->dD1, p1 * 16); A(&N->dT1b, p1 * 16); A(&N->dC1, p1 * 48); A(&N->dT1, p1 * 16);
   A(&N->dD2, p2 * 32); A(&N->dT2b, p2 * 32); A(&N->dC2, p2 * 96); A(&N->dT2, p2 * 32); A(&N->dPl1, p2 * 16);
   A(&N->dB3, p3 * 64); A(&N->dT3, p3 * 64); A(&N->dPl2, p3 * 32);
-  // partial rows: kWgGroups of up to 96 x 64 channels, or kWgTileGroups of up to 768 channel pairs
-  static_assert(size_t(kWgTileGroups) * 27 * 768 <= size_t(kWgGroups) * 27 * 96 * 64, "wgrad partials");
+  // partial rows: kWgGroups of up to 96 x 64 channels, or kWgTileGroups of every tiled layer's pairs
+  static_assert(size_t(kWgTileGroups) * 27 * wgrad_tile_pairs_max() <= size_t(kWgGroups) * 27 * 96 * 64,
+                "wgrad partials");
   if (e == hipSuccess) e = dalloc(N, &N->part, size_t(kWgGroups) * 27 * 96 * 64);
   if (e == hipSuccess) e = dalloc(N, &N->bpart, size_t(kWgTileGroups) * 64);
   if (e == hipSuccess) e = dalloc(N, &N->m, size_t(N->np));
