@@ -284,8 +284,9 @@ def main():
           f"method {args.method}", file=sys.stderr, flush=True)
 
     def one_solve(pl, method):
-        U.zero_()
-        _, info = pl.solve(F, U, method=method, restart=w.restart, tol=w.tol, maxit=500)
+        # from U = 0: the library does not read U (SKS starts with U_1 = A_p^{-1} F)
+        _, info = pl.solve(F, U, method=method, restart=w.restart, tol=w.tol, maxit=500,
+                           zero_guess=True)
         if info["status"] != "ok":
             raise RuntimeError(f"solve did not converge: {info}")
         return info

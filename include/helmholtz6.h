@@ -79,6 +79,11 @@ typedef struct {
   double* history;   /* in (optional, host): per-iteration residual estimates (GMRES: the
                         least-squares residual; SKS: the true residual), relative to ||F|| */
   int history_len;   /* in: capacity of history; out: entries written */
+  int zero_guess;    /* in: nonzero: the solve starts from U = 0 and U's contents are never
+                        read (U may hold anything).  SKS then forms U_1 = A_p^{-1} F directly
+                        (r_0 = F, no residual pass) with the same arithmetic as from a zeroed
+                        U; the other methods clear U on the stream first.  0: U is the initial
+                        guess. */
 } h6_solve_info;
 
 /* Builds a plan: validates the parameters, derives the unknown counts, the

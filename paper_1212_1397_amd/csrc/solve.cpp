@@ -500,7 +500,7 @@ h6_status zero_solution(Ctx& c, double2* U, h6_solve_info* info) {
 // order after the wait: no reduction kernel and no copy per iteration.  The
 // first residual pass also sums |F|^2 (it reads F anyway), which replaces
 // the separate norm pass of the other solvers.
-h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info) {
+h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, bool zero_guess) {
   h6_plan P = c.P;
   const bool mixed = P->p.precision == H6_MIXED;
   float2* r32 = reinterpret_cast<float2*>(P->r);
@@ -528,10 +528,30 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info) {
     return mixed ? launch_pinv_acc_f32in(P, r32, U, c.s, part) : launch_pinv_acc(P, P->r, U, c.s, part);
   };
   int nh = 0;
-  h6_status st = resid(true);
-  if (st != H6_OK) return st;
   info->iters = 0;
   double normF = -1.0;
+  h6_status st = H6_OK;
+  if (zero_guess) {
+    // from U_0 = 0: r_0 = F, so the first step is U_1 = A_p^{-1} F, written
+    // over U, then r_1; |F| comes from a norm pass enqueued behind them
+    H6_TRY_HIP(launch_pinv(P, F, U, c.s, PINV_ALL));
+    st = resid(false);
+    if (st != H6_OK) return st;
+    double normF2 = 0.0;
+    st = norm2(c, F, &normF2);
+    if (st != H6_OK) return st;
+    normF = std::sqrt(normF2);
+    if (normF == 0.0) return zero_solution(c, U, info);
+    if (info->tol >= 1.0) {                     // U_0 = 0 already meets the tolerance
+      st = zero_solution(c, U, info);
+      info->rel_resid = 1.0;
+      return st;
+    }
+    info->iters = 1;
+  } else {
+    st = resid(true);
+  }
+  if (st != H6_OK) return st;
   while (true) {
     const bool more = info->iters < info->maxit;
     if (more) H6_TRY_HIP(pinv(PINV_FIRST));
@@ -626,7 +646,10 @@ h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info
   }
   Ctx c{P, s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
   info->iters = 0;
-  if (info->method == H6_SKS) return sks(c, F, U, info);    // |F| from its first residual pass
+  const bool zero_guess = info->zero_guess != 0;
+  // |F| from its first residual pass, or from a norm pass from a zero guess
+  if (info->method == H6_SKS) return sks(c, F, U, info, zero_guess);
+  if (zero_guess) H6_TRY_HIP(hipMemsetAsync(U, 0, c.N * sizeof(double2), c.s));
   double normF2 = 0.0;
   st = norm2(c, F, &normF2);
   if (st != H6_OK) return st;

@@ -47,7 +47,8 @@ class H6Params(ctypes.Structure):
 class H6SolveInfo(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("iters", ctypes.c_int), ("rel_resid", ctypes.c_double),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("zero_guess", ctypes.c_int)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -255,12 +256,16 @@ class Plan:
         return F
 
     def solve(self, F, U=None, method="gmres", restart=30, maxit=1000, tol=1e-10, history=512,
-              stream=None):
-        """Solve A U = F (U: initial guess, overwritten).  Returns (U, info dict)."""
-        U = torch.zeros_like(F) if U is None else U
+              stream=None, zero_guess=None):
+        """Solve A U = F (U: initial guess, overwritten).  Returns (U, info dict).
+        zero_guess=True starts from U = 0 without reading U (default: when U is None)."""
+        if zero_guess is None:
+            zero_guess = U is None
+        U = torch.empty_like(F) if U is None else U
         hist = (ctypes.c_double * max(history, 1))()
         info = H6SolveInfo(METHODS[method], int(restart), int(maxit), float(tol), 0, 0.0,
-                           ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(history))
+                           ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(history),
+                           int(bool(zero_guess)))
         st = self._check(_lib.helmholtz6_solve(self._plan, self._vec(F, "F"), self._vec(U, "U"),
                                                ctypes.byref(info), _stream_handle(stream)))
         status = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}[st]

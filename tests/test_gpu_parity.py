@@ -205,3 +205,25 @@ def test_solver_status_codes():
         assert info["status"] == "ok" and info["iters"] == 0 and float(U.abs().max()) == 0.0, prec
     with pytest.raises(ValueError):
         plan.apply_A(F[:, :, :-1].contiguous())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("method", ["sks", "fgmres"])
+def test_zero_guess_matches_zeroed_start(prec, method):
+    # zero_guess never reads U: a NaN-filled U gives the iterates of U = 0
+    # (SKS forms U_1 = A_p^{-1} F directly; the other methods clear U)
+    h6 = _h6()
+    n, k, bc = (30, 27, 33), 8.0 + 0.1j, "DDNNSS"
+    prob = _problem(n, k, bc)
+    pl = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+    F = to_gpu(random_field(prob.shape, seed=5))
+    kw = dict(method=method, restart=20, maxit=80, tol=1e-9)
+    Ua, ia = pl.solve(F, torch.zeros_like(F), zero_guess=False, **kw)
+    Ub, ib = pl.solve(F, torch.full_like(F, float("nan")), zero_guess=True, **kw)
+    assert ia["status"] == ib["status"] == "ok" and ia["iters"] == ib["iters"]
+    assert relerr(Ub.cpu().numpy(), Ua.cpu().numpy()) <= 1e-12
+    assert ib["history"] == pytest.approx(ia["history"], rel=1e-10)
+    # a tolerance that U = 0 already meets returns U = 0 without a step
+    kw["tol"] = 1.0
+    Uc, ic = pl.solve(F, torch.full_like(F, float("nan")), zero_guess=True, **kw)
+    assert ic["status"] == "ok" and ic["iters"] == 0 and float(Uc.abs().max()) == 0.0
