@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -26,20 +27,28 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, cmds = [], []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
-               "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include"),
-               *DEVICE_FLAGS, *lang, path, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-c",
+                     "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include"),
+                     *DEVICE_FLAGS, *lang, path, "-o", obj])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # the sources compile independently; at most 8 compiler processes at once
+    jobs = max(1, min(8, len(cmds), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for res in pool.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+            if verbose or res.returncode != 0:
+                sys.stderr.write(res.stderr)
+            if res.returncode != 0:
+                raise subprocess.CalledProcessError(res.returncode, res.args, res.stdout, res.stderr)
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
