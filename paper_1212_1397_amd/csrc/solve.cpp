@@ -552,9 +552,24 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, bool ze
     st = resid(true);
   }
   if (st != H6_OK) return st;
+  // The first pass of the next preconditioner application is enqueued before
+  // the host waits for |r| (speculatively), except when the residual trend
+  // (geometric: the last ratio of successive residuals) predicts that this
+  // residual meets the tolerance.  Every return waits for the stream, so no
+  // speculative pass is left running.
+  double prev = -1.0, predicted = -1.0;
+  auto finish = [&](h6_status s) -> h6_status {
+    info->history_len = nh;
+    if (hipStreamSynchronize(c.s) != hipSuccess) {
+      P->last_error = "hipStreamSynchronize failed at the end of the SKS solve";
+      return H6_ERR_HIP;
+    }
+    return s;
+  };
   while (true) {
     const bool more = info->iters < info->maxit;
-    if (more) H6_TRY_HIP(pinv(PINV_FIRST));
+    const bool spec = more && !(predicted >= 0.0 && predicted <= info->tol);
+    if (spec) H6_TRY_HIP(pinv(PINV_FIRST));
     st = wait(c);
     if (st != H6_OK) return st;
     if (normF < 0.0) {
@@ -563,12 +578,13 @@ h6_status sks(Ctx& c, const double2* F, double2* U, h6_solve_info* info, bool ze
     }
     info->rel_resid = std::sqrt(host_sum(P->h_parts)) / normF;
     if (info->iters > 0) record(info, nh, info->rel_resid);
-    if (info->rel_resid <= info->tol) { info->history_len = nh; return H6_OK; }
-    if (!std::isfinite(info->rel_resid) || (info->iters > 0 && info->rel_resid > 1e4)) {
-      info->history_len = nh;
-      return H6_DIVERGED;
-    }
-    if (!more) { info->history_len = nh; return H6_NOT_CONVERGED; }
+    if (info->rel_resid <= info->tol) return finish(H6_OK);
+    if (!std::isfinite(info->rel_resid) || (info->iters > 0 && info->rel_resid > 1e4))
+      return finish(H6_DIVERGED);
+    if (!more) return finish(H6_NOT_CONVERGED);
+    predicted = prev > 0.0 ? info->rel_resid * (info->rel_resid / prev) : -1.0;
+    prev = info->rel_resid;
+    if (!spec) H6_TRY_HIP(pinv(PINV_FIRST));
     H6_TRY_HIP(pinv(PINV_REST));
     st = resid(false);
     if (st != H6_OK) return st;

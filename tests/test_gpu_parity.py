@@ -207,8 +207,8 @@ def test_solver_status_codes():
         plan.apply_A(F[:, :, :-1].contiguous())
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("method", ["sks", "fgmres"])
+@pytest.mark.parametrize("prec,method", [("fp64", "sks"), ("mixed", "sks"), ("fp64", "fgmres"),
+                                         ("mixed", "fgmres"), ("fp64", "gmres")])
 def test_zero_guess_matches_zeroed_start(prec, method):
     # zero_guess never reads U: a NaN-filled U gives the iterates of U = 0
     # (SKS forms U_1 = A_p^{-1} F directly; the other methods clear U)
@@ -227,3 +227,29 @@ def test_zero_guess_matches_zeroed_start(prec, method):
     kw["tol"] = 1.0
     Uc, ic = pl.solve(F, torch.full_like(F, float("nan")), zero_guess=True, **kw)
     assert ic["status"] == "ok" and ic["iters"] == 0 and float(Uc.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sks_returns_with_its_stream_idle(prec):
+    # SKS enqueues the first pass of the next preconditioner application
+    # before it reads |r|; the solve must not return with work of the plan
+    # still running: apply_Pinv on another stream right after the solve
+    # (the same plan workspace) gives the result of an isolated call, for a
+    # converged and for a not-converged return
+    h6 = _h6()
+    n, k, bc = (40, 30, 20), 12.0 + 0.1j, "DDNNSS"
+    prob = _problem(n, k, bc)
+    pl = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+    F = to_gpu(random_field(prob.shape, seed=8))
+    x = to_gpu(random_field(prob.shape, seed=9))
+    ref = pl.apply_Pinv(x)
+    torch.cuda.synchronize()
+    other = torch.cuda.Stream()
+    for maxit, status in ((3, "not_converged"), (200, "ok")):
+        U, info = pl.solve(F, method="sks", tol=1e-10, maxit=maxit)
+        assert info["status"] == status
+        with torch.cuda.stream(other):
+            out = torch.empty_like(x)
+            pl.apply_Pinv(x, out, stream=other)
+        other.synchronize()
+        assert torch.equal(out, ref), maxit
