@@ -108,6 +108,25 @@ h6_status helmholtz6_apply_A(h6_plan plan, const void* x, void* y, void* hip_str
  * Enqueue only. */
 h6_status helmholtz6_apply_Pinv(h6_plan plan, const void* r, void* z, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * z = A_p^{-1} r as helmholtz6_apply_Pinv (the same kernels, the same result
+ * bit for bit), with the preconditioner's two intermediate vectors in a fixed
+ * work space that the library holds in device memory (a file-scope array of
+ * 128 MiB, one copy on every GPU the library runs on, kept until the process
+ * ends) instead of the plan's workspace.  Limit: 2 vectors of n'x n'y n'z
+ * values in the plan's compute precision, each rounded up to 256 bytes, must
+ * fit in 128 MiB: up to 4,194,304 unknowns in H6_FP64 plans (complex128) and
+ * 8,388,608 in H6_MIXED plans (complex64); larger grids give H6_ERR_ARG with
+ * a message (use helmholtz6_apply_Pinv).  The call allocates nothing (no
+ * hipMalloc, hipFree, event creation or library allocation; kernel timing of
+ * helmholtz6_profile does not cover it).  Every call on one GPU shares that
+ * GPU's work space, which keeps the last call's contents: calls whose work
+ * overlaps in time on one GPU (other streams, other plans, other host threads)
+ * race and give wrong results; order them on one stream or synchronise.
+ * Nothing needs to start at zero.  Enqueue only. */
+h6_status helmholtz6_apply_Pinv_noalloc(h6_plan plan, const void* r, void* z, void* hip_stream);
+
 /* F = h^2-scaled compact right-hand side (eq. (scheme) right side, with the
  * mixed fourth-derivative coefficient h^4/180, plus the Neumann and
  * Sommerfeld face terms of (3DN) and (3DIMP)/(3DDISCS)) for the source

@@ -429,6 +429,12 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   if (e == hipSuccess) e = hipMalloc(&P->partials, sizeof(double) * 2 * kMaxPartials);
   if (e == hipSuccess) e = hipMalloc(&P->d_scal, sizeof(double2) * kScal);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), sizeof(double2) * kScal);
+  if (e == hipSuccess) {
+    // device address of the fixed work space of helmholtz6_apply_Pinv_noalloc
+    // on this device (looked up once per device)
+    void* ws = nullptr;
+    e = static_work_address(&ws);
+  }
   if (e != hipSuccess) {
     err = std::string("device setup failed: ") + hipGetErrorString(e);
     const bool oom = e == hipErrorOutOfMemory;
@@ -672,6 +678,31 @@ h6_status helmholtz6_apply_Pinv(h6_plan P, const void* r, void* z, void* hip_str
   if (!r || !z || r == z) { P->last_error = "r, z must be distinct non-null pointers"; return H6_ERR_ARG; }
   H6_TRY_HIP(launch_pinv(P, static_cast<const double2*>(r), static_cast<double2*>(z),
                          static_cast<hipStream_t>(hip_stream)));
+  return H6_OK;
+}
+
+h6_status helmholtz6_apply_Pinv_noalloc(h6_plan P, const void* r, void* z, void* hip_stream) {
+  if (!P) return H6_ERR_ARG;
+  P->last_error.clear();
+  if (!r || !z || r == z) { P->last_error = "r, z must be distinct non-null pointers"; return H6_ERR_ARG; }
+  const size_t elem = P->p.precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
+  const size_t vec = (P->N * elem + 255) / 256 * 256;
+  if (2 * vec > kStaticWorkBytes) {
+    P->last_error = "apply_Pinv_noalloc: this grid needs " + std::to_string(2 * vec) +
+                    " bytes of work space, more than the fixed " + std::to_string(kStaticWorkBytes) +
+                    " bytes (use helmholtz6_apply_Pinv)";
+    return H6_ERR_ARG;
+  }
+  void* base = nullptr;
+  H6_TRY_HIP(static_work_address(&base));
+  void* ws[2] = {base, static_cast<unsigned char*>(base) + vec};
+  // no timing events here (creating one may allocate)
+  const bool timed = P->timing.enabled;
+  P->timing.enabled = false;
+  const hipError_t e = launch_pinv_ws(P, static_cast<const double2*>(r), static_cast<double2*>(z), ws,
+                                      static_cast<hipStream_t>(hip_stream));
+  P->timing.enabled = timed;
+  H6_TRY_HIP(e);
   return H6_OK;
 }
 

@@ -187,6 +187,14 @@ hipError_t launch_stencil(h6_plan P, const double2* x, double2* y, const double2
 // the host.  PINV_ALL = both.
 enum { PINV_FIRST = 1, PINV_REST = 2, PINV_ALL = 3 };
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part = PINV_ALL);
+// z = A_p^{-1} r with the work vectors ws[0], ws[1] (each N complex values in
+// the plan's compute precision) instead of the plan's
+hipError_t launch_pinv_ws(h6_plan P, const double2* r, double2* z, void* const ws[2], hipStream_t s);
+// Fixed work space of helmholtz6_apply_Pinv_noalloc (a file-scope device
+// array): its size, and its device address on the current device (looked up
+// once per device).
+constexpr size_t kStaticWorkBytes = size_t(128) << 20;
+hipError_t static_work_address(void** out);
 // U += A_p^{-1} r (the update folded into the last inverse transform)
 hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s,
                            int part = PINV_ALL);

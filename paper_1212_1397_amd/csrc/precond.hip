@@ -14,11 +14,44 @@
 // (xform_dense.hip).  Compute type R is double (FP64 plans) or float (mixed
 // plans, complex64 intermediates); the input r and output z are complex128 in
 // both.
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "h6_internal.h"
 
 namespace h6 {
+
+// Fixed device work space of helmholtz6_apply_Pinv_noalloc: the two
+// intermediate vectors of the five passes, for callers that cannot allocate.
+// Every GPU the library runs on holds one copy until the process ends.  In
+// host code the name is only a host-side handle: kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticWorkBytes];
+
+namespace {
+std::mutex g_scratch_mutex;
+std::vector<void*> g_scratch_addr;   // per device ordinal, resolved once
+}  // namespace
+
+hipError_t static_work_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> g(g_scratch_mutex);
+  if (size_t(dev) >= g_scratch_addr.size()) g_scratch_addr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 namespace {
 
 template <typename R> struct C2;
@@ -176,12 +209,14 @@ __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
 }
 
 // z = A_p^{-1} r, or z += A_p^{-1} r with acc != 0 (folded into the last pass)
+// (ws: the two work vectors; NULL: the plan's own)
 template <typename R, typename Tin, typename Tout>
-hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, int acc = 0) {
+hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, int acc = 0,
+                     void* const* ws = nullptr) {
   using T2 = typename C2<R>::T;
   const int nx = P->dims[0], ny = P->dims[1], nz = P->dims[2];
-  T2* w0 = static_cast<T2*>(P->w_pc[0]);
-  T2* w1 = static_cast<T2*>(P->w_pc[1]);
+  T2* w0 = static_cast<T2*>(ws ? ws[0] : P->w_pc[0]);
+  T2* w1 = static_cast<T2*>(ws ? ws[1] : P->w_pc[1]);
   const AxisXform& X = P->ax[0];
   const AxisXform& Y = P->ax[1];
   const int nlines_x = ny * nz;
@@ -236,6 +271,11 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
 hipError_t launch_pinv(h6_plan P, const double2* r, double2* z, hipStream_t s, int part) {
   if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, z, s, part);
   return pinv_impl<double, double2, double2>(P, r, z, s, part);
+}
+
+hipError_t launch_pinv_ws(h6_plan P, const double2* r, double2* z, void* const ws[2], hipStream_t s) {
+  if (P->p.precision == H6_MIXED) return pinv_impl<float, double2, double2>(P, r, z, s, PINV_ALL, 0, ws);
+  return pinv_impl<double, double2, double2>(P, r, z, s, PINV_ALL, 0, ws);
 }
 
 hipError_t launch_pinv_acc(h6_plan P, const double2* r, double2* U, hipStream_t s, int part) {

@@ -25,6 +25,7 @@ KERNEL_CLASSES = ("stencil", "stencil_resid", "xform_x", "xform_y", "tridiag_z",
                   "mgs_update", "norm", "axpy", "rhs")
 
 EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
+            "helmholtz6_apply_Pinv_noalloc",
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
@@ -61,6 +62,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.helmholtz6_apply_A.argtypes = [vp, vp, vp, vp]
     lib.helmholtz6_apply_Pinv.argtypes = [vp, vp, vp, vp]
+    lib.helmholtz6_apply_Pinv_noalloc.argtypes = [vp, vp, vp, vp]
     lib.helmholtz6_rhs_gaussians.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp]
     lib.helmholtz6_solve.argtypes = [vp, vp, vp, ctypes.POINTER(H6SolveInfo), vp]
@@ -93,7 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_rhs_neumann.argtypes = [vp, ip, ip] + [ctypes.POINTER(ctypes.c_double)] * 3 + [vp, vp]
     lib.helmholtz6_rhs_neumann.restype = ctypes.c_int
     for name in ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmholtz6_apply_Pinv",
-                 "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
+                 "helmholtz6_apply_Pinv_noalloc", "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
                  "helmholtz6_kernel_time"):
         getattr(lib, name).restype = ctypes.c_int
     fp = ctypes.POINTER(ctypes.c_float)
@@ -190,6 +192,14 @@ class Plan:
         out = self.empty() if out is None else out
         self._check(_lib.helmholtz6_apply_Pinv(self._plan, self._vec(r, "r"), self._vec(out, "out"),
                                               _stream_handle(stream)))
+        return out
+
+    def apply_Pinv_noalloc(self, r, out=None, stream=None):
+        """apply_Pinv with the library's fixed device work space (allocates nothing
+        in the library; `out` must be given to avoid an allocation here)."""
+        out = self.empty() if out is None else out
+        self._check(_lib.helmholtz6_apply_Pinv_noalloc(self._plan, self._vec(r, "r"), self._vec(out, "out"),
+                                                      _stream_handle(stream)))
         return out
 
     def rhs_gaussians(self, centres, amps, sigma: float, out=None, stream=None):
