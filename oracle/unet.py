@@ -36,6 +36,17 @@ GMRES.  Definition (the one the GPU path implements):
   Sommerfeld faces A is not symmetric in its closure rows and this is the
   training gradient by definition (the GPU computes the same).
 
+* Storage precision.  The device stores activations and gradients in BF16
+  (the network's definition: BF16 activations, FP32 accumulation); the
+  functions below take an optional `store` map applied exactly where a value
+  is stored: the input features, every hidden layer's output after its ReLU,
+  the pooled values (forward); the output gradient, every convolution's input
+  gradient, the upsampling gradient and the sum of a skip gradient with the
+  pooling gradient (backward).  The final layer's output stays unrounded.
+  store=None is the exact FP64 network; store=round_bf16 takes every ReLU
+  decision on the values the device holds (both sides then decide in the
+  kernel's precision), so the two differ only by accumulation order.
+
 Gradients are written out by hand (the adjoint of each step in reverse
 order); the tests pin them to central finite differences.
 """
@@ -68,7 +79,8 @@ def conv(x, W, b):
     out = np.empty((W.shape[0], Z, Y, X))
     out[...] = b[:, None, None, None]
     for dz, dy, dx in _taps():
-        out += np.einsum("oc,czyx->ozyx", W[:, :, dz, dy, dx], xp[:, dz:dz + Z, dy:dy + Y, dx:dx + X])
+        # out[o, p] += sum_c W[o, c, t] x[c, p + t]  (contraction over the channel axis)
+        out += np.tensordot(W[:, :, dz, dy, dx], xp[:, dz:dz + Z, dy:dy + Y, dx:dx + X], axes=(1, 0))
     return out
 
 
@@ -80,8 +92,9 @@ def conv_backward(x, W, dout):
     dW = np.empty_like(W)
     for dz, dy, dx in _taps():
         sl = (slice(None), slice(dz, dz + Z), slice(dy, dy + Y), slice(dx, dx + X))
-        dW[:, :, dz, dy, dx] = np.einsum("ozyx,czyx->oc", dout, xp[sl])
-        dxp[sl] += np.einsum("oc,ozyx->czyx", W[:, :, dz, dy, dx], dout)
+        # dW[o, c, t] = sum_p dout[o, p] x[c, p + t];  dx[c, p + t] += sum_o W[o, c, t] dout[o, p]
+        dW[:, :, dz, dy, dx] = np.tensordot(dout, xp[sl], axes=([1, 2, 3], [1, 2, 3]))
+        dxp[sl] += np.tensordot(W[:, :, dz, dy, dx], dout, axes=(0, 0))
     return dxp[:, 1:-1, 1:-1, 1:-1], dW, dout.sum(axis=(1, 2, 3))
 
 
@@ -121,6 +134,21 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
+def round_bf16(a):
+    """Nearest BF16 value of each element (via binary32; BF16 keeps the sign,
+    the 8 exponent bits and the top 7 fraction bits of a binary32 number;
+    ties round to an even last kept bit), as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = ((u + 0x7FFF + lsb) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(a):
+    return a
+
+
 def features(r, k, h):
     """Network input of a complex residual r (n'z, n'y, n'x) and its scale s."""
     s = float(np.sqrt(np.mean(np.abs(r) ** 2)))
@@ -131,8 +159,11 @@ def features(r, k, h):
     return x, s
 
 
-def forward(params, x):
-    """Network output y (2, ...) and the saved activations for backward."""
+def forward(params, x, store=None):
+    """Network output y (2, ...) and the saved activations for backward
+    (store: the storage rounding, see the module docstring)."""
+    st = store or _identity
+    x = st(x)
     cache = {"x": x}
 
     def layer(name, inp):
@@ -143,23 +174,24 @@ def forward(params, x):
 
     n1 = x.shape[1:]
     n2 = pooled_shape(n1)
-    a = relu(layer("e1a", x))
-    s1 = relu(layer("e1b", a))
-    a = relu(layer("e2a", pool(s1)))
-    s2 = relu(layer("e2b", a))
-    a = relu(layer("b3a", pool(s2)))
-    b3 = relu(layer("b3b", a))
-    a = relu(layer("d2a", np.concatenate([up(b3, n2), s2])))
-    d2 = relu(layer("d2b", a))
-    a = relu(layer("d1a", np.concatenate([up(d2, n1), s1])))
-    d1 = relu(layer("d1b", a))
+    a = st(relu(layer("e1a", x)))
+    s1 = st(relu(layer("e1b", a)))
+    a = st(relu(layer("e2a", st(pool(s1)))))
+    s2 = st(relu(layer("e2b", a)))
+    a = st(relu(layer("b3a", st(pool(s2)))))
+    b3 = st(relu(layer("b3b", a)))
+    a = st(relu(layer("d2a", np.concatenate([up(b3, n2), s2]))))
+    d2 = st(relu(layer("d2b", a)))
+    a = st(relu(layer("d1a", np.concatenate([up(d2, n1), s1]))))
+    d1 = st(relu(layer("d1b", a)))
     y = layer("out", d1)
     cache["shapes"] = (n1, n2, pooled_shape(n2))
     return y, cache
 
 
-def backward(params, cache, dy):
+def backward(params, cache, dy, store=None):
     """Parameter gradients {name: (dW, db)} and the input gradient, for dL/dy."""
+    st = store or _identity
     grads = {}
     n1, n2, n3 = cache["shapes"]
 
@@ -169,49 +201,49 @@ def backward(params, cache, dy):
             dz = dz * (z > 0.0)
         dinp, dW, db = conv_backward(inp, params[name][0], dz)
         grads[name] = (dW, db)
-        return dinp
+        return st(dinp)
 
-    d = back("out", dy)
+    d = back("out", st(dy))
     d = back("d1b", d)
     d = back("d1a", d)                    # 48 channels: [up d2 (32), s1 (16)]
     ds1 = d[32:]
-    d = back("d2b", up_backward(d[:32], n2))
+    d = back("d2b", st(up_backward(d[:32], n2)))
     d = back("d2a", d)                    # 96 channels: [up b3 (64), s2 (32)]
     ds2 = d[64:]
-    d = back("b3b", up_backward(d[:64], n3))
+    d = back("b3b", st(up_backward(d[:64], n3)))
     d = back("b3a", d)
-    d = back("e2b", ds2 + pool_backward(d, n2))
+    d = back("e2b", st(ds2 + pool_backward(d, n2)))
     d = back("e2a", d)
-    d = back("e1b", ds1 + pool_backward(d, n1))
+    d = back("e1b", st(ds1 + pool_backward(d, n1)))
     dx = back("e1a", d)
     return grads, dx
 
 
-def correction(params, r, k, h):
+def correction(params, r, k, h, store=None):
     """c = s (y_0 + i y_1) for the residual r."""
     x, s = features(r, k, h)
-    y, _ = forward(params, x)
+    y, _ = forward(params, x, store)
     return s * (y[0] + 1j * y[1])
 
 
-def loss_and_grads(params, r, k, h, target):
+def loss_and_grads(params, r, k, h, target, store=None):
     """Relative squared error of the correction and its parameter gradients."""
     x, s = features(r, k, h)
-    y, cache = forward(params, x)
+    y, cache = forward(params, x, store)
     c = s * (y[0] + 1j * y[1])
     den = float(np.sum(np.abs(target) ** 2))
     diff = c - target
     L = float(np.sum(np.abs(diff) ** 2)) / den
     dy = np.stack([2.0 * s * diff.real, 2.0 * s * diff.imag]) / den
-    grads, _ = backward(params, cache, dy)
+    grads, _ = backward(params, cache, dy, store)
     return L, grads
 
 
-def loss_and_grads_op(params, r, k, h, target, apply_A):
+def loss_and_grads_op(params, r, k, h, target, apply_A, store=None):
     """Operator-weighted relative error L_A = |A (c - t)|^2 / |A t|^2 and its
     parameter gradients (apply_A: vector -> A vector, complex symmetric A)."""
     x, s = features(r, k, h)
-    y, cache = forward(params, x)
+    y, cache = forward(params, x, store)
     c = s * (y[0] + 1j * y[1])
     At = apply_A(target)
     den = float(np.sum(np.abs(At) ** 2))
@@ -219,7 +251,7 @@ def loss_and_grads_op(params, r, k, h, target, apply_A):
     L = float(np.sum(np.abs(u) ** 2)) / den
     g = np.conj(apply_A(np.conj(u)))          # A^H u for complex symmetric A
     dy = np.stack([2.0 * s * g.real, 2.0 * s * g.imag]) / den
-    grads, _ = backward(params, cache, dy)
+    grads, _ = backward(params, cache, dy, store)
     return L, grads
 
 

@@ -22,6 +22,68 @@ def make(h6, inst):
     return plan, F
 
 
+# instances of the 96-problem batch (seed 4) checked against the FP64 oracle:
+# both face patterns at n = 48, 64, 96, with the heavy tail (n = 48,
+# k_r = 56: k h = 1.15, about 110 FGMRES steps) of each pattern
+BATCH_ORACLE = (31, 46, 1, 2, 5, 17)
+
+
+@pytest.fixture(scope="module")
+def batch_oracle():
+    """The oracle's right-hand side, GMRES solution at tol 1e-11 and FP64
+    flexible GMRES step count at tol 1e-8 for each chosen batch instance."""
+    import oracle
+    from oracle.functions import gaussian_sources as oracle_sources
+    insts = batch_workload(96, seed=4)
+    out = {}
+    for idx in BATCH_ORACLE:
+        inst = insts[idx]
+        prob = oracle.Problem.cube(inst.n, inst.k, tuple(inst.bc))
+        Fo = oracle.rhs(prob, oracle_sources(inst.centres, inst.amps, inst.sigma))
+        Uref, iref = oracle.solve(prob, Fo, "gmres", restart=30, tol=1e-11, maxit=3000)
+        _, ifl = oracle.solve(prob, Fo, "fgmres", restart=30, tol=1e-8, maxit=3000)
+        assert iref.status == "ok" and ifl.status == "ok"
+        out[idx] = (inst, Fo, Uref, ifl.iters)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_matches_oracle(h6, batch_oracle, precision):
+    """FGMRES(30) solves of batch instances, run concurrently with captured
+    step graphs, against the oracle: each solution within 1e-6 (max-abs
+    relative) of the oracle's GMRES solution at tol 1e-11 (the oracle's own
+    tol-1e-8 solutions sit within 1e-7 of it on these instances); the
+    right-hand sides the library assembles equal the oracle's.  Step counts:
+    FP64 plans follow the oracle's FP64 flexible GMRES (tol 1e-8) within one
+    step.  Mixed plans use a complex64 preconditioner, whose rounding (about
+    1e-7 relative per application) moves each restart cycle's stopping point,
+    and with it the next cycle's start: within one step per restart cycle of
+    the oracle's solve."""
+    import math
+    import numpy as np
+    plans, Fs = [], []
+    for idx in BATCH_ORACLE:
+        inst = batch_oracle[idx][0]
+        p = h6.Plan(inst.n, inst.h, inst.k, inst.bc, precision=precision)
+        plans.append(p)
+        Fs.append(p.rhs_gaussians(inst.centres, inst.amps, inst.sigma))
+        p.set_graphs(True)
+    Us = [torch.zeros_like(F) for F in Fs]
+    infos = h6.solve_batch(plans, Fs, Us, method="fgmres", restart=30, tol=1e-8, maxit=600, nstreams=4)
+    for idx, F, U, info in zip(BATCH_ORACLE, Fs, Us, infos):
+        inst, Fo, Uref, oits = batch_oracle[idx]
+        ef = float(np.abs(F.cpu().numpy() - Fo).max() / np.abs(Fo).max())
+        err = float(np.abs(U.cpu().numpy() - Uref).max() / np.abs(Uref).max())
+        slack = 1 if precision == "fp64" else math.ceil(oits / 30)
+        print(f"{precision} instance {idx}: n {inst.n} faces {inst.bc} k {inst.k:.2f}: GPU {info['iters']} "
+              f"steps (oracle FGMRES {oits}, allowed +-{slack}), rel resid {info['rel_resid']:.2e}, "
+              f"solution error {err:.2e}, F difference {ef:.1e}", flush=True)
+        assert ef <= 1e-13
+        assert info["status"] == "ok"
+        assert err <= 1e-6
+        assert abs(info["iters"] - oits) <= slack
+
+
 def test_batch_equals_sequential(h6):
     insts = batch_workload(12, seed=11, sizes=(48, 64))
     plans, Fs = zip(*[make(h6, i) for i in insts])

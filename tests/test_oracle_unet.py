@@ -171,3 +171,57 @@ def test_operator_loss_gradients_finite_differences():
     assert np.isclose(L0, L1, rtol=1e-14)
     for name in g0:
         np.testing.assert_allclose(g1[name][0], g0[name][0], rtol=1e-12, atol=1e-15)
+
+
+def test_round_bf16_matches_torch_conversion():
+    # torch's float32 -> bfloat16 conversion (round to nearest, ties to even)
+    import torch
+    rng = np.random.default_rng(3)
+    a = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [0.0, -0.0, 1.0, -2.5, 3.0e38]]).astype(np.float32)
+    # exact ties: the dropped 16 bits are 0x8000, with an even and an odd kept part
+    ties = (np.array([0x3F800000, 0x3F810000, 0xBF828000 & 0xFFFF0000], dtype=np.uint32) | 0x8000)
+    a = np.concatenate([a, ties.view(np.float32)])
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(unet.round_bf16(a), ref)
+
+
+def test_storage_points_of_the_network():
+    # the storage map is applied at the definition's BF16 storage points: the
+    # input, the ten hidden outputs and the two pools forward; the output
+    # gradient, eleven input gradients, two upsampling gradients and two
+    # skip + pooling sums backward
+    params, r, t = small_problem((6, 5, 4))
+    seen = []
+
+    def record(a):
+        seen.append(np.shape(a))
+        return a
+
+    L0, g0 = unet.loss_and_grads(params, r, 20.0, 0.05, t)
+    L1, g1 = unet.loss_and_grads(params, r, 20.0, 0.05, t, store=record)
+    assert L1 == L0 and all(np.array_equal(g0[k][0], g1[k][0]) for k in g0)
+    n1, n2, n3 = (6, 5, 4), (3, 3, 2), (2, 2, 1)
+    fwd = [(3,) + n1, (16,) + n1, (16,) + n1, (16,) + n2, (32,) + n2, (32,) + n2, (32,) + n3,
+           (64,) + n3, (64,) + n3, (32,) + n2, (32,) + n2, (16,) + n1, (16,) + n1]
+    bwd = [(2,) + n1, (16,) + n1, (16,) + n1, (48,) + n1, (32,) + n2, (32,) + n2, (96,) + n2,
+           (64,) + n3, (64,) + n3, (32,) + n3, (32,) + n2, (32,) + n2, (16,) + n2, (16,) + n1,
+           (16,) + n1, (3,) + n1]
+    assert seen == fwd + bwd
+
+
+def test_bf16_storage_stays_close_to_the_exact_network():
+    # storing in BF16 (unit roundoff 2^-9) at 13 forward points perturbs the
+    # output by at most about sqrt(13) 2^-9 ~ 0.7% (less where the output is
+    # dominated by the biases) and the gradients by about twice that (all
+    # ReLUs active: positive biases)
+    params, r, t = small_problem((8, 7, 6))
+    params = {k: (0.3 * W, np.ones_like(b)) for k, (W, b) in params.items()}
+    c0 = unet.correction(params, r, 20.0, 0.05)
+    c1 = unet.correction(params, r, 20.0, 0.05, store=unet.round_bf16)
+    assert 0.0 < np.linalg.norm(c1 - c0) / np.linalg.norm(c0) < 2e-2
+    _, g0 = unet.loss_and_grads(params, r, 20.0, 0.05, t)
+    _, g1 = unet.loss_and_grads(params, r, 20.0, 0.05, t, store=unet.round_bf16)
+    for k in g0:
+        e = np.linalg.norm(g1[k][0] - g0[k][0]) / np.linalg.norm(g0[k][0])
+        assert 1e-5 < e < 4e-2, (k, e)
