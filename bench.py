@@ -27,8 +27,10 @@ synchronisations.  The process prints one JSON line:
                        the oracle's apply_A and apply_Pinv on the 128^3 and
                        256^3 workloads (one call each),
   extra                the other methods (plain FP64 GMRES and SKS, mixed
-                       FGMRES) timed once each with every solution's relative
-                       difference from the plain FP64 GMRES one, the median
+                       FGMRES): median of five timed solves after a warm-up,
+                       with every solution's relative difference from the
+                       plain FP64 GMRES one (speed-ups are median over
+                       median), the median
                        and minimum of the K timed solves, the per-kernel
                        breakdown (with counter-measured GB/s where a current
                        counter summary is committed), the
@@ -103,10 +105,28 @@ def measured_traffic(workload: str, method: str, kernel: str):
     return rows.get(kernel)
 
 
+def host_description():
+    """The host the oracle runs on: logical CPUs, the ones this process may
+    use, the CPU model and the thread settings of the numerical libraries."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "thread_env": env, "scipy_fft_workers": 1,
+            "note": "NumPy elementwise arithmetic runs on one thread; scipy.fft uses its default of one "
+                    "worker; vector dot products may use BLAS threads"}
+
+
 def run_cpu_baseline(w, method: str, iters: int):
     """The oracle's `method` ("gmres" or "sks") on the same problem, stopped
-    after two iterations, scaled to a whole solve of `iters` iterations (the
-    oracle's per-iteration cost is uniform)."""
+    after two iterations (a bounded sample), scaled to a whole solve of
+    `iters` iterations (the oracle's per-iteration cost is uniform)."""
     import oracle
     from oracle.functions import gaussian_sources
     from paper_1212_1397_amd.workloads import gaussian_sources as wl_sources
@@ -120,11 +140,12 @@ def run_cpu_baseline(w, method: str, iters: int):
     per_iter = dt / max(info.iters, 1)
     what = f"GMRES({w.restart})" if method == "gmres" else "SKS"
     return {"value": round(per_iter * iters, 2), "unit": "s", "cores": 1, "kind": "oracle",
+            "extrapolated": True, "measured_iterations": info.iters, "scaled_to_iterations": iters,
             "sample": f"FP64 oracle {what} on the full {w.name} grid stopped after "
                       f"{info.iters} iterations (including the initial residual): "
                       f"{dt:.1f} s, scaled to the {iters} iterations of the FP64 GPU solve; "
                       f"numpy/scipy on one host thread",
-            "sample_seconds": round(dt, 2)}
+            "sample_seconds": round(dt, 2), "host": host_description()}
 
 
 OPERATOR_WORKLOADS = ("dns-128", "dns-256")
@@ -243,6 +264,8 @@ def main():
     ap.add_argument("--workload", default="dns-256")
     ap.add_argument("--method", default="mixed-sks", choices=sorted(METHODS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-runs", type=int, default=5,
+                    help="timed solves (after one warm-up) of each comparison method; the median is reported")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -359,11 +382,15 @@ def main():
             pl = plan_for(p2)
             one_solve(pl, m2)                     # warm-up (workspace allocation)
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            i2 = one_solve(pl, m2)
-            torch.cuda.synchronize()
-            others[name] = {"s": round(time.perf_counter() - t1, 6), "iters": i2["iters"],
-                            "rel_resid": i2["rel_resid"]}
+            ts = []
+            for _ in range(args.compare_runs):
+                t1 = time.perf_counter()
+                i2 = one_solve(pl, m2)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t1)
+            ts.sort()
+            others[name] = {"s": round(ts[len(ts) // 2], 6), "s_min": round(ts[0], 6), "runs": len(ts),
+                            "iters": i2["iters"], "rel_resid": i2["rel_resid"]}
             solutions[name] = U.clone()
             if name == fp64_name:
                 fp64_iters = i2["iters"]
@@ -377,10 +404,12 @@ def main():
                 (others[name] if name in others else extra.setdefault("headline", {}))["rel_diff_vs_fp64_gmres"] = d
         del solutions, ref
         extra["methods"] = others
+        # speed-ups: medians over medians
+        med = per_step[len(per_step) // 2]
         if "fp64-gmres" in others:
-            extra["speedup_vs_fp64_gmres"] = round(others["fp64-gmres"]["s"] / dt, 3)
+            extra["speedup_vs_fp64_gmres"] = round(others["fp64-gmres"]["s"] / med, 3)
         if fp64_name in others:
-            extra["speedup_vs_fp64_same_solver"] = round(others[fp64_name]["s"] / dt, 3)
+            extra["speedup_vs_fp64_same_solver"] = round(others[fp64_name]["s"] / med, 3)
 
     if not args.no_extra and not args.no_learned and w.name == "dns-256":
         import numpy as np
