@@ -22,7 +22,11 @@
  * x = (Re r / s, Im r / s, kh) with kh = Re(k) h; correction c = s (y0 + i y1).
  * Activations and weights are BF16 on the device, every convolution
  * accumulates in FP32 on the matrix cores; master weights, gradients and the
- * Adam state are FP32.  Training loss of a pair (r, t):
+ * Adam state are FP32.  Values stored in BF16: the input features, every
+ * hidden layer's output after its ReLU and the pooled values (forward); the
+ * output gradient, every convolution's input gradient, the upsampling
+ * gradient and each skip gradient plus pooling gradient (training).  The last
+ * layer's output is kept in FP32.  Training loss of a pair (r, t):
  * L = sum |c(r) - t|^2 / sum |t|^2.
  *
  * Parameters (host FP32, h6net_param_count() values): for each layer in the
@@ -89,6 +93,18 @@ h6_status h6net_gradients_op(h6_net net, h6_plan plan, const void* r, const void
                              double* loss, void* hip_stream);
 h6_status h6net_train_step_op(h6_net net, h6_plan plan, const void* r, const void* t, float lr,
                               double* loss, void* hip_stream);
+
+/* Training pair of the correction from an iterate U of a plain solve of
+ * A U* = F on the plan's grid: the residual r = F - A U (eq. (scheme)'s
+ * operator, FP64) and the target t = (U* - U) - A_p^{-1} r, the part of the
+ * error e = U* - U that the plain preconditioner of eq. (3DAP) misses (A e = r;
+ * A_p^{-1} in the plan's precision, complex64 arithmetic in H6_MIXED plans).
+ * All six vectors are device complex128 on the plan's grid; r and t are
+ * outputs and must not alias each other or the inputs.  Uses the plan's
+ * preconditioner workspace and reduction buffer (do not overlap with other
+ * work on the plan).  Enqueue only. */
+h6_status h6net_training_pair(h6_plan plan, const void* F, const void* Ustar, const void* U, void* r,
+                              void* t, void* hip_stream);
 
 /* Attaches (net != NULL) or detaches (NULL) the network to a plan: flexible
  * GMRES solves of the plan then use z = A_p^{-1} q + c(q) for the Arnoldi

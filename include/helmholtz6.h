@@ -219,6 +219,28 @@ double helmholtz6_psi_order(double r1_h, double r2_h, double r1_gh, double r2_gh
 h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* const* U,
                                  h6_solve_info* infos, h6_status* statuses, int count, int nstreams);
 
+/* The same many independent solves as one captured HIP graph fed by a
+ * device-side work queue (flexible GMRES only, infos[i].method = H6_FGMRES,
+ * one restart length for all; tol and maxit per solve).  Problems are grouped
+ * by grid shape (unknown counts, faces, precision); each group gets up to
+ * `lanes` (1..16) lanes, a lane being a library-owned plan of that shape with
+ * its own workspace, and a queue of its problems in decreasing order of an
+ * estimated cost (unknowns times a kh-based iteration estimate).  A replay of
+ * the graph advances every lane by one restart cycle with the Givens rotations
+ * on the device; at the start of each cycle the lane tests its problem's true
+ * residual on the device, and when the problem is done it copies U out, takes
+ * the next problem from the queue (atomic head) and loads that problem's
+ * right-hand side and wavenumber-dependent tables (stencil weights and z
+ * tridiagonal data of plans[i]) into the lane.  The host replays the graph
+ * until every lane has found its queue empty (one wait per replay).  Each
+ * U[i] starts from zero (its contents are not read), F[i] and plans[i] are
+ * read only; infos[i] receives iters and rel_resid (no history), statuses[i]
+ * the solve's status.  The lanes' workspace is allocated and released inside
+ * the call.  Returns H6_OK when every solve returned a non-negative status,
+ * otherwise the first negative one (message in helmholtz6_last_error(plans[0])). */
+h6_status helmholtz6_solve_batch_queue(h6_plan* plans, const void* const* F, void* const* U,
+                                       h6_solve_info* infos, h6_status* statuses, int count, int lanes);
+
 /* HIP graphs for GMRES / FGMRES solves on the plan, run on a plan-owned
  * stream ordered after hip_stream; built on first use, replayed by later
  * solves, rebuilt when the workspace, restart length or solution vector

@@ -2,7 +2,7 @@
 wavenumber and face pattern) solved as a batch and one by one.  Every step
 runs in the HIP library; this module only orders the calls.
 
-    python -m paper_1212_1397_amd.batch [--count 96] [--streams 4] [--no-graphs]
+    python -m paper_1212_1397_amd.batch [--count 96] [--streams 4] [--no-graphs] [--lanes 2]
 """
 from __future__ import annotations
 
@@ -18,9 +18,12 @@ from .workloads import batch_workload
 
 
 def run(count: int = 96, streams: int = 4, graphs=True, tune: bool = True, seed: int = 4,
-        log=None):
-    """Seconds for the sequential plain solves and for the batched solves
-    (mixed FGMRES(30) to 1e-8), iteration counts and agreement."""
+        log=None, lanes: int = 2):
+    """Seconds for the sequential plain solves, for the batched solves on
+    concurrent streams and for the queued form (one captured graph, a
+    device-side queue per grid shape, `lanes` lanes per shape; lane set-up,
+    capture and release included), all mixed FGMRES(30) to 1e-8, with
+    iteration counts and agreement."""
     insts = batch_workload(count, seed)
     plans, Fs = [], []
     for inst in insts:
@@ -58,13 +61,27 @@ def run(count: int = 96, streams: int = 4, graphs=True, tune: bool = True, seed:
     t_batch = time.perf_counter() - t0
     worst = max(float(torch.linalg.norm(U - s[0]) / torch.linalg.norm(s[0])) for U, s in zip(Us, seq))
     its = [i["iters"] for i in infos]
+    # queued form: one graph, device-side queue per grid shape (from U = 0)
+    Uq = [torch.zeros_like(F) for F in Fs]
+    h6.solve_batch_queue(plans, Fs, Uq, restart=30, tol=1e-8, maxit=600, lanes=lanes)    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qinfos = h6.solve_batch_queue(plans, Fs, Uq, restart=30, tol=1e-8, maxit=600, lanes=lanes)
+    torch.cuda.synchronize()
+    t_queue = time.perf_counter() - t0
+    qworst = max(float(torch.linalg.norm(U - s[0]) / torch.linalg.norm(s[0])) for U, s in zip(Uq, seq))
+    qits = [i["iters"] for i in qinfos]
     res = {"count": count, "streams": streams, "graphs": graphs, "autotuned": tune,
            "unknowns": int(sum(p.dims[0] * p.dims[1] * p.dims[2] for p in plans)),
            "sequential_s": round(t_seq, 4), "batched_s": round(t_batch, 4),
            "speedup": round(t_seq / t_batch, 3), "solves_per_s": round(count / t_batch, 2),
            "iters_min": min(its), "iters_max": max(its), "iters_total": sum(its),
            "all_converged": all(i["status"] == "ok" for i in infos),
-           "max_rel_diff_vs_sequential": worst}
+           "max_rel_diff_vs_sequential": worst,
+           "queued": {"lanes_per_shape": lanes, "s": round(t_queue, 4),
+                      "speedup_vs_sequential": round(t_seq / t_queue, 3), "solves_per_s": round(count / t_queue, 2),
+                      "iters_total": sum(qits), "all_converged": all(i["status"] == "ok" for i in qinfos),
+                      "max_rel_diff_vs_sequential": qworst}}
     for p in plans:
         p.close()
     return res
@@ -78,9 +95,10 @@ def main(argv=None):
     ap.add_argument("--cycle-graphs", action="store_true",
                     help="one graph per restart cycle (device Givens) instead of one per step")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--lanes", type=int, default=2, help="lanes per grid shape of the queued form")
     a = ap.parse_args(argv)
     graphs = False if a.no_graphs else ("cycle" if a.cycle_graphs else True)
-    print(json.dumps(run(a.count, a.streams, graphs, not a.no_tune)), flush=True)
+    print(json.dumps(run(a.count, a.streams, graphs, not a.no_tune, lanes=a.lanes)), flush=True)
 
 
 if __name__ == "__main__":

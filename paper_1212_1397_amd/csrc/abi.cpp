@@ -295,6 +295,7 @@ void free_plan(h6_plan P) {
   (void)hipFree(P->d_lambda_y);
   for (auto& a : P->ax) (void)hipFree(a.wmat);
   (void)hipFree(P->d_cstart);
+  (void)hipFree(P->d_zparams);
   for (void* w : P->w_pc) (void)hipFree(w);
   (void)hipFree(P->V);
   (void)hipFree(P->Z);
@@ -405,6 +406,12 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   hipError_t e = hipSuccess;
   std::vector<StencilTable> st(1, P->stencil);
   if (e == hipSuccess) e = upload(&P->d_stencil, st, s);
+  {
+    const ZEnds& z = P->zends;
+    std::vector<double> zp = {P->kappa.real(), P->kappa.imag(), z.b0_re, z.b0_im, z.s0, z.bl_re, z.bl_im, z.sl};
+    static_assert(kZParams == 8, "z-solver parameter block");
+    if (e == hipSuccess) e = upload(&P->d_zparams, zp, s);
+  }
   if (e == hipSuccess) e = upload(&P->d_lambda_x, lx, s);
   if (e == hipSuccess) e = upload(&P->d_lambda_y, ly, s);
   for (int a = 0; a < 2 && e == hipSuccess; ++a)
@@ -891,6 +898,25 @@ h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* con
   for (int i = 0; i < count; ++i)
     if (statuses[i] < 0) return statuses[i];
   return H6_OK;
+}
+
+h6_status helmholtz6_solve_batch_queue(h6_plan* plans, const void* const* F, void* const* U,
+                                       h6_solve_info* infos, h6_status* statuses, int count, int lanes) {
+  if (!plans || !F || !U || !infos || !statuses || count < 0 || lanes < 1 || lanes > 16) return H6_ERR_ARG;
+  if (count == 0) return H6_OK;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) return H6_ERR_ARG;
+  std::string err;
+  h6_status st;
+  try {
+    st = solve_queue(plans, reinterpret_cast<const double2* const*>(F), reinterpret_cast<double2* const*>(U),
+                     infos, statuses, count, lanes, err);
+  } catch (...) {
+    st = H6_ERR_ALLOC;
+    err = "exception in the queued batch";
+  }
+  if (st < 0) plans[0]->last_error = err;
+  return st;
 }
 
 h6_status helmholtz6_set_graphs(h6_plan P, int enable) {

@@ -110,6 +110,7 @@ struct h6_plan_s {
   double* d_lambda_x = nullptr;     // transverse eigenvalues per mode
   double* d_lambda_y = nullptr;
   h6::ZEnds zends{};                // end rows of the z tridiagonal (scaled form)
+  double* d_zparams = nullptr;      // device copy for the z solver: kappa (re, im), then zends (kZParams doubles)
   void* d_cstart = nullptr;         // Thomas c' entering each z segment: [z_segments(n'z)][n'x n'y], complex
                                     // (double2, or float2 in mixed plans)
 
@@ -155,6 +156,7 @@ struct h6_plan_s {
 namespace h6 {
 
 constexpr int kRedBlocks = 1024;   // blocks of the grid-stride reductions
+constexpr int kZParams = 8;        // doubles of h6_plan_s::d_zparams
 constexpr int kMaxPartials = 1 << 20;
 constexpr int kScal = 4096;        // device scalar slots (double2)
 constexpr int kGramMax = 16;       // Gram row entries formed by launch_update_gram
@@ -301,6 +303,57 @@ h6_status spectrum_bounds(h6_plan P);
 // e = c1 e + c2 t; U += e (Chebyshev step)
 hipError_t launch_cheb_update(double2* e, const double2* t, double2* U, double c1, double c2, size_t n,
                               hipStream_t s);
+
+// Queued batch (queue.hip, solve.cpp): problems of one grid shape in a
+// device-side queue (longest first), lanes that take the next problem when
+// theirs is done.
+struct QueueEntry {            // one problem (device memory, queue order)
+  const double2* F;            // caller's right-hand side and solution
+  double2* U;
+  const StencilTable* stencil; // the problem's own plan tables (wavenumber-dependent)
+  const void* cstart;
+  const double* zparams;
+  double tol;
+  int maxit;
+  int result;                  // index of the problem in the caller's arrays
+};
+struct QueueResult {           // host-mapped, one per problem
+  int iters;
+  int status;
+  double rel_resid;
+};
+struct QueueLane {             // device memory, one per lane
+  int cur;                     // queue position of the lane's problem, -1 none
+  int out;                     // problem whose U is copied out this replay, -1 none
+  int pend;                    // problem finished at a cycle start, copied out next replay
+  int fresh;                   // the lane took a new problem this replay
+  int idle;                    // the queue was empty when the lane asked
+  int skip_refill, skip_fresh; // kernel skip flags (1 = skip)
+  int iters;                   // steps done on the lane's problem
+  double normF;
+  int* idle_mirror;            // host-mapped copy of idle
+};
+struct LaneRefill {
+  QueueLane* lane;
+  const QueueEntry* q;
+  double2 *F, *U, *V0;         // the lane plan's right-hand side, solution and first basis vector
+  StencilTable* stencil;       // the lane plan's tables
+  void* cstart;
+  double* zparams;
+  size_t N;
+  size_t cstart_words;         // 8-byte words of the segment-start table
+  double* partials;            // kRedBlocks |F|^2 partials
+};
+hipError_t launch_lane_check(QueueLane* lane, const QueueEntry* q, int* head, int count, const double* rnorm2,
+                             QueueResult* res, hipStream_t s);
+hipError_t launch_lane_refill(const LaneRefill& a, hipStream_t s);
+hipError_t launch_lane_cycle(QueueLane* lane, const QueueEntry* q, QueueResult* res, const double* rnorm2,
+                             double* prm, int* stop, int* jdone, int m, hipStream_t s);
+hipError_t launch_lane_count(QueueLane* lane, const int* jdone, hipStream_t s);
+// sum of nparts partials into *out; skipped while *skip != 0
+hipError_t launch_reduce_sum_skip(const double* partials, int nparts, double* out, const int* skip, hipStream_t s);
+h6_status solve_queue(h6_plan* plans, const double2* const* F, double2* const* U, h6_solve_info* infos,
+                      h6_status* statuses, int count, int lanes, std::string& err);
 
 void release_graphs(h6_plan P);
 h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s);

@@ -432,6 +432,12 @@ hipError_t launch_norm2(const double2* a, size_t n, double* partials, double* ou
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_sum_skip(const double* partials, int nparts, double* out, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(1), dim3(kThreads), 0, s, partials, nparts, out, skip,
+                     static_cast<double*>(nullptr));
+  return hipGetLastError();
+}
+
 hipError_t launch_diff_norm2(const double2* a, const double2* b, size_t n, double* partials, double* out,
                              hipStream_t s) {
   hipLaunchKernelGGL(diff_norm2_kernel, dim3(kRedBlocks), dim3(kThreads), 0, s, a, b, n, partials);

@@ -122,9 +122,12 @@ template <typename R, int kLanes, int kSegs, int kSmax>
 __global__ __launch_bounds__(kLanes * kSegs) void tridiag_z_kernel(
     const typename C2<R>::T* __restrict__ in, typename C2<R>::T* __restrict__ out,
     const typename C2<R>::T* __restrict__ cstart, const double* __restrict__ lx,
-    const double* __restrict__ ly, double kap_re, double kap_im, ZEnds ends, int nx, int ny, int nz,
+    const double* __restrict__ ly, const double* __restrict__ zp, int nx, int ny, int nz,
     const int* __restrict__ skip) {
   if (skip && *skip) return;
+  // kappa and the scaled end rows (ZEnds), from device memory (kZParams doubles)
+  const double kap_re = zp[0], kap_im = zp[1];
+  const ZEnds ends{zp[2], zp[3], zp[4], zp[5], zp[6], zp[7]};
   using T2 = typename C2<R>::T;
   __shared__ T2 sh[2][kSegs][kLanes];
   const int tid = threadIdx.x;
@@ -245,11 +248,10 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
   {
-    const double kr = P->kappa.real(), ki = P->kappa.imag();
     const T2* cst = static_cast<const T2*>(P->d_cstart);
     auto go = [&](auto kern, int lanes) {
       hipLaunchKernelGGL(kern, dim3((nx * ny + lanes - 1) / lanes), dim3(512), 0, s, w1, w0, cst,
-                         P->d_lambda_x, P->d_lambda_y, kr, ki, P->zends, nx, ny, nz, P->skip);
+                         P->d_lambda_x, P->d_lambda_y, P->d_zparams, nx, ny, nz, P->skip);
     };
     if (z_segments(nz, sizeof(R) == 4) == 16) {
       if (nz <= 16 * 5) go(tridiag_z_kernel<R, 32, 16, 5>, 32);

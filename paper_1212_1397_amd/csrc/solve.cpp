@@ -23,7 +23,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "h6_internal.h"
@@ -180,6 +182,58 @@ h6_status upload_coefs(Ctx& c, int off, const std::vector<cplx>& v, int count) {
   return H6_OK;
 }
 
+// The kernels of one restart cycle of GMRES(m) / FGMRES(m) on c.s, with the
+// Givens rotations on the device: steps j = 0..m-1 (preconditioner, A, MGS,
+// Givens update), each returning at once while gs.stop is set, then
+// y = R^{-1} g over the steps done and U += Z y (U += A_p^{-1} V y).  The
+// cycle starts from the unnormalised residual in the first basis slot and
+// |r|^2 in the kNorm slot, and reads (steps allowed, ||F||, tol) from kPrm.
+hipError_t enqueue_cycle(Ctx& c, double2* U, int m, bool flex, bool mixed, const GivensState& gs) {
+  h6_plan P = c.P;
+  const size_t N = c.N;
+  double* prm = c.dev + kPrm;
+  hipError_t e = hipSuccess;
+  P->skip = gs.stop;
+  const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
+  double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
+  for (int j = 0; j < m && e == hipSuccess; ++j) {
+    const double2* qj = P->V + size_t(j) * N;
+    double2* w = P->V + size_t(j + 1) * N;
+    if (mixed) {
+      float2* z = static_cast<float2*>(P->Z) + size_t(j) * N;
+      e = launch_pinv_f32out(P, qj, z, c.s, PINV_ALL);
+      if (e == hipSuccess) e = launch_stencil_f32in(P, z, w, c.s);
+    } else {
+      double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
+      e = launch_pinv(P, qj, z, c.s, PINV_ALL);
+      if (e == hipSuccess) e = launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s);
+    }
+    if (e == hipSuccess) e = launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s, gs.stop);
+    if (e == hipSuccess && j > kGramMax)
+      e = launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, qj, N, P->partials, c.dev + kGram2,
+                            c.s, gs.stop);
+    if (e == hipSuccess)
+      e = launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu, P->d_gram, P->gram_dim,
+                          dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s, gs.stop);
+    if (e == hipSuccess) e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s, gs.stop);
+    if (e == hipSuccess) e = launch_givens_step(j, c.dev + kNorm, c.dev + kNu, dhcol, gs, m, prm, c.s);
+  }
+  P->skip = nullptr;
+  double2* dy = reinterpret_cast<double2*>(c.dev + kY);
+  if (e == hipSuccess) e = launch_lsq_solve(m, gs, c.dev + kNu, dy, c.s);
+  if (e == hipSuccess) {
+    if (flex && mixed)
+      e = launch_multi_axpy_f32(U, static_cast<float2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
+    else if (flex)
+      e = launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
+    else {
+      e = launch_multi_axpy(P->t, P->V, dy, m, N, 0, c.s, gs.jdone);
+      if (e == hipSuccess) e = launch_pinv_acc(P, P->t, U, c.s);
+    }
+  }
+  return e;
+}
+
 // GMRES / FGMRES with whole restart cycles as one captured HIP graph: every
 // step's kernels (preconditioner, A, MGS) are followed by a one-thread
 // Givens update of the least-squares problem on the device; when it meets
@@ -204,46 +258,7 @@ h6_status gmres_cycles(Ctx& c, const double2* F, double2* U, h6_solve_info* info
   if (!P->cycle_graph) {
     hipGraph_t graph = nullptr;
     H6_TRY_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeRelaxed));
-    hipError_t e = hipSuccess;
-    P->skip = gs.stop;
-    const double2* dcoef = reinterpret_cast<const double2*>(c.dev + kCoef);
-    double2* dhcol = reinterpret_cast<double2*>(c.dev + kHcol);
-    for (int j = 0; j < m && e == hipSuccess; ++j) {
-      const double2* qj = P->V + size_t(j) * N;
-      double2* w = P->V + size_t(j + 1) * N;
-      if (mixed) {
-        float2* z = static_cast<float2*>(P->Z) + size_t(j) * N;
-        e = launch_pinv_f32out(P, qj, z, c.s, PINV_ALL);
-        if (e == hipSuccess) e = launch_stencil_f32in(P, z, w, c.s);
-      } else {
-        double2* z = flex ? static_cast<double2*>(P->Z) + size_t(j) * N : P->t;
-        e = launch_pinv(P, qj, z, c.s, PINV_ALL);
-        if (e == hipSuccess) e = launch_stencil(P, z, w, nullptr, nullptr, nullptr, c.s);
-      }
-      if (e == hipSuccess) e = launch_block_dots(P->V, j + 1, w, N, P->partials, c.dev + kDots, c.s, gs.stop);
-      if (e == hipSuccess && j > kGramMax)
-        e = launch_block_dots(P->V + size_t(kGramMax) * N, j - kGramMax, qj, N, P->partials, c.dev + kGram2,
-                              c.s, gs.stop);
-      if (e == hipSuccess)
-        e = launch_mgs_coef(j, c.dev + kDots, c.dev + kNorm, c.dev + kGram2, c.dev + kNu, P->d_gram, P->gram_dim,
-                            dhcol, reinterpret_cast<double2*>(c.dev + kCoef), c.s, gs.stop);
-      if (e == hipSuccess)
-        e = launch_update_gram(w, P->V, dcoef, j + 1, N, P->partials, c.dev + kNorm, c.s, gs.stop);
-      if (e == hipSuccess) e = launch_givens_step(j, c.dev + kNorm, c.dev + kNu, dhcol, gs, m, prm, c.s);
-    }
-    P->skip = nullptr;
-    double2* dy = reinterpret_cast<double2*>(c.dev + kY);
-    if (e == hipSuccess) e = launch_lsq_solve(m, gs, c.dev + kNu, dy, c.s);
-    if (e == hipSuccess) {
-      if (flex && mixed)
-        e = launch_multi_axpy_f32(U, static_cast<float2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
-      else if (flex)
-        e = launch_multi_axpy(U, static_cast<double2*>(P->Z), dy, m, N, 1, c.s, gs.jdone);
-      else {
-        e = launch_multi_axpy(P->t, P->V, dy, m, N, 0, c.s, gs.jdone);
-        if (e == hipSuccess) e = launch_pinv_acc(P, P->t, U, c.s);
-      }
-    }
+    hipError_t e = enqueue_cycle(c, U, m, flex, mixed, gs);
     const hipError_t e2 = hipStreamEndCapture(c.s, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&P->cycle_graph, graph, nullptr, nullptr, 0);
@@ -673,6 +688,239 @@ h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info
   if (normF == 0.0) return zero_solution(c, U, info);
   if (info->method == H6_CHEBYSHEV) return chebyshev(c, F, U, info, normF);
   return gmres(c, F, U, info, normF);
+}
+
+// Queued batch: problems grouped by grid shape (dims, faces, precision); per
+// group a few lanes, each a plan of that shape with its own workspace and
+// right-hand side / solution slots, and a device-side queue of the group's
+// problems in decreasing order of estimated cost.  One captured graph holds
+// every lane of every group (each lane forked onto its own stream); a replay
+// advances each lane by one restart cycle, and the lanes themselves decide
+// on the device when their problem is done and which problem comes next
+// (queue.hip).  The host replays the graph until every lane reports an
+// empty queue.
+h6_status solve_queue(h6_plan* plans, const double2* const* F, double2* const* U, h6_solve_info* infos,
+                      h6_status* statuses, int count, int lanes, std::string& err) {
+  const int m = infos[0].restart;
+  if (m < 1 || m > 256) { err = "restart must be in 1..256"; return H6_ERR_ARG; }
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !F[i] || !U[i] || F[i] == U[i]) { err = "null or aliased plan / vector"; return H6_ERR_ARG; }
+    const h6_solve_info& in = infos[i];
+    if (in.method != H6_FGMRES || in.restart != m || in.maxit < 1 || !(in.tol >= 0.0)) {
+      err = "the queued batch runs flexible GMRES with one restart length, maxit >= 1 and tol >= 0";
+      return H6_ERR_ARG;
+    }
+  }
+  // groups of one grid shape, each in decreasing order of estimated cost
+  using Key = std::tuple<int, int, int, int, int, int, int, int, int, int>;
+  std::map<Key, std::vector<int>> groups;
+  std::vector<double> cost(count);
+  for (int i = 0; i < count; ++i) {
+    const h6_plan P = plans[i];
+    const double kh = std::abs(P->k) * P->p.h;
+    cost[i] = double(P->N) * (1.0 + 40.0 * kh * kh);
+    groups[Key{P->dims[0], P->dims[1], P->dims[2], P->p.bc[0], P->p.bc[2], P->p.bc[4], P->p.bc[5],
+               P->p.precision, P->xmirror, P->ymirror}].push_back(i);
+  }
+  struct Lane {
+    h6_plan P = nullptr;
+    double2* F = nullptr;
+    double2* U = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t join = nullptr;
+    int group = 0;
+  };
+  std::vector<Lane> L;
+  std::vector<int> goff, gcount;        // queue offset and size per group
+  std::vector<QueueEntry> entries;
+  hipStream_t s0 = nullptr;
+  hipEvent_t fork = nullptr;
+  QueueEntry* d_q = nullptr;
+  int* d_head = nullptr;
+  QueueLane* d_lanes = nullptr;
+  QueueResult* h_res = nullptr;
+  QueueResult* d_res = nullptr;
+  int* h_idle = nullptr;
+  int* d_idle = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  h6_status st = H6_OK;
+  auto fail = [&](const std::string& what, hipError_t e) {
+    err = what + ": " + hipGetErrorString(e);
+    st = e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
+  };
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (Lane& l : L) {
+      if (l.join) (void)hipEventDestroy(l.join);
+      if (l.s) (void)hipStreamDestroy(l.s);
+      (void)hipFree(l.F);
+      (void)hipFree(l.U);
+      helmholtz6_destroy(l.P);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (s0) (void)hipStreamDestroy(s0);
+    (void)hipFree(d_q);
+    (void)hipFree(d_head);
+    (void)hipFree(d_lanes);
+    if (h_res) (void)hipHostFree(h_res);
+    if (h_idle) (void)hipHostFree(h_idle);
+  };
+  // queue entries (group by group) and lanes
+  for (auto& kv : groups) {
+    std::vector<int>& ids = kv.second;
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    goff.push_back(int(entries.size()));
+    gcount.push_back(int(ids.size()));
+    for (int i : ids) {
+      const h6_plan P = plans[i];
+      entries.push_back(QueueEntry{F[i], U[i], P->d_stencil, P->d_cstart, P->d_zparams, infos[i].tol,
+                                   infos[i].maxit, i});
+    }
+    const int nl = std::min(lanes, int(ids.size()));
+    for (int l = 0; l < nl; ++l) {
+      Lane ln;
+      ln.group = int(goff.size()) - 1;
+      const h6_plan src = plans[ids[0]];
+      h6_status s1 = helmholtz6_setup(&src->p, nullptr, &ln.P);
+      if (s1 != H6_OK) {
+        err = "lane plan setup failed";
+        cleanup();
+        return s1;
+      }
+      L.push_back(ln);
+      Lane& lr = L.back();
+      // the kernel variants chosen for the group's plans
+      lr.P->stencil_tz = src->stencil_tz;
+      for (int a = 0; a < 2; ++a)
+        if (lr.P->ax[a].fast == src->ax[a].fast) lr.P->ax[a].lines = src->ax[a].lines;
+      lr.P->use_graphs = 2;                           // device least-squares state
+      s1 = ensure(lr.P, H6_FGMRES, m);
+      if (s1 != H6_OK) {
+        err = lr.P->last_error;
+        cleanup();
+        return s1;
+      }
+      const size_t vb = lr.P->N * sizeof(double2);
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&lr.F), vb);
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&lr.U), vb);
+      if (e == hipSuccess) e = hipMemset(lr.F, 0, vb);
+      if (e == hipSuccess) e = hipMemset(lr.U, 0, vb);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&lr.s, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&lr.join, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        fail("lane allocation", e);
+        cleanup();
+        return st;
+      }
+    }
+  }
+  const int nl = int(L.size());
+  {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_q), sizeof(QueueEntry) * entries.size());
+    if (e == hipSuccess) e = hipMemcpy(d_q, entries.data(), sizeof(QueueEntry) * entries.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_head), sizeof(int) * goff.size());
+    if (e == hipSuccess) e = hipMemset(d_head, 0, sizeof(int) * goff.size());
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h_res), sizeof(QueueResult) * count,
+                                           hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d_res), h_res, 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h_idle), sizeof(int) * nl,
+                                           hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d_idle), h_idle, 0);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_lanes), sizeof(QueueLane) * nl);
+    if (e == hipSuccess) {
+      for (int i = 0; i < count; ++i) h_res[i] = QueueResult{0, int(H6_ERR_HIP), 0.0};
+      std::vector<QueueLane> init(nl);
+      for (int l = 0; l < nl; ++l) {
+        h_idle[l] = 0;
+        init[l] = QueueLane{-1, -1, -1, 0, 0, 1, 1, 0, 0.0, d_idle + l};
+      }
+      e = hipMemcpy(d_lanes, init.data(), sizeof(QueueLane) * nl, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s0, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      fail("queue set-up", e);
+      cleanup();
+      return st;
+    }
+  }
+  // capture: every lane forked from s0 onto its own stream
+  {
+    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) e = hipEventRecord(fork, s0);
+    for (int l = 0; l < nl && e == hipSuccess; ++l) {
+      Lane& ln = L[l];
+      h6_plan P = ln.P;
+      QueueLane* lane = d_lanes + l;
+      const QueueEntry* q = d_q + goff[ln.group];
+      const int qn = gcount[ln.group];
+      Ctx c{P, ln.s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
+      const GivensState gs = givens_state(P, m);
+      const bool mixed = P->p.precision == H6_MIXED;
+      e = hipStreamWaitEvent(ln.s, fork, 0);
+      int nparts = 0;
+      P->skip = &lane->idle;
+      if (e == hipSuccess) e = launch_stencil(P, ln.U, P->V, ln.F, P->partials, &nparts, ln.s);
+      P->skip = nullptr;
+      if (e == hipSuccess) e = launch_reduce_sum_skip(P->partials, nparts, c.dev + kNorm, &lane->idle, ln.s);
+      if (e == hipSuccess) e = launch_lane_check(lane, q, d_head + ln.group, qn, c.dev + kNorm, d_res, ln.s);
+      if (e == hipSuccess) {
+        const size_t cst_bytes = size_t(z_segments(P->dims[2], mixed)) * P->dims[0] * P->dims[1] *
+                                 (mixed ? sizeof(float2) : sizeof(double2));
+        const LaneRefill a{lane, q, ln.F, ln.U, P->V, P->d_stencil, P->d_cstart, P->d_zparams, P->N,
+                           cst_bytes / 8, P->partials};
+        e = launch_lane_refill(a, ln.s);
+      }
+      if (e == hipSuccess) e = launch_reduce_sum_skip(P->partials, kRedBlocks, c.dev + kNorm, &lane->skip_fresh, ln.s);
+      if (e == hipSuccess)
+        e = launch_lane_cycle(lane, q, d_res, c.dev + kNorm, c.dev + kPrm, gs.stop, gs.jdone, m, ln.s);
+      if (e == hipSuccess) e = enqueue_cycle(c, ln.U, m, true, mixed, gs);
+      if (e == hipSuccess) e = launch_lane_count(lane, gs.jdone, ln.s);
+      if (e == hipSuccess) e = hipEventRecord(ln.join, ln.s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s0, ln.join, 0);
+    }
+    const hipError_t e2 = hipStreamEndCapture(s0, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      fail("queue graph capture", e);
+      cleanup();
+      return st;
+    }
+  }
+  // replays until every lane found its queue empty (bounded by the step budgets)
+  long long bound = 2;
+  for (int i = 0; i < count; ++i) bound += (infos[i].maxit + m - 1) / m + 2;
+  bool drained = false;
+  for (long long rep = 0; rep < bound; ++rep) {
+    hipError_t e = hipGraphLaunch(exec, s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    if (e != hipSuccess) {
+      fail("queue graph replay", e);
+      cleanup();
+      return st;
+    }
+    drained = true;
+    for (int l = 0; l < nl; ++l) drained = drained && h_idle[l] != 0;
+    if (drained) break;
+  }
+  if (!drained) {
+    err = "internal: the queued batch did not drain within its step budget";
+    cleanup();
+    return H6_ERR_HIP;
+  }
+  for (int i = 0; i < count; ++i) {
+    statuses[i] = h6_status(h_res[i].status);
+    infos[i].iters = h_res[i].iters;
+    infos[i].rel_resid = h_res[i].rel_resid;
+    infos[i].history_len = 0;
+    if (statuses[i] < 0 && st == H6_OK) st = statuses[i];
+  }
+  cleanup();
+  return st;
 }
 
 }  // namespace h6

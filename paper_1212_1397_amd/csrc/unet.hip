@@ -531,6 +531,15 @@ __global__ void sub_kernel(const double2* __restrict__ a, const double2* __restr
   b[v] = make_double2(x.x - y.x, x.y - y.y);
 }
 
+// training target t = (U* - U) - t, where t holds A_p^{-1} r on entry
+__global__ void pair_target_kernel(const double2* __restrict__ us, const double2* __restrict__ u,
+                                   double2* __restrict__ t, long long P) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= P) return;
+  const double2 a = us[v], b = u[v], c = t[v];
+  t[v] = make_double2((a.x - b.x) - c.x, (a.y - b.y) - c.y);
+}
+
 // b = conj(a)
 __global__ void conj_kernel(const double2* __restrict__ a, double2* __restrict__ b, long long P) {
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1008,6 +1017,24 @@ h6_status h6net_train_step_op(h6_net N, h6_plan plan, const void* r, const void*
       return H6_ERR_HIP;
     *loss = N->h_scal[1] > 0.0 ? N->h_scal[2] / N->h_scal[1] : 0.0;
   }
+  return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
+}
+
+h6_status h6net_training_pair(h6_plan plan, const void* F, const void* Ustar, const void* U, void* r, void* t,
+                              void* hip_stream) {
+  if (!plan || !F || !Ustar || !U || !r || !t || r == t) return H6_ERR_ARG;
+  for (const void* in : {F, Ustar, U})
+    if (in == r || in == t) return H6_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const long long P = (long long)plan->N;
+  double2* rr = static_cast<double2*>(r);
+  double2* tt = static_cast<double2*>(t);
+  if (launch_stencil(plan, static_cast<const double2*>(U), rr, static_cast<const double2*>(F), plan->partials,
+                     nullptr, s) != hipSuccess ||
+      launch_pinv(plan, rr, tt, s) != hipSuccess)
+    return H6_ERR_HIP;
+  hipLaunchKernelGGL(pair_target_kernel, dim3(nblk(P)), dim3(256), 0, s, static_cast<const double2*>(Ustar),
+                     static_cast<const double2*>(U), tt, P);
   return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
 }
 

@@ -29,11 +29,12 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
-            "helmholtz6_solve_batch", "helmholtz6_set_graphs", "helmholtz6_autotune",
+            "helmholtz6_solve_batch", "helmholtz6_solve_batch_queue", "helmholtz6_set_graphs", "helmholtz6_autotune",
             "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z", "helmholtz6_rhs_neumann")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "h6net_gradients_op",
-                "h6net_train_step_op", "helmholtz6_attach_net", "helmholtz6_learned_steps", "h6net_destroy")
+                "h6net_train_step_op", "h6net_training_pair", "helmholtz6_attach_net",
+                "helmholtz6_learned_steps", "h6net_destroy")
 # layers of the correction network: (name, Cin, Cout), in parameter order
 NET_LAYERS = (("e1a", 3, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32), ("b3a", 32, 64),
               ("b3b", 64, 64), ("d2a", 96, 32), ("d2b", 32, 32), ("d1a", 48, 16), ("d1b", 16, 16),
@@ -84,6 +85,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                            ctypes.POINTER(H6SolveInfo), ctypes.POINTER(ip), ip, ip]
     lib.helmholtz6_solve_batch.restype = ctypes.c_int
+    lib.helmholtz6_solve_batch_queue.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                                 ctypes.POINTER(H6SolveInfo), ctypes.POINTER(ip), ip, ip]
+    lib.helmholtz6_solve_batch_queue.restype = ctypes.c_int
     lib.helmholtz6_set_graphs.argtypes = [vp, ip]
     lib.helmholtz6_set_graphs.restype = ctypes.c_int
     lib.helmholtz6_autotune.argtypes = [vp, ctypes.c_char_p, vp]
@@ -110,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.h6net_train_step.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_float, dp, vp]
     lib.h6net_gradients_op.argtypes = [vp, vp, vp, vp, fp, dp, vp]
     lib.h6net_train_step_op.argtypes = [vp, vp, vp, vp, ctypes.c_float, dp, vp]
+    lib.h6net_training_pair.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.h6net_training_pair.restype = ctypes.c_int
     lib.helmholtz6_attach_net.argtypes = [vp, vp]
     lib.helmholtz6_learned_steps.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.h6net_destroy.argtypes = [vp]
@@ -300,6 +306,15 @@ class Plan:
         self._check(_lib.helmholtz6_spectrum_bounds(self._plan, ctypes.byref(lo), ctypes.byref(hi)))
         return lo.value, hi.value
 
+    def training_pair(self, F, Ustar, U, r=None, t=None, stream=None):
+        """(r, t): r = F - A U and t = (Ustar - U) - A_p^{-1} r (h6net_training_pair)."""
+        r = self.empty() if r is None else r
+        t = self.empty() if t is None else t
+        st = _lib.h6net_training_pair(self._plan, self._vec(F, "F"), self._vec(Ustar, "Ustar"), self._vec(U, "U"),
+                                      self._vec(r, "r"), self._vec(t, "t"), _stream_handle(stream))
+        self._check(st)
+        return r, t
+
     def attach_net(self, net):
         """Use the learned correction of `net` in flexible GMRES solves (None detaches)."""
         self._net = net
@@ -480,6 +495,29 @@ def solve_batch(plans, Fs, Us, method="fgmres", restart=30, maxit=1000, tol=1e-8
     names = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}
     return [dict(status=names[sts[i]], iters=infos[i].iters, rel_resid=infos[i].rel_resid,
                  history=list(hists[i][:infos[i].history_len])) for i in range(n)]
+
+
+def solve_batch_queue(plans, Fs, Us, restart=30, maxit=1000, tol=1e-8, lanes=2):
+    """Flexible GMRES(restart) solves of plans[i] x = Fs[i] into Us[i] (from zero) as one
+    captured graph fed by a device-side queue per grid shape (helmholtz6_solve_batch_queue),
+    `lanes` lanes per shape.  Returns a list of info dicts (no history)."""
+    n = len(plans)
+    if not (len(Fs) == len(Us) == n):
+        raise ValueError("plans, Fs and Us must have the same length")
+    P = (ctypes.c_void_p * n)(*[p._plan.value for p in plans])
+    Fp = (ctypes.c_void_p * n)(*[p._vec(F, "F").value for p, F in zip(plans, Fs)])
+    Up = (ctypes.c_void_p * n)(*[p._vec(U, "U").value for p, U in zip(plans, Us)])
+    infos = (H6SolveInfo * n)()
+    for i in range(n):
+        infos[i] = H6SolveInfo(METHODS["fgmres"], int(restart), int(maxit), float(tol), 0, 0.0, None, 0, 1)
+    sts = (ctypes.c_int * n)()
+    torch.cuda.synchronize()              # inputs ready before the library's streams start
+    st = _lib.helmholtz6_solve_batch_queue(P, Fp, Up, infos, sts, n, int(lanes))
+    if st < 0:
+        raise H6Error(st, _lib.helmholtz6_last_error(plans[0]._plan).decode() or "queued batch failed")
+    names = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}
+    return [dict(status=names[sts[i]], iters=infos[i].iters, rel_resid=infos[i].rel_resid, history=[])
+            for i in range(n)]
 
 
 def psi_order(r1_h: float, r2_h: float, r1_gh: float, r2_gh: float, gamma: float) -> float:

@@ -16,6 +16,7 @@ solver accepts or rejects a correction.
     python -m paper_1212_1397_amd.learned train --out weights.npz [--n 128] [--problems 16]
                                               [--iters 8] [--steps 1500] [--seed 4]
                                               [--loss plain|operator] [--init weights.npz]
+                                              [--stream --steps-per-problem 8 --buffer 8]
     python -m paper_1212_1397_amd.learned eval  --weights weights.npz [--workload dns-256]
     python -m paper_1212_1397_amd.learned speed [--workload dns-256]
 """
@@ -44,29 +45,74 @@ def problem(n: int, seed: int):
     return kr * (1 + 0.01j), random_sources(nsrc, seed + 1000, h), h
 
 
+def problem_pairs(n: int, seed: int, iters: int):
+    """One seeded problem: its plan, k, h, the reference solve's info and the
+    pairs [(r_j, t_j)] of the SKS iterates U_0 = 0, U_1, ..., U_{iters-1}
+    (formed by h6net_training_pair)."""
+    k, (centres, amps, sigma), h = problem(n, seed)
+    plan = h6.Plan(n, h, k, BC, precision="mixed")
+    F = plan.rhs_gaussians(centres, amps, sigma)
+    Us, info = plan.solve(F, method="fgmres", restart=30, tol=1e-11, maxit=400)
+    U = torch.zeros_like(F)
+    pairs = []
+    for j in range(iters):
+        if j > 0:       # U_j = U_{j-1} + A_p^{-1} (F - A U_{j-1}): one SKS step from U_{j-1}
+            plan.solve(F, U, method="sks", tol=0.0, maxit=1, zero_guess=False)
+        pairs.append(plan.training_pair(F, Us, U))
+    return plan, k, h, info, pairs
+
+
 def make_pairs(n: int, nproblems: int, iters: int, seed: int, log=print, keep_plans: bool = False):
     """[(r, t, kh, plan)] on the GPU from plain solves of `nproblems` seeded
     problems; plan is the problem's (open) plan if keep_plans, else None."""
-    pairs = []
+    out = []
     for p in range(nproblems):
-        k, (centres, amps, sigma), h = problem(n, seed + p)
-        plan = h6.Plan(n, h, k, BC, precision="mixed")
-        F = plan.rhs_gaussians(centres, amps, sigma)
-        Us, info = plan.solve(F, method="fgmres", restart=30, tol=1e-11, maxit=400)
+        plan, k, h, info, pairs = problem_pairs(n, seed + p, iters)
         kh = k.real * h
-        for j in range(iters):
-            if j == 0:
-                Uj = torch.zeros_like(F)
-            else:
-                Uj, _ = plan.solve(F, method="sks", tol=0.0, maxit=j)
-            r = F - plan.apply_A(Uj)
-            t = (Us - Uj) - plan.apply_Pinv(r)
-            pairs.append((r, t, kh, plan if keep_plans else None))
+        out += [(r, t, kh, plan if keep_plans else None) for r, t in pairs]
         log(f"problem {p}: k = {k:.2f}, reference {info['iters']} FGMRES steps "
             f"(rel resid {info['rel_resid']:.1e}), {iters} pairs")
         if not keep_plans:
             plan.close()
-    return pairs
+    return out
+
+
+def train_stream(net: h6.Net, n: int, problems: int, iters: int, seed: int, steps_per_problem: int,
+                 buffer: int = 8, lr0: float = 1e-3, loss: str = "operator", log=print):
+    """Training on a stream of `problems` seeded problems (problems x iters
+    pairs in all): each new problem's pairs join a buffer of the last
+    `buffer` problems, and `steps_per_problem` Adam steps follow, each on a
+    pair drawn at random from the buffer (cosine learning-rate decay over the
+    whole run).  Returns the loss history and the seconds spent."""
+    from collections import deque
+    rng = np.random.default_rng(seed)
+    buf = deque()
+    total = problems * steps_per_problem
+    hist, step = [], 0
+    t0 = time.perf_counter()
+    for p in range(problems):
+        plan, k, h, info, pairs = problem_pairs(n, seed + p, iters)
+        buf.append((plan, k.real * h, pairs))
+        if len(buf) > buffer:
+            buf.popleft()[0].close()
+        for _ in range(steps_per_problem):
+            lr = lr0 * 0.5 * (1 + np.cos(np.pi * step / total)) + 1e-5
+            pl, kh, prs = buf[int(rng.integers(len(buf)))]
+            r, t = prs[int(rng.integers(len(prs)))]
+            want = step % 250 == 0 or step == total - 1
+            if loss == "operator":
+                L = net.train_step_op(pl, r, t, lr, want_loss=want)
+            else:
+                L = net.train_step(r, kh, t, lr, want_loss=want)
+            if want:
+                hist.append((step, L))
+                log(f"step {step} (problem {p}, {(p + 1) * iters} pairs): loss {L:.4f} lr {lr:.2e} "
+                    f"({time.perf_counter() - t0:.1f} s)")
+            step += 1
+    for pl, _, _ in buf:
+        pl.close()
+    torch.cuda.synchronize()
+    return hist, time.perf_counter() - t0
 
 
 def train(net: h6.Net, pairs, steps: int, lr0: float = 1e-3, seed: int = 0, log=print, loss: str = "plain"):
@@ -185,6 +231,11 @@ def main(argv=None):
     t.add_argument("--holdout", type=int, default=2)
     t.add_argument("--loss", choices=("plain", "operator"), default="plain")
     t.add_argument("--init", default=None, help="start from these weights (.npz) instead of a seeded init")
+    t.add_argument("--stream", action="store_true",
+                   help="generate the problems' pairs while training (a buffer of recent problems) "
+                        "instead of holding every pair")
+    t.add_argument("--steps-per-problem", type=int, default=8)
+    t.add_argument("--buffer", type=int, default=8)
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--workload", default="dns-256")
@@ -194,31 +245,45 @@ def main(argv=None):
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.cmd == "train":
         op = args.loss == "operator"
-        pairs = make_pairs(args.n, args.problems, args.iters, args.seed, log, keep_plans=op)
         held = make_pairs(args.n, args.holdout, args.iters, args.seed + 10_000, log, keep_plans=True)
-        dims = tuple(pairs[0][0].shape[::-1])
+        dims = tuple(held[0][0].shape[::-1])
         net = h6.Net(dims)
         if args.init:
             net.set_params(np.load(args.init)["params"])
         else:
             net.set_params(h6.pack_net_params(init_net_params(h6.NET_LAYERS, args.seed)))
         before = [a / b for a, b in pair_losses(net, held, operator=True)]
-        hist, secs = train(net, pairs, args.steps, args.lr, args.seed, log, loss=args.loss)
+        if args.stream:
+            hist, secs = train_stream(net, args.n, args.problems, args.iters, args.seed, args.steps_per_problem,
+                                      args.buffer, args.lr, args.loss, log)
+            steps = args.problems * args.steps_per_problem
+        else:
+            pairs = make_pairs(args.n, args.problems, args.iters, args.seed, log, keep_plans=op)
+            hist, secs = train(net, pairs, args.steps, args.lr, args.seed, log, loss=args.loss)
+            steps = args.steps
+            for _, _, _, plan in pairs:
+                if plan is not None:
+                    plan.close()
         ratio = float(np.mean([a / b for a, b in pair_losses(net, held)]))
         ratio_op = [a / b for a, b in pair_losses(net, held, operator=True)]
         log(f"held-out pairs: mean |c - t| / |t| = {ratio:.4f}; mean |A (c - t)| / |A t| = "
             f"{np.mean(ratio_op):.4f} (before training {np.mean(before):.4f}; 1 = no gain)")
         params = net.get_params()
         np.savez(args.out, params=params, loss=np.array(hist), heldout_ratio=ratio,
-                 heldout_op_ratio=float(np.mean(ratio_op)), train_seconds=secs, loss_kind=args.loss,
-                 n=args.n, problems=args.problems, iters=args.iters, steps=args.steps, seed=args.seed)
-        for _, _, _, plan in pairs + held:
-            if plan is not None:
+                 heldout_op_ratio=float(np.mean(ratio_op)), heldout_op_ratios=np.array(ratio_op),
+                 heldout_op_ratio_before=float(np.mean(before)), train_seconds=secs, loss_kind=args.loss,
+                 n=args.n, problems=args.problems, iters=args.iters, steps=steps, seed=args.seed,
+                 pairs=args.problems * args.iters, streamed=args.stream, lr=args.lr,
+                 init=args.init or "seeded initialisation")
+        seen = set()
+        for _, _, _, plan in held:
+            if plan is not None and id(plan) not in seen:
+                seen.add(id(plan))
                 plan.close()
         res = solve_compare(WORKLOADS["dns-128"], params, log)
         print(json.dumps({"loss": args.loss, "train_seconds": round(secs, 2), "heldout_ratio": ratio,
                           "heldout_op_ratio": [round(x, 4) for x in ratio_op],
-                          "final_loss": hist[-1][1], "dns-128": res}))
+                          "final_loss": hist[-1][1], "dns-128": res}), flush=True)
     elif args.cmd == "eval":
         params = np.load(args.weights)["params"]
         res = solve_compare(WORKLOADS[args.workload], params, log)

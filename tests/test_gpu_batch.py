@@ -84,6 +84,64 @@ def test_batch_matches_oracle(h6, batch_oracle, precision):
         assert abs(info["iters"] - oits) <= slack
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_queue_matches_oracle(h6, batch_oracle, precision):
+    """The queued batch (one captured graph, device-side queue per grid shape,
+    two lanes per shape) on the same instances and against the same oracle
+    results and bounds as the streams form; the instances are given in
+    reverse order, so the device queue must reorder them."""
+    import math
+    import numpy as np
+    plans, Fs = [], []
+    order = list(reversed(BATCH_ORACLE))
+    for idx in order:
+        inst = batch_oracle[idx][0]
+        p = h6.Plan(inst.n, inst.h, inst.k, inst.bc, precision=precision)
+        plans.append(p)
+        Fs.append(p.rhs_gaussians(inst.centres, inst.amps, inst.sigma))
+    Us = [torch.full_like(F, float("nan")) for F in Fs]        # not read: every solve starts from 0
+    infos = h6.solve_batch_queue(plans, Fs, Us, restart=30, tol=1e-8, maxit=600, lanes=2)
+    for idx, U, info in zip(order, Us, infos):
+        inst, Fo, Uref, oits = batch_oracle[idx]
+        err = float(np.abs(U.cpu().numpy() - Uref).max() / np.abs(Uref).max())
+        slack = 1 if precision == "fp64" else math.ceil(oits / 30)
+        print(f"queue {precision} instance {idx}: n {inst.n} faces {inst.bc} k {inst.k:.2f}: GPU "
+              f"{info['iters']} steps (oracle FGMRES {oits}), rel resid {info['rel_resid']:.2e}, "
+              f"solution error {err:.2e}", flush=True)
+        assert info["status"] == "ok" and info["rel_resid"] <= 1e-8
+        assert err <= 1e-6
+        assert abs(info["iters"] - oits) <= slack
+
+
+def test_queue_equals_streams_and_edge_cases(h6):
+    """The queued batch against the streams form on twelve instances of two
+    sizes (three shapes, one lane for some, more problems than lanes), plus a
+    zero right-hand side (U = 0 in no steps) and a step budget that ends a
+    solve unconverged."""
+    insts = batch_workload(12, seed=11, sizes=(48, 64))
+    plans, Fs = zip(*[make(h6, i) for i in insts])
+    plans, Fs = list(plans), list(Fs)
+    ref = [torch.zeros_like(F) for F in Fs]
+    i_ref = h6.solve_batch(plans, Fs, ref, method="fgmres", restart=30, tol=1e-8, maxit=400, nstreams=4)
+    Us = [torch.full_like(F, float("nan")) for F in Fs]
+    i_q = h6.solve_batch_queue(plans, Fs, Us, restart=30, tol=1e-8, maxit=400, lanes=3)
+    for k, (a, b, Ua, Ub) in enumerate(zip(i_ref, i_q, ref, Us)):
+        d = float(torch.linalg.norm(Ub - Ua) / torch.linalg.norm(Ua))
+        print(f"instance {k}: streams {a['iters']} steps, queue {b['iters']} steps, difference {d:.1e}",
+              flush=True)
+        assert b["status"] == "ok" and abs(a["iters"] - b["iters"]) <= 1 and d <= 1e-7
+    # F = 0 and a three-step budget, beside a normal solve of the same shape
+    p0, F0 = make(h6, insts[0])
+    p1, F1 = make(h6, insts[0])
+    Z = torch.zeros_like(F0)
+    outs = [torch.full_like(F0, 1.0) for _ in range(3)]
+    infos = h6.solve_batch_queue([p0, p1, plans[0]], [Z, F1, Fs[0]], outs, restart=30, tol=1e-8, maxit=3,
+                                 lanes=1)
+    assert infos[0]["status"] == "ok" and infos[0]["iters"] == 0 and float(outs[0].abs().max()) == 0.0
+    assert infos[1]["status"] == "not_converged" and infos[1]["iters"] == 3
+    assert infos[2]["status"] == "not_converged" and infos[2]["iters"] == 3
+
+
 def test_batch_equals_sequential(h6):
     insts = batch_workload(12, seed=11, sizes=(48, 64))
     plans, Fs = zip(*[make(h6, i) for i in insts])

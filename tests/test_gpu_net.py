@@ -253,12 +253,29 @@ def test_committed_weights_gain(h6):
     print(f"dns-128 mixed FGMRES(30): plain {res['plain']['iters']} steps, learned "
           f"{res['learned']['iters']} steps ({res['learned']['steps_with_correction']} with the "
           f"correction), solution difference {res['solution_rel_diff']:.2e}", flush=True)
-    # the network lowers the preconditioner's residual on held-out pairs; in
-    # the solve the judge accepts or rejects it per restart cycle, and the
-    # solve converges either way, in no more steps than the plain one
+    # the network lowers the preconditioner's residual on held-out pairs, the
+    # judge accepts it on every step, and the corrected solve needs fewer
+    # steps than the plain one (measured: 9 against 10)
     assert float(np.mean(ratios)) < 1.0
     assert res["plain"]["rel_resid"] <= 1e-8 and res["learned"]["rel_resid"] <= 1e-8
-    assert res["learned"]["iters"] <= res["plain"]["iters"]
-    if res["learned"]["steps_with_correction"] == 0:        # rejected: the plain iterates
-        assert res["learned"]["iters"] == res["plain"]["iters"] and res["solution_rel_diff"] == 0.0
+    assert res["learned"]["steps_with_correction"] == res["learned"]["iters"]
+    assert res["learned"]["iters"] < res["plain"]["iters"]
     assert res["solution_rel_diff"] < 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_training_pair_matches_oracle(h6, precision, tol):
+    """h6net_training_pair: r = F - A U and t = (U* - U) - A_p^{-1} r against
+    the oracle's operator and preconditioner (complex64 preconditioner
+    arithmetic in mixed plans: relative error about 1e-6)."""
+    import oracle
+    n, h, k, bc = (20, 13, 17), 1.0 / 21, 7.0 + 0.2j, "DDNNSS"
+    plan = h6.Plan(n, h, k, bc, precision=precision)
+    prob = oracle.Problem(n, h, k, tuple(bc))
+    F, Us, U = (random_field(prob.shape, s) for s in (21, 22, 23))
+    r, t = plan.training_pair(*(torch.from_numpy(a).cuda() for a in (F, Us, U)))
+    r_ref = F - oracle.apply_A(prob, U)
+    t_ref = (Us - U) - oracle.apply_Pinv(prob, r_ref)
+    er, et = maxrel(r.cpu().numpy(), r_ref), maxrel(t.cpu().numpy(), t_ref)
+    print(f"{precision}: r error {er:.2e}, t error {et:.2e}", flush=True)
+    assert er <= 1e-12 and et <= tol
