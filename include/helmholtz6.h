@@ -220,24 +220,38 @@ h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* con
                                  h6_solve_info* infos, h6_status* statuses, int count, int nstreams);
 
 /* The same many independent solves as one captured HIP graph fed by a
- * device-side work queue (flexible GMRES only, infos[i].method = H6_FGMRES,
- * one restart length for all; tol and maxit per solve).  Problems are grouped
- * by grid shape (unknown counts, faces, precision); each group gets up to
- * `lanes` (1..16) lanes, a lane being a library-owned plan of that shape with
- * its own workspace, and a queue of its problems in decreasing order of an
- * estimated cost (unknowns times a kh-based iteration estimate).  A replay of
- * the graph advances every lane by one restart cycle with the Givens rotations
- * on the device; at the start of each cycle the lane tests its problem's true
- * residual on the device, and when the problem is done it copies U out, takes
- * the next problem from the queue (atomic head) and loads that problem's
- * right-hand side and wavenumber-dependent tables (stencil weights and z
- * tridiagonal data of plans[i]) into the lane.  The host replays the graph
- * until every lane has found its queue empty (one wait per replay).  Each
- * U[i] starts from zero (its contents are not read), F[i] and plans[i] are
- * read only; infos[i] receives iters and rel_resid (no history), statuses[i]
- * the solve's status.  The lanes' workspace is allocated and released inside
- * the call.  Returns H6_OK when every solve returned a non-negative status,
- * otherwise the first negative one (message in helmholtz6_last_error(plans[0])). */
+ * device-side work queue (flexible GMRES only).  helmholtz6_queue_create
+ * groups the problems of plans[0..count-1] by grid shape (unknown counts,
+ * faces, precision); each group gets up to `lanes` (1..16) lanes, a lane
+ * being a library-owned plan of that shape with its own FGMRES(restart)
+ * workspace, and a queue of the group's problems in decreasing order of an
+ * estimated cost (unknowns times a kh-based iteration estimate); it captures
+ * one graph holding every lane (allocates; synchronous).  The queue keeps
+ * pointers to the plans, which must stay alive and unchanged until it is
+ * destroyed.  helmholtz6_queue_solve solves problem i: plans[i] U[i] = F[i]
+ * with infos[i] (method H6_FGMRES, restart equal to the queue's; tol and
+ * maxit per problem): U[i] starts from zero (its contents are not read), F[i]
+ * is read only; infos[i] receives iters and rel_resid (no history),
+ * statuses[i] the solve's status.  A replay of the graph advances every lane
+ * by one restart cycle with the Givens rotations on the device; at the start
+ * of each cycle the lane tests its problem's true residual on the device, and
+ * when the problem is done it copies U out, takes the next problem from its
+ * queue (atomic head) and loads that problem's right-hand side and
+ * wavenumber-dependent tables (stencil weights and z tridiagonal data of
+ * plans[i]) into the lane.  The host replays the graph until every lane has
+ * found its queue empty (one wait per replay); the call returns when all
+ * solves are done, with H6_OK when every solve returned a non-negative
+ * status, otherwise the first negative one (message in
+ * helmholtz6_queue_last_error).  One solve at a time per queue.
+ * helmholtz6_solve_batch_queue is create, solve and destroy in one call
+ * (infos[0].restart sets the restart length; message in
+ * helmholtz6_last_error(plans[0])). */
+typedef struct h6_queue_s* h6_queue;
+h6_status helmholtz6_queue_create(h6_plan* plans, int count, int restart, int lanes, h6_queue* out);
+h6_status helmholtz6_queue_solve(h6_queue queue, const void* const* F, void* const* U, h6_solve_info* infos,
+                                 h6_status* statuses);
+const char* helmholtz6_queue_last_error(h6_queue queue);
+void helmholtz6_queue_destroy(h6_queue queue);
 h6_status helmholtz6_solve_batch_queue(h6_plan* plans, const void* const* F, void* const* U,
                                        h6_solve_info* infos, h6_status* statuses, int count, int lanes);
 

@@ -900,22 +900,67 @@ h6_status helmholtz6_solve_batch(h6_plan* plans, const void* const* F, void* con
   return H6_OK;
 }
 
+h6_status helmholtz6_queue_create(h6_plan* plans, int count, int restart, int lanes, h6_queue* out) {
+  if (!out) return H6_ERR_ARG;
+  *out = nullptr;
+  if (!plans || count < 1 || lanes < 1 || lanes > 16) return H6_ERR_ARG;
+  std::string err;
+  h6_status st;
+  try {
+    st = queue_create(plans, count, restart, lanes, out, err);
+  } catch (...) {
+    st = H6_ERR_ALLOC;
+    err = "exception while creating the queue";
+  }
+  if (st != H6_OK) {
+    std::lock_guard<std::mutex> g(g_setup_mutex);
+    g_setup_error = err;
+  }
+  return st;
+}
+
+h6_status helmholtz6_queue_solve(h6_queue Q, const void* const* F, void* const* U, h6_solve_info* infos,
+                                 h6_status* statuses) {
+  if (!Q) return H6_ERR_ARG;
+  Q->last_error.clear();
+  if (!F || !U || !infos || !statuses) {
+    Q->last_error = "null array";
+    return H6_ERR_ARG;
+  }
+  try {
+    return queue_solve(Q, reinterpret_cast<const double2* const*>(F), reinterpret_cast<double2* const*>(U), infos,
+                       statuses, Q->last_error);
+  } catch (...) {
+    Q->last_error = "exception in the queued solve";
+    return H6_ERR_ALLOC;
+  }
+}
+
+const char* helmholtz6_queue_last_error(h6_queue Q) {
+  if (!Q) {
+    std::lock_guard<std::mutex> g(g_setup_mutex);
+    return g_setup_error.c_str();
+  }
+  return Q->last_error.c_str();
+}
+
+void helmholtz6_queue_destroy(h6_queue Q) { queue_destroy(Q); }
+
 h6_status helmholtz6_solve_batch_queue(h6_plan* plans, const void* const* F, void* const* U,
                                        h6_solve_info* infos, h6_status* statuses, int count, int lanes) {
   if (!plans || !F || !U || !infos || !statuses || count < 0 || lanes < 1 || lanes > 16) return H6_ERR_ARG;
   if (count == 0) return H6_OK;
   for (int i = 0; i < count; ++i)
     if (!plans[i]) return H6_ERR_ARG;
-  std::string err;
-  h6_status st;
-  try {
-    st = solve_queue(plans, reinterpret_cast<const double2* const*>(F), reinterpret_cast<double2* const*>(U),
-                     infos, statuses, count, lanes, err);
-  } catch (...) {
-    st = H6_ERR_ALLOC;
-    err = "exception in the queued batch";
+  h6_queue Q = nullptr;
+  h6_status st = helmholtz6_queue_create(plans, count, infos[0].restart, lanes, &Q);
+  if (st != H6_OK) {
+    plans[0]->last_error = helmholtz6_queue_last_error(nullptr);
+    return st;
   }
-  if (st < 0) plans[0]->last_error = err;
+  st = helmholtz6_queue_solve(Q, F, U, infos, statuses);
+  if (st < 0) plans[0]->last_error = Q->last_error;
+  helmholtz6_queue_destroy(Q);
   return st;
 }
 

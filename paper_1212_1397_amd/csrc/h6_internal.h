@@ -352,8 +352,41 @@ hipError_t launch_lane_cycle(QueueLane* lane, const QueueEntry* q, QueueResult* 
 hipError_t launch_lane_count(QueueLane* lane, const int* jdone, hipStream_t s);
 // sum of nparts partials into *out; skipped while *skip != 0
 hipError_t launch_reduce_sum_skip(const double* partials, int nparts, double* out, const int* skip, hipStream_t s);
-h6_status solve_queue(h6_plan* plans, const double2* const* F, double2* const* U, h6_solve_info* infos,
-                      h6_status* statuses, int count, int lanes, std::string& err);
+struct QLane {                 // one lane: a plan of its group's shape and its F / U slots
+  h6_plan P = nullptr;
+  double2* F = nullptr;
+  double2* U = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t join = nullptr;
+  int group = 0;
+};
+}  // namespace h6
+
+struct h6_queue_s {
+  int m = 0, count = 0;
+  std::vector<h6_plan> plans;          // the problems' plans (not owned)
+  std::vector<int> order;              // queue position -> problem index (groups contiguous)
+  std::vector<int> goff, gcount;       // queue offset and size per group
+  std::vector<h6::QLane> L;
+  hipStream_t s0 = nullptr;
+  hipEvent_t fork = nullptr;
+  h6::QueueEntry* d_q = nullptr;
+  int* d_head = nullptr;
+  h6::QueueLane* d_lanes = nullptr;
+  h6::QueueResult* h_res = nullptr;    // host-mapped results, one per problem
+  h6::QueueResult* d_res = nullptr;
+  int* h_idle = nullptr;               // host-mapped idle flags, one per lane
+  int* d_idle = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string last_error;
+};
+
+namespace h6 {
+h6_status queue_create(h6_plan* plans, int count, int m, int lanes, h6_queue* out, std::string& err);
+h6_status queue_solve(h6_queue Q, const double2* const* F, double2* const* U, h6_solve_info* infos,
+                      h6_status* statuses, std::string& err);
+void queue_destroy(h6_queue Q);
 
 void release_graphs(h6_plan P);
 h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s);

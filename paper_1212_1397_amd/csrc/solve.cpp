@@ -698,19 +698,46 @@ h6_status run_solve(h6_plan P, const double2* F, double2* U, h6_solve_info* info
 // advances each lane by one restart cycle, and the lanes themselves decide
 // on the device when their problem is done and which problem comes next
 // (queue.hip).  The host replays the graph until every lane reports an
-// empty queue.
-h6_status solve_queue(h6_plan* plans, const double2* const* F, double2* const* U, h6_solve_info* infos,
-                      h6_status* statuses, int count, int lanes, std::string& err) {
-  const int m = infos[0].restart;
-  if (m < 1 || m > 256) { err = "restart must be in 1..256"; return H6_ERR_ARG; }
-  for (int i = 0; i < count; ++i) {
-    if (!plans[i] || !F[i] || !U[i] || F[i] == U[i]) { err = "null or aliased plan / vector"; return H6_ERR_ARG; }
-    const h6_solve_info& in = infos[i];
-    if (in.method != H6_FGMRES || in.restart != m || in.maxit < 1 || !(in.tol >= 0.0)) {
-      err = "the queued batch runs flexible GMRES with one restart length, maxit >= 1 and tol >= 0";
-      return H6_ERR_ARG;
-    }
+// empty queue.  queue_create builds the lanes and the graph once;
+// queue_solve fills the queue with the caller's vectors and tolerances and
+// replays.
+void queue_destroy(h6_queue Q) {
+  if (!Q) return;
+  if (Q->exec) (void)hipGraphExecDestroy(Q->exec);
+  if (Q->graph) (void)hipGraphDestroy(Q->graph);
+  for (QLane& l : Q->L) {
+    if (l.join) (void)hipEventDestroy(l.join);
+    if (l.s) (void)hipStreamDestroy(l.s);
+    (void)hipFree(l.F);
+    (void)hipFree(l.U);
+    helmholtz6_destroy(l.P);
   }
+  if (Q->fork) (void)hipEventDestroy(Q->fork);
+  if (Q->s0) (void)hipStreamDestroy(Q->s0);
+  (void)hipFree(Q->d_q);
+  (void)hipFree(Q->d_head);
+  (void)hipFree(Q->d_lanes);
+  if (Q->h_res) (void)hipHostFree(Q->h_res);
+  if (Q->h_idle) (void)hipHostFree(Q->h_idle);
+  delete Q;
+}
+
+h6_status queue_create(h6_plan* plans, int count, int m, int lanes, h6_queue* out, std::string& err) {
+  *out = nullptr;
+  if (m < 1 || m > 256) { err = "restart must be in 1..256"; return H6_ERR_ARG; }
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) { err = "null plan"; return H6_ERR_ARG; }
+  h6_queue Q = new h6_queue_s();
+  Q->m = m;
+  Q->count = count;
+  Q->plans.assign(plans, plans + count);
+  h6_status st = H6_OK;
+  auto fail = [&](const std::string& what, hipError_t e) {
+    err = what + ": " + hipGetErrorString(e);
+    st = e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
+    queue_destroy(Q);
+    return st;
+  };
   // groups of one grid shape, each in decreasing order of estimated cost
   using Key = std::tuple<int, int, int, int, int, int, int, int, int, int>;
   std::map<Key, std::vector<int>> groups;
@@ -722,204 +749,160 @@ h6_status solve_queue(h6_plan* plans, const double2* const* F, double2* const* U
     groups[Key{P->dims[0], P->dims[1], P->dims[2], P->p.bc[0], P->p.bc[2], P->p.bc[4], P->p.bc[5],
                P->p.precision, P->xmirror, P->ymirror}].push_back(i);
   }
-  struct Lane {
-    h6_plan P = nullptr;
-    double2* F = nullptr;
-    double2* U = nullptr;
-    hipStream_t s = nullptr;
-    hipEvent_t join = nullptr;
-    int group = 0;
-  };
-  std::vector<Lane> L;
-  std::vector<int> goff, gcount;        // queue offset and size per group
-  std::vector<QueueEntry> entries;
-  hipStream_t s0 = nullptr;
-  hipEvent_t fork = nullptr;
-  QueueEntry* d_q = nullptr;
-  int* d_head = nullptr;
-  QueueLane* d_lanes = nullptr;
-  QueueResult* h_res = nullptr;
-  QueueResult* d_res = nullptr;
-  int* h_idle = nullptr;
-  int* d_idle = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  h6_status st = H6_OK;
-  auto fail = [&](const std::string& what, hipError_t e) {
-    err = what + ": " + hipGetErrorString(e);
-    st = e == hipErrorOutOfMemory ? H6_ERR_ALLOC : H6_ERR_HIP;
-  };
-  auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    for (Lane& l : L) {
-      if (l.join) (void)hipEventDestroy(l.join);
-      if (l.s) (void)hipStreamDestroy(l.s);
-      (void)hipFree(l.F);
-      (void)hipFree(l.U);
-      helmholtz6_destroy(l.P);
-    }
-    if (fork) (void)hipEventDestroy(fork);
-    if (s0) (void)hipStreamDestroy(s0);
-    (void)hipFree(d_q);
-    (void)hipFree(d_head);
-    (void)hipFree(d_lanes);
-    if (h_res) (void)hipHostFree(h_res);
-    if (h_idle) (void)hipHostFree(h_idle);
-  };
-  // queue entries (group by group) and lanes
   for (auto& kv : groups) {
     std::vector<int>& ids = kv.second;
     std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    goff.push_back(int(entries.size()));
-    gcount.push_back(int(ids.size()));
-    for (int i : ids) {
-      const h6_plan P = plans[i];
-      entries.push_back(QueueEntry{F[i], U[i], P->d_stencil, P->d_cstart, P->d_zparams, infos[i].tol,
-                                   infos[i].maxit, i});
-    }
+    Q->goff.push_back(int(Q->order.size()));
+    Q->gcount.push_back(int(ids.size()));
+    Q->order.insert(Q->order.end(), ids.begin(), ids.end());
     const int nl = std::min(lanes, int(ids.size()));
     for (int l = 0; l < nl; ++l) {
-      Lane ln;
-      ln.group = int(goff.size()) - 1;
+      Q->L.emplace_back();
+      QLane& ln = Q->L.back();
+      ln.group = int(Q->goff.size()) - 1;
       const h6_plan src = plans[ids[0]];
       h6_status s1 = helmholtz6_setup(&src->p, nullptr, &ln.P);
       if (s1 != H6_OK) {
         err = "lane plan setup failed";
-        cleanup();
+        queue_destroy(Q);
         return s1;
       }
-      L.push_back(ln);
-      Lane& lr = L.back();
       // the kernel variants chosen for the group's plans
-      lr.P->stencil_tz = src->stencil_tz;
+      ln.P->stencil_tz = src->stencil_tz;
       for (int a = 0; a < 2; ++a)
-        if (lr.P->ax[a].fast == src->ax[a].fast) lr.P->ax[a].lines = src->ax[a].lines;
-      lr.P->use_graphs = 2;                           // device least-squares state
-      s1 = ensure(lr.P, H6_FGMRES, m);
+        if (ln.P->ax[a].fast == src->ax[a].fast) ln.P->ax[a].lines = src->ax[a].lines;
+      ln.P->use_graphs = 2;                           // device least-squares state
+      s1 = ensure(ln.P, H6_FGMRES, m);
       if (s1 != H6_OK) {
-        err = lr.P->last_error;
-        cleanup();
+        err = ln.P->last_error;
+        queue_destroy(Q);
         return s1;
       }
-      const size_t vb = lr.P->N * sizeof(double2);
-      hipError_t e = hipMalloc(reinterpret_cast<void**>(&lr.F), vb);
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&lr.U), vb);
-      if (e == hipSuccess) e = hipMemset(lr.F, 0, vb);
-      if (e == hipSuccess) e = hipMemset(lr.U, 0, vb);
-      if (e == hipSuccess) e = hipStreamCreateWithFlags(&lr.s, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&lr.join, hipEventDisableTiming);
-      if (e != hipSuccess) {
-        fail("lane allocation", e);
-        cleanup();
-        return st;
-      }
+      const size_t vb = ln.P->N * sizeof(double2);
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&ln.F), vb);
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ln.U), vb);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.join, hipEventDisableTiming);
+      if (e != hipSuccess) return fail("lane allocation", e);
     }
   }
-  const int nl = int(L.size());
+  const int nl = int(Q->L.size());
   {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_q), sizeof(QueueEntry) * entries.size());
-    if (e == hipSuccess) e = hipMemcpy(d_q, entries.data(), sizeof(QueueEntry) * entries.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_head), sizeof(int) * goff.size());
-    if (e == hipSuccess) e = hipMemset(d_head, 0, sizeof(int) * goff.size());
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h_res), sizeof(QueueResult) * count,
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&Q->d_q), sizeof(QueueEntry) * count);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&Q->d_head), sizeof(int) * Q->goff.size());
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&Q->h_res), sizeof(QueueResult) * count,
                                            hipHostMallocMapped | hipHostMallocCoherent);
-    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d_res), h_res, 0);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h_idle), sizeof(int) * nl,
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&Q->d_res), Q->h_res, 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&Q->h_idle), sizeof(int) * nl,
                                            hipHostMallocMapped | hipHostMallocCoherent);
-    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d_idle), h_idle, 0);
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&d_lanes), sizeof(QueueLane) * nl);
-    if (e == hipSuccess) {
-      for (int i = 0; i < count; ++i) h_res[i] = QueueResult{0, int(H6_ERR_HIP), 0.0};
-      std::vector<QueueLane> init(nl);
-      for (int l = 0; l < nl; ++l) {
-        h_idle[l] = 0;
-        init[l] = QueueLane{-1, -1, -1, 0, 0, 1, 1, 0, 0.0, d_idle + l};
-      }
-      e = hipMemcpy(d_lanes, init.data(), sizeof(QueueLane) * nl, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s0, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&Q->d_idle), Q->h_idle, 0);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&Q->d_lanes), sizeof(QueueLane) * nl);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&Q->s0, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&Q->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-      fail("queue set-up", e);
-      cleanup();
-      return st;
-    }
+    if (e != hipSuccess) return fail("queue set-up", e);
   }
   // capture: every lane forked from s0 onto its own stream
-  {
-    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) e = hipEventRecord(fork, s0);
-    for (int l = 0; l < nl && e == hipSuccess; ++l) {
-      Lane& ln = L[l];
-      h6_plan P = ln.P;
-      QueueLane* lane = d_lanes + l;
-      const QueueEntry* q = d_q + goff[ln.group];
-      const int qn = gcount[ln.group];
-      Ctx c{P, ln.s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
-      const GivensState gs = givens_state(P, m);
-      const bool mixed = P->p.precision == H6_MIXED;
-      e = hipStreamWaitEvent(ln.s, fork, 0);
-      int nparts = 0;
-      P->skip = &lane->idle;
-      if (e == hipSuccess) e = launch_stencil(P, ln.U, P->V, ln.F, P->partials, &nparts, ln.s);
-      P->skip = nullptr;
-      if (e == hipSuccess) e = launch_reduce_sum_skip(P->partials, nparts, c.dev + kNorm, &lane->idle, ln.s);
-      if (e == hipSuccess) e = launch_lane_check(lane, q, d_head + ln.group, qn, c.dev + kNorm, d_res, ln.s);
-      if (e == hipSuccess) {
-        const size_t cst_bytes = size_t(z_segments(P->dims[2], mixed)) * P->dims[0] * P->dims[1] *
-                                 (mixed ? sizeof(float2) : sizeof(double2));
-        const LaneRefill a{lane, q, ln.F, ln.U, P->V, P->d_stencil, P->d_cstart, P->d_zparams, P->N,
-                           cst_bytes / 8, P->partials};
-        e = launch_lane_refill(a, ln.s);
-      }
-      if (e == hipSuccess) e = launch_reduce_sum_skip(P->partials, kRedBlocks, c.dev + kNorm, &lane->skip_fresh, ln.s);
-      if (e == hipSuccess)
-        e = launch_lane_cycle(lane, q, d_res, c.dev + kNorm, c.dev + kPrm, gs.stop, gs.jdone, m, ln.s);
-      if (e == hipSuccess) e = enqueue_cycle(c, ln.U, m, true, mixed, gs);
-      if (e == hipSuccess) e = launch_lane_count(lane, gs.jdone, ln.s);
-      if (e == hipSuccess) e = hipEventRecord(ln.join, ln.s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s0, ln.join, 0);
+  hipError_t e = hipStreamBeginCapture(Q->s0, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) e = hipEventRecord(Q->fork, Q->s0);
+  for (int l = 0; l < nl && e == hipSuccess; ++l) {
+    QLane& ln = Q->L[l];
+    h6_plan P = ln.P;
+    QueueLane* lane = Q->d_lanes + l;
+    const QueueEntry* q = Q->d_q + Q->goff[ln.group];
+    const int qn = Q->gcount[ln.group];
+    Ctx c{P, ln.s, P->N, reinterpret_cast<double*>(P->d_scal), reinterpret_cast<double*>(P->h_pinned)};
+    const GivensState gs = givens_state(P, m);
+    const bool mixed = P->p.precision == H6_MIXED;
+    e = hipStreamWaitEvent(ln.s, Q->fork, 0);
+    int nparts = 0;
+    P->skip = &lane->idle;
+    if (e == hipSuccess) e = launch_stencil(P, ln.U, P->V, ln.F, P->partials, &nparts, ln.s);
+    P->skip = nullptr;
+    if (e == hipSuccess) e = launch_reduce_sum_skip(P->partials, nparts, c.dev + kNorm, &lane->idle, ln.s);
+    if (e == hipSuccess) e = launch_lane_check(lane, q, Q->d_head + ln.group, qn, c.dev + kNorm, Q->d_res, ln.s);
+    if (e == hipSuccess) {
+      const size_t cst_bytes = size_t(z_segments(P->dims[2], mixed)) * P->dims[0] * P->dims[1] *
+                               (mixed ? sizeof(float2) : sizeof(double2));
+      const LaneRefill a{lane, q, ln.F, ln.U, P->V, P->d_stencil, P->d_cstart, P->d_zparams, P->N,
+                         cst_bytes / 8, P->partials};
+      e = launch_lane_refill(a, ln.s);
     }
-    const hipError_t e2 = hipStreamEndCapture(s0, &graph);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      fail("queue graph capture", e);
-      cleanup();
-      return st;
+    if (e == hipSuccess)
+      e = launch_reduce_sum_skip(P->partials, kRedBlocks, c.dev + kNorm, &lane->skip_fresh, ln.s);
+    if (e == hipSuccess)
+      e = launch_lane_cycle(lane, q, Q->d_res, c.dev + kNorm, c.dev + kPrm, gs.stop, gs.jdone, m, ln.s);
+    if (e == hipSuccess) e = enqueue_cycle(c, ln.U, m, true, mixed, gs);
+    if (e == hipSuccess) e = launch_lane_count(lane, gs.jdone, ln.s);
+    if (e == hipSuccess) e = hipEventRecord(ln.join, ln.s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(Q->s0, ln.join, 0);
+  }
+  const hipError_t e2 = hipStreamEndCapture(Q->s0, &Q->graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&Q->exec, Q->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail("queue graph capture", e);
+  *out = Q;
+  return H6_OK;
+}
+
+h6_status queue_solve(h6_queue Q, const double2* const* F, double2* const* U, h6_solve_info* infos,
+                      h6_status* statuses, std::string& err) {
+  const int count = Q->count, nl = int(Q->L.size()), m = Q->m;
+  std::vector<QueueEntry> entries(count);
+  for (int k = 0; k < count; ++k) {
+    const int i = Q->order[k];
+    const h6_solve_info& in = infos[i];
+    if (!F[i] || !U[i] || F[i] == U[i]) { err = "null or aliased vector"; return H6_ERR_ARG; }
+    if (in.method != H6_FGMRES || in.restart != m || in.maxit < 1 || !(in.tol >= 0.0)) {
+      err = "the queued batch runs flexible GMRES with the queue's restart length, maxit >= 1 and tol >= 0";
+      return H6_ERR_ARG;
     }
+    const h6_plan P = Q->plans[i];
+    entries[k] = QueueEntry{F[i], U[i], P->d_stencil, P->d_cstart, P->d_zparams, in.tol, in.maxit, i};
+  }
+  for (int i = 0; i < count; ++i) Q->h_res[i] = QueueResult{0, int(H6_ERR_HIP), 0.0};
+  std::vector<QueueLane> init(nl);
+  for (int l = 0; l < nl; ++l) {
+    Q->h_idle[l] = 0;
+    init[l] = QueueLane{-1, -1, -1, 0, 0, 1, 1, 0, 0.0, Q->d_idle + l};
+  }
+  hipError_t e = hipMemcpyAsync(Q->d_q, entries.data(), sizeof(QueueEntry) * count, hipMemcpyHostToDevice, Q->s0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(Q->d_lanes, init.data(), sizeof(QueueLane) * nl, hipMemcpyHostToDevice, Q->s0);
+  if (e == hipSuccess) e = hipMemsetAsync(Q->d_head, 0, sizeof(int) * Q->goff.size(), Q->s0);
+  for (int l = 0; l < nl && e == hipSuccess; ++l) {    // the lanes start from empty slots
+    const size_t vb = Q->L[l].P->N * sizeof(double2);
+    e = hipMemsetAsync(Q->L[l].F, 0, vb, Q->s0);
+    if (e == hipSuccess) e = hipMemsetAsync(Q->L[l].U, 0, vb, Q->s0);
   }
   // replays until every lane found its queue empty (bounded by the step budgets)
   long long bound = 2;
   for (int i = 0; i < count; ++i) bound += (infos[i].maxit + m - 1) / m + 2;
   bool drained = false;
-  for (long long rep = 0; rep < bound; ++rep) {
-    hipError_t e = hipGraphLaunch(exec, s0);
-    if (e == hipSuccess) e = hipStreamSynchronize(s0);
-    if (e != hipSuccess) {
-      fail("queue graph replay", e);
-      cleanup();
-      return st;
-    }
+  for (long long rep = 0; rep < bound && e == hipSuccess; ++rep) {
+    e = hipGraphLaunch(Q->exec, Q->s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(Q->s0);
+    if (e != hipSuccess) break;
     drained = true;
-    for (int l = 0; l < nl; ++l) drained = drained && h_idle[l] != 0;
+    for (int l = 0; l < nl; ++l) drained = drained && Q->h_idle[l] != 0;
     if (drained) break;
+  }
+  if (e != hipSuccess) {
+    err = std::string("queue replay: ") + hipGetErrorString(e);
+    return H6_ERR_HIP;
   }
   if (!drained) {
     err = "internal: the queued batch did not drain within its step budget";
-    cleanup();
     return H6_ERR_HIP;
   }
+  h6_status st = H6_OK;
   for (int i = 0; i < count; ++i) {
-    statuses[i] = h6_status(h_res[i].status);
-    infos[i].iters = h_res[i].iters;
-    infos[i].rel_resid = h_res[i].rel_resid;
+    statuses[i] = h6_status(Q->h_res[i].status);
+    infos[i].iters = Q->h_res[i].iters;
+    infos[i].rel_resid = Q->h_res[i].rel_resid;
     infos[i].history_len = 0;
     if (statuses[i] < 0 && st == H6_OK) st = statuses[i];
   }
-  cleanup();
   return st;
 }
 

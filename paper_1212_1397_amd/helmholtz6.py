@@ -29,7 +29,9 @@ EXPORTED = ("helmholtz6_setup", "helmholtz6_dims", "helmholtz6_apply_A", "helmho
             "helmholtz6_rhs_gaussians", "helmholtz6_solve", "helmholtz6_profile",
             "helmholtz6_kernel_time", "helmholtz6_destroy", "helmholtz6_status_string",
             "helmholtz6_last_error", "helmholtz6_spectrum_bounds", "helmholtz6_psi_order",
-            "helmholtz6_solve_batch", "helmholtz6_solve_batch_queue", "helmholtz6_set_graphs", "helmholtz6_autotune",
+            "helmholtz6_solve_batch", "helmholtz6_solve_batch_queue", "helmholtz6_queue_create",
+            "helmholtz6_queue_solve", "helmholtz6_queue_last_error", "helmholtz6_queue_destroy",
+            "helmholtz6_set_graphs", "helmholtz6_autotune",
             "helmholtz6_rhs_separable", "helmholtz6_rhs_dirichlet_z", "helmholtz6_rhs_neumann")
 EXPORTED_NET = ("h6net_param_count", "h6net_create", "h6net_set_params", "h6net_get_params",
                 "h6net_forward", "h6net_gradients", "h6net_train_step", "h6net_gradients_op",
@@ -88,6 +90,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.helmholtz6_solve_batch_queue.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                                  ctypes.POINTER(H6SolveInfo), ctypes.POINTER(ip), ip, ip]
     lib.helmholtz6_solve_batch_queue.restype = ctypes.c_int
+    lib.helmholtz6_queue_create.argtypes = [ctypes.POINTER(vp), ip, ip, ip, ctypes.POINTER(vp)]
+    lib.helmholtz6_queue_create.restype = ctypes.c_int
+    lib.helmholtz6_queue_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(H6SolveInfo), ctypes.POINTER(ip)]
+    lib.helmholtz6_queue_solve.restype = ctypes.c_int
+    lib.helmholtz6_queue_last_error.argtypes = [vp]
+    lib.helmholtz6_queue_last_error.restype = ctypes.c_char_p
+    lib.helmholtz6_queue_destroy.argtypes = [vp]
+    lib.helmholtz6_queue_destroy.restype = None
     lib.helmholtz6_set_graphs.argtypes = [vp, ip]
     lib.helmholtz6_set_graphs.restype = ctypes.c_int
     lib.helmholtz6_autotune.argtypes = [vp, ctypes.c_char_p, vp]
@@ -497,27 +508,72 @@ def solve_batch(plans, Fs, Us, method="fgmres", restart=30, maxit=1000, tol=1e-8
                  history=list(hists[i][:infos[i].history_len])) for i in range(n)]
 
 
-def solve_batch_queue(plans, Fs, Us, restart=30, maxit=1000, tol=1e-8, lanes=2):
-    """Flexible GMRES(restart) solves of plans[i] x = Fs[i] into Us[i] (from zero) as one
-    captured graph fed by a device-side queue per grid shape (helmholtz6_solve_batch_queue),
-    `lanes` lanes per shape.  Returns a list of info dicts (no history)."""
+def _queue_arrays(plans, Fs, Us, restart, maxit, tol):
     n = len(plans)
     if not (len(Fs) == len(Us) == n):
         raise ValueError("plans, Fs and Us must have the same length")
-    P = (ctypes.c_void_p * n)(*[p._plan.value for p in plans])
     Fp = (ctypes.c_void_p * n)(*[p._vec(F, "F").value for p, F in zip(plans, Fs)])
     Up = (ctypes.c_void_p * n)(*[p._vec(U, "U").value for p, U in zip(plans, Us)])
     infos = (H6SolveInfo * n)()
     for i in range(n):
         infos[i] = H6SolveInfo(METHODS["fgmres"], int(restart), int(maxit), float(tol), 0, 0.0, None, 0, 1)
-    sts = (ctypes.c_int * n)()
+    return Fp, Up, infos, (ctypes.c_int * n)()
+
+
+def _queue_results(infos, sts, n):
+    names = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}
+    return [dict(status=names[sts[i]], iters=infos[i].iters, rel_resid=infos[i].rel_resid, history=[])
+            for i in range(n)]
+
+
+class Queue:
+    """Many flexible GMRES(restart) solves as one captured graph fed by a
+    device-side queue per grid shape (helmholtz6_queue_create): built once for
+    a list of plans, solved any number of times with new right-hand sides."""
+
+    def __init__(self, plans, restart=30, lanes=2):
+        n = len(plans)
+        P = (ctypes.c_void_p * n)(*[p._plan.value for p in plans])
+        self._q = ctypes.c_void_p()
+        st = _lib.helmholtz6_queue_create(P, n, int(restart), int(lanes), ctypes.byref(self._q))
+        if st != H6_OK:
+            raise H6Error(st, _lib.helmholtz6_queue_last_error(None).decode() or "queue creation failed")
+        self.plans, self.restart = list(plans), int(restart)
+
+    def solve(self, Fs, Us, tol=1e-8, maxit=1000):
+        """U[i] (overwritten; solves start from zero) for every F[i]; list of info dicts."""
+        n = len(self.plans)
+        Fp, Up, infos, sts = _queue_arrays(self.plans, Fs, Us, self.restart, maxit, tol)
+        torch.cuda.synchronize()          # inputs ready before the library's streams start
+        st = _lib.helmholtz6_queue_solve(self._q, Fp, Up, infos, sts)
+        if st < 0:
+            raise H6Error(st, _lib.helmholtz6_queue_last_error(self._q).decode() or "queued solve failed")
+        return _queue_results(infos, sts, n)
+
+    def close(self):
+        if self._q:
+            _lib.helmholtz6_queue_destroy(self._q)
+            self._q = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch_queue(plans, Fs, Us, restart=30, maxit=1000, tol=1e-8, lanes=2):
+    """Flexible GMRES(restart) solves of plans[i] x = Fs[i] into Us[i] (from zero) as one
+    captured graph fed by a device-side queue per grid shape (helmholtz6_solve_batch_queue:
+    queue create, solve and destroy in one call), `lanes` lanes per shape."""
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[p._plan.value for p in plans])
+    Fp, Up, infos, sts = _queue_arrays(plans, Fs, Us, restart, maxit, tol)
     torch.cuda.synchronize()              # inputs ready before the library's streams start
     st = _lib.helmholtz6_solve_batch_queue(P, Fp, Up, infos, sts, n, int(lanes))
     if st < 0:
         raise H6Error(st, _lib.helmholtz6_last_error(plans[0]._plan).decode() or "queued batch failed")
-    names = {H6_OK: "ok", H6_NOT_CONVERGED: "not_converged", H6_DIVERGED: "diverged"}
-    return [dict(status=names[sts[i]], iters=infos[i].iters, rel_resid=infos[i].rel_resid, history=[])
-            for i in range(n)]
+    return _queue_results(infos, sts, n)
 
 
 def psi_order(r1_h: float, r2_h: float, r1_gh: float, r2_gh: float, gamma: float) -> float:

@@ -130,6 +130,15 @@ def test_queue_equals_streams_and_edge_cases(h6):
         print(f"instance {k}: streams {a['iters']} steps, queue {b['iters']} steps, difference {d:.1e}",
               flush=True)
         assert b["status"] == "ok" and abs(a["iters"] - b["iters"]) <= 1 and d <= 1e-7
+    # a queue built once and solved twice: 2 F gives exactly 2 U (scaling by 2 is exact)
+    q = h6.Queue(plans, restart=30, lanes=2)
+    U1 = [torch.full_like(F, float("nan")) for F in Fs]
+    U2 = [torch.full_like(F, float("nan")) for F in Fs]
+    i1 = q.solve(Fs, U1, tol=1e-8, maxit=400)
+    i2 = q.solve([2.0 * F for F in Fs], U2, tol=1e-8, maxit=400)
+    q.close()
+    for a, b, x, y in zip(i1, i2, U1, U2):
+        assert a["iters"] == b["iters"] and torch.equal(y, 2.0 * x)
     # F = 0 and a three-step budget, beside a normal solve of the same shape
     p0, F0 = make(h6, insts[0])
     p1, F1 = make(h6, insts[0])
