@@ -19,7 +19,7 @@ ARCH = os.environ.get("H6_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "solve.cpp", "stencil.hip", "precond.hip", "xform_rader.hip", "xform_dense.hip",
            "krylov.hip",
-           "rhs.hip", "unet.hip", "queue.hip"]
+           "rhs.hip", "unet.hip", "queue.hip", "xform_bluestein.hip"]
 
 # Packed FP32 instructions are disabled for every device pass.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

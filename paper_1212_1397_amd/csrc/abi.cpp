@@ -104,23 +104,25 @@ std::vector<double> mode_lambdas(const AxisXform& a) {
 }
 
 // Basis matrices of the dense transforms of one axis (xform_dense.hip), in
-// the compute precision R: forward then inverse, each [Lm][Lq] row-major
-// (row m = output, column q = input), zero-padded.  Inverse: W_mq =
-// sin(pi (q+1)(m+1) / M) (sine basis) or cos(pi q m / M) (cosine basis);
-// forward W^{-1} = (2/M) W (sine) or (2/M) C W C, C = diag(1/2, 1, .., 1, 1/2)
-// (cosine).  Angles are reduced modulo 2M in integers.
+// the compute precision R, folded by their reflection symmetry: for the
+// forward then the inverse matrix W, We[j][p] = W[2j][p] (p < ceil(L/2)) and
+// Wo[j][p] = W[2j+1][p] (p < floor(L/2)), each [Hm][Hk] row-major and
+// zero-padded.  Inverse: W_mq = sin(pi (q+1)(m+1) / M) (sine basis) or
+// cos(pi q m / M) (cosine basis); forward W^{-1} = (2/M) W (sine) or
+// (2/M) C W C, C = diag(1/2, 1, .., 1, 1/2) (cosine).  Angles are reduced
+// modulo 2M in integers.
 template <typename T>
 hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s);
 
 template <typename R>
 hipError_t build_dense(AxisXform& ax, hipStream_t s) {
-  const int L = ax.L, M = ax.M;
-  ax.Lm = (L + 63) / 64 * 64;
-  ax.Lq = (L + 15) / 16 * 16;
-  const size_t one = size_t(ax.Lm) * ax.Lq;
-  std::vector<R> h(2 * one, R(0));
+  const int L = ax.L, M = ax.M, h = L / 2, H = L - h;
+  ax.Hm = (H + 31) / 32 * 32;
+  ax.Hk = (H + 15) / 16 * 16;
+  const size_t one = size_t(ax.Hm) * ax.Hk;
+  std::vector<R> hv(4 * one, R(0));     // [direction][parity][Hm][Hk]
   for (int m = 0; m < L; ++m)
-    for (int q = 0; q < L; ++q) {
+    for (int q = 0; q < ((m & 1) ? h : H); ++q) {
       double inv, fwd;
       if (!ax.neumann) {
         const long long t = (long long)(q + 1) * (m + 1) % (2 * M);
@@ -132,11 +134,12 @@ hipError_t build_dense(AxisXform& ax, hipStream_t s) {
         const double cq = (q == 0 || q == L - 1) ? 0.5 : 1.0, sm = (m == 0 || m == L - 1) ? 0.5 : 1.0;
         fwd = (2.0 / M) * sm * cq * inv;
       }
-      h[size_t(m) * ax.Lq + q] = R(fwd);
-      h[one + size_t(m) * ax.Lq + q] = R(inv);
+      const size_t at = size_t(m & 1) * one + size_t(m >> 1) * ax.Hk + q;
+      hv[at] = R(fwd);
+      hv[2 * one + at] = R(inv);
     }
   R* d = nullptr;
-  const hipError_t e = upload(&d, h, s);
+  const hipError_t e = upload(&d, hv, s);
   ax.wmat = d;
   return e;
 }
@@ -192,6 +195,88 @@ bool factor_modes(h6_plan P, const std::vector<double>& lx, const std::vector<do
       }
     }
   return false;
+}
+
+// Tables of the Bluestein path (xform_bluestein.hip) for odd M <= 255:
+// c_q = exp(-i pi q^2 / M) (q^2 taken mod 2M, the period of c), the spectrum
+// FFT_P(b) / P of b_j = conj(c_j) for |j| < M laid out cyclically (computed as
+// a plain DFT in long double), the FFT twiddles and sin / cos(pi q / M), in
+// double and in single precision, in one device allocation.
+hipError_t build_bluestein(AxisXform& ax, hipStream_t s) {
+  const int M = ax.M, P = bluestein_length(M);
+  std::vector<double2> chirp(M), bhat(P), tw(P);
+  std::vector<double> sq(M), cq(M);
+  std::vector<std::complex<long double>> b(P, 0.0L);
+  for (int q = 0; q < M; ++q) {
+    const long double ang = -M_PIl * (long double)((long long)q * q % (2LL * M)) / M;
+    chirp[q] = make_double2(double(cosl(ang)), double(sinl(ang)));
+    const std::complex<long double> bj(cosl(ang), -sinl(ang));      // conj(c_q)
+    b[q] = bj;
+    if (q > 0) b[P - q] = bj;
+    sq[q] = std::sin(M_PI * q / M);
+    cq[q] = std::cos(M_PI * q / M);
+  }
+  for (int k = 0; k < P; ++k) {
+    std::complex<long double> acc = 0.0L;
+    for (int j = 0; j < P; ++j) {
+      if (b[j] == std::complex<long double>(0.0L)) continue;
+      const long double ang = -2.0L * M_PIl * (long double)((long long)j * k % P) / P;
+      acc += b[j] * std::complex<long double>(cosl(ang), sinl(ang));
+    }
+    bhat[k] = make_double2(double(acc.real() / P), double(acc.imag() / P));
+  }
+  for (int t = 0; t < P; ++t)
+    tw[t] = make_double2(std::cos(-2.0 * M_PI * t / P), std::sin(-2.0 * M_PI * t / P));
+  // layout (16-byte aligned pieces)
+  auto al = [](size_t x) { return (x + 15) / 16 * 16; };
+  const size_t o_ch = 0, o_bh = o_ch + al(M * sizeof(double2)), o_tw = o_bh + al(P * sizeof(double2));
+  const size_t o_s = o_tw + al(P * sizeof(double2)), o_c = o_s + al(M * sizeof(double));
+  const size_t o_chf = o_c + al(M * sizeof(double)), o_bhf = o_chf + al(M * sizeof(float2));
+  const size_t o_twf = o_bhf + al(P * sizeof(float2)), o_sf = o_twf + al(P * sizeof(float2));
+  const size_t o_cf = o_sf + al(M * sizeof(float)), bytes = o_cf + al(M * sizeof(float));
+  std::vector<char> host(bytes, 0);
+  auto put = [&](size_t off, const void* src, size_t n) { std::memcpy(host.data() + off, src, n); };
+  std::vector<float2> chf(M), bhf(P), twf(P);
+  std::vector<float> sf(M), cf(M);
+  for (int q = 0; q < M; ++q) {
+    chf[q] = make_float2(float(chirp[q].x), float(chirp[q].y));
+    sf[q] = float(sq[q]);
+    cf[q] = float(cq[q]);
+  }
+  for (int k = 0; k < P; ++k) {
+    bhf[k] = make_float2(float(bhat[k].x), float(bhat[k].y));
+    twf[k] = make_float2(float(tw[k].x), float(tw[k].y));
+  }
+  put(o_ch, chirp.data(), M * sizeof(double2));
+  put(o_bh, bhat.data(), P * sizeof(double2));
+  put(o_tw, tw.data(), P * sizeof(double2));
+  put(o_s, sq.data(), M * sizeof(double));
+  put(o_c, cq.data(), M * sizeof(double));
+  put(o_chf, chf.data(), M * sizeof(float2));
+  put(o_bhf, bhf.data(), P * sizeof(float2));
+  put(o_twf, twf.data(), P * sizeof(float2));
+  put(o_sf, sf.data(), M * sizeof(float));
+  put(o_cf, cf.data(), M * sizeof(float));
+  char* mem = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&mem), bytes);
+  if (e != hipSuccess) return e;
+  ax.blue_mem = mem;
+  e = hipMemcpyAsync(mem, host.data(), bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  BluesteinTables& t = ax.blue;
+  t.M = M;
+  t.P = P;
+  t.chirp = reinterpret_cast<const double2*>(mem + o_ch);
+  t.bhat = reinterpret_cast<const double2*>(mem + o_bh);
+  t.tw = reinterpret_cast<const double2*>(mem + o_tw);
+  t.sin_q = reinterpret_cast<const double*>(mem + o_s);
+  t.cos_q = reinterpret_cast<const double*>(mem + o_c);
+  t.chirp_f = reinterpret_cast<const float2*>(mem + o_chf);
+  t.bhat_f = reinterpret_cast<const float2*>(mem + o_bhf);
+  t.tw_f = reinterpret_cast<const float2*>(mem + o_twf);
+  t.sin_f = reinterpret_cast<const float*>(mem + o_sf);
+  t.cos_f = reinterpret_cast<const float*>(mem + o_cf);
+  return e;
 }
 
 // Tables of the Rader path for a prime M with M - 1 = 256 (xform_rader.hip).
@@ -290,6 +375,7 @@ void free_plan(h6_plan P) {
   if (P->gstream) (void)hipStreamDestroy(P->gstream);
   if (P->ev_order) (void)hipEventDestroy(P->ev_order);
   for (auto& a : P->ax) (void)hipFree(a.rader_mem);
+  for (auto& a : P->ax) (void)hipFree(a.blue_mem);
   (void)hipFree(P->d_stencil);
   (void)hipFree(P->d_lambda_x);
   (void)hipFree(P->d_lambda_y);
@@ -429,6 +515,10 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
   }
   for (int a = 0; a < 2 && e == hipSuccess; ++a) {
     if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
+    else if (bluestein_ok(P->ax[a].M) && P->ax[a].L <= 256 && !std::getenv("H6_DENSE_TRANSFORMS")) {
+      e = build_bluestein(P->ax[a], s);
+      if (e == hipSuccess) P->ax[a].fast = 2;     // untuned default; the autotuner may pick the dense product
+    }
     P->ax[a].lines = a == 0 ? 4 : 16;     // untuned default: best on gfx950 at 256^3
   }
   const size_t elem = p->precision == H6_MIXED ? sizeof(float2) : sizeof(double2);
@@ -544,9 +634,15 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
       std::snprintf(devname, sizeof devname, "%s", prop.gcnArchName);
   }
   char key[512];
-  std::snprintf(key, sizeof key, "h6tune2 %s %d %d %d %d", devname, P->dims[0], P->dims[1], P->dims[2],
+  std::snprintf(key, sizeof key, "h6tune3 %s %d %d %d %d", devname, P->dims[0], P->dims[1], P->dims[2],
                 P->p.precision);
   const bool can_x = P->ax[0].rader_mem != nullptr, can_y = P->ax[1].rader_mem != nullptr;
+  // transform variant code of the cache (0 dense, 1 Rader, 2 Bluestein) -> the variants this plan has
+  auto fast_code = [&](int ax, int code) {
+    if (code == 1 && P->ax[ax].rader_mem) return 1;
+    if (code == 2 && P->ax[ax].blue_mem) return 2;
+    return 0;
+  };
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[600];
@@ -559,8 +655,8 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
             (tz == 8 || tz == 16 || tz == 32) && rader_lines_ok(0, xl) && rader_lines_ok(1, yl)) {
           std::fclose(f);
           P->stencil_tz = tz;
-          P->ax[0].fast = can_x && xf;
-          P->ax[1].fast = can_y && yf;
+          P->ax[0].fast = fast_code(0, xf);
+          P->ax[1].fast = fast_code(1, yf);
           P->ax[0].lines = xl;
           P->ax[1].lines = yl;
           return H6_OK;
@@ -626,6 +722,15 @@ h6_status autotune(h6_plan P, const char* cache_path, hipStream_t s) {
     }
     P->ax[ax].fast = best_lines ? 1 : 0;
     P->ax[ax].lines = best_lines ? best_lines : (ax == 0 ? 4 : 16);
+  }
+  // the Bluestein path against the dense product (odd M <= 255)
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!P->ax[ax].blue_mem) continue;
+    P->ax[ax].fast = 0;
+    const double dense = time_it([&] { (void)launch_pinv(P, x, y, s); });
+    P->ax[ax].fast = 2;
+    const double blue = time_it([&] { (void)launch_pinv(P, x, y, s); });
+    P->ax[ax].fast = blue <= dense ? 2 : 0;
   }
   P->timing.enabled = timing;
   const hipError_t err = hipStreamSynchronize(s);

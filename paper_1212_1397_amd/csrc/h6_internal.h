@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/helmholtz6.h"
+#include "xform_bluestein.h"
 #include "xform_rader.h"
 
 namespace h6 {
@@ -51,12 +52,14 @@ struct AxisXform {
   int L = 0;        // unknowns on the axis (n for D, n + 2 for N)
   int M = 0;        // n + 1
   int neumann = 0;  // 0: DST-I pair, 1: DCT-I pair
-  int fast = 0;     // 1: Rader FFT path (M = 257), 0: dense sums in LDS
+  int fast = 0;     // 1: Rader FFT path (M = 257), 2: Bluestein FFT path (odd M <= 255), 0: dense product
   int lines = 0;    // Rader path: lines (x) / columns (y) per workgroup (autotuned)
-  void* wmat = nullptr;   // dense path: forward then inverse basis matrix, [Lm][Lq] each
-  int Lm = 0, Lq = 0;     // padded rows (multiple of 64) and columns (multiple of 16)
+  void* wmat = nullptr;   // dense path: folded basis matrices We, Wo of the forward, then of the inverse
+  int Hm = 0, Hk = 0;     // their padded rows (multiple of 32) and columns (multiple of 16)
   RaderTables rader{};
   void* rader_mem = nullptr;   // one device allocation holding the tables
+  BluesteinTables blue{};
+  void* blue_mem = nullptr;    // one device allocation holding the Bluestein tables
 };
 
 // End rows of T_z for the z solver.  T_z is tridiag(1, -2, 1) inside; row 0

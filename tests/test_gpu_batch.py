@@ -210,7 +210,7 @@ def test_sks_after_stencil_depth_change(h6, tmp_path):
     for tz in (32, 8, 16):
         path = os.path.join(tmp_path, f"tune_tz{tz}.txt")
         with open(path, "w") as f:
-            f.write(f"h6tune2 {arch} {nx} {ny} {nz} 1 tz={tz} xfast=0 yfast=0 xlines=4 ylines=16\n")
+            f.write(f"h6tune3 {arch} {nx} {ny} {nz} 1 tz={tz} xfast=0 yfast=0 xlines=4 ylines=16\n")
         plan.autotune(path)
         U, info = plan.solve(F, method="sks", tol=w.tol, maxit=200)
         assert info["status"] == "ok", (tz, info)
@@ -230,7 +230,7 @@ def test_autotune_keeps_results_and_caches(h6, tmp_path):
     cache = os.path.join(tmp_path, "tune.txt")
     plan.autotune(cache)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("h6tune2 ")
+    assert len(lines) == 1 and lines[0].startswith("h6tune3 ")
     print(lines[0], flush=True)
     assert torch.equal(plan.apply_A(x), y0)      # the stencil variants differ only in the launch shape
     z1 = plan.apply_Pinv(x)
@@ -257,7 +257,7 @@ def test_transform_workgroup_widths_agree(h6, tmp_path, precision):
     for xl, yl in [(8, 8), (8, 16), (4, 8), (4, 16)]:
         path = os.path.join(tmp_path, f"tune_{xl}_{yl}.txt")
         with open(path, "w") as f:
-            f.write(f"h6tune2 {arch} {nx} {ny} {nz} {pnum} tz=16 xfast=1 yfast=1 xlines={xl} ylines={yl}\n")
+            f.write(f"h6tune3 {arch} {nx} {ny} {nz} {pnum} tz=16 xfast=1 yfast=1 xlines={xl} ylines={yl}\n")
         plan.autotune(path)
         assert torch.equal(plan.apply_Pinv(x), z0), (xl, yl)
 
@@ -273,8 +273,10 @@ def test_cycle_graphs_match_step_solver(h6, precision, method, restart, maxit):
     length of 4 runs the cycle graph many times, maxit = 7 stops inside the
     first cycle.  Within a cycle the estimates agree to 1e-8; after a restart
     the device's rotations and division round differently from the host's,
-    and the solution's O(1e-16) change reaches the next residual amplified by
-    ||U|| / ||F|| (about 1e4 here), hence 1e-4 on the estimates overall."""
+    and the solution's O(1e-16) relative change reaches the next residual as
+    about 1e-16 ||A|| ||U|| (||A|| ||U|| / ||F|| is about 1e4 here): relative
+    to an estimate rho ||F|| that is 1e-12 / rho, 2.5e-4 at the last estimate
+    (rho = 4e-9), hence 5e-4 on the estimates overall."""
     import numpy as np
     w = WORKLOADS["dns-128"]
     plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=precision)
@@ -290,7 +292,7 @@ def test_cycle_graphs_match_step_solver(h6, precision, method, restart, maxit):
         print(f"rep {rep}: {i1['iters']} steps ({i0['iters']}), {i1['status']}", flush=True)
         assert i1["iters"] == i0["iters"] and i1["status"] == i0["status"], rep
         np.testing.assert_allclose(i1["history"][:restart], i0["history"][:restart], rtol=1e-8)
-        np.testing.assert_allclose(i1["history"], i0["history"], rtol=1e-4)
+        np.testing.assert_allclose(i1["history"], i0["history"], rtol=5e-4)
         assert float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0)) < 1e-9, rep
         del junk
     plan.set_graphs(0)
