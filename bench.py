@@ -39,9 +39,9 @@ synchronisations.  The process prints one JSON line:
                        the 96-problem batch (batched + graphs + autotuned vs
                        sequential plain solves), and `operators`: the GPU's
                        apply_A and apply_Pinv (FP64 and mixed plans) on the
-                       128^3 and 256^3 workloads, and `dense_transform`: the
-                       matrix-core transform passes at 128^3 (M = 129) in
-                       TFLOP/s against the FP32 matrix peak.
+                       128^3 and 256^3 workloads, and `transforms_dns128`:
+                       the transform passes at 128^3 (M = 129) on the folded
+                       dense product and on the chirp-z FFT path.
 """
 from __future__ import annotations
 
@@ -183,39 +183,55 @@ def gpu_operator_times(reps: int = 10):
     return out
 
 
-def dense_transform_roofline(reps: int = 20):
-    """The matrix-core dense transforms (every M without a fast path) on the
-    128^3 workload (M = 129), complex64 plan: average launch time of the x and
-    y passes inside apply_Pinv (library HIP events) and their throughput,
-    4 L flop per element (a real L x L matrix applied to re and im), against
-    the FP32 matrix-core peak."""
+def transform_paths_dns128(reps: int = 20):
+    """The transform passes at 128^3 (M = 129 on both axes), complex64 and
+    complex128 plans, on each path the autotuner chooses from: the folded
+    dense product on the matrix cores (H6_DENSE_TRANSFORMS at setup) and the
+    chirp-z FFT path.  Per pass: average launch time inside apply_Pinv
+    (library HIP events, forward and inverse launches together), the
+    library's algorithmic bytes per launch over that time against 8 TB/s,
+    and for the dense product its matrix-core rate (2 L flop per element:
+    the two half-size real matrices applied to re and im) against the
+    matrix peak of the precision."""
     import torch
     from paper_1212_1397_amd import helmholtz6 as h6
     from paper_1212_1397_amd.workloads import WORKLOADS
     w = WORKLOADS["dns-128"]
-    plan = h6.Plan(w.n, w.h, w.k, w.bc, precision="mixed")
-    g = torch.Generator(device="cuda").manual_seed(6)
-    x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda", generator=g)
-    y = torch.empty_like(x)
-    plan.apply_Pinv(x, y)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    for cls in ("xform_x", "xform_y"):
-        plan.kernel_time(cls, reset=True)
-    for _ in range(reps):
-        plan.apply_Pinv(x, y)
-    torch.cuda.synchronize()
-    N = plan.dims[0] * plan.dims[1] * plan.dims[2]
-    out = {"workload": w.name, "grid_unknowns": list(plan.dims), "precision": "complex64 (FP32 MFMA)",
-           "peak_tflops": 157.3}
-    for cls, L in (("xform_x", plan.dims[0]), ("xform_y", plan.dims[1])):
-        ms, n, _ = plan.kernel_time(cls)
-        us = ms * 1e3 / max(n, 1)
-        tf = 4.0 * L * N / (us * 1e-6) / 1e12
-        out[cls] = {"line_length": L, "avg_us": round(us, 2), "tflops": round(tf, 1),
-                    "frac": round(tf / 157.3, 4), "launches": n}
-    plan.profile(False)
-    plan.close()
+    out = {"workload": w.name}
+    for prec, peak in (("mixed", 157.3), ("fp64", 78.6)):
+        for path in ("dense", "chirp-z"):
+            if path == "dense":
+                os.environ["H6_DENSE_TRANSFORMS"] = "1"
+            try:
+                plan = h6.Plan(w.n, w.h, w.k, w.bc, precision=prec)
+            finally:
+                os.environ.pop("H6_DENSE_TRANSFORMS", None)
+            g = torch.Generator(device="cuda").manual_seed(6)
+            x = torch.randn(plan.shape, dtype=torch.complex128, device="cuda", generator=g)
+            y = torch.empty_like(x)
+            plan.apply_Pinv(x, y)
+            torch.cuda.synchronize()
+            plan.profile(True)
+            for cls in ("xform_x", "xform_y"):
+                plan.kernel_time(cls, reset=True)
+            for _ in range(reps):
+                plan.apply_Pinv(x, y)
+            torch.cuda.synchronize()
+            N = plan.dims[0] * plan.dims[1] * plan.dims[2]
+            res = {"grid_unknowns": list(plan.dims)}
+            for cls, L in (("xform_x", plan.dims[0]), ("xform_y", plan.dims[1])):
+                ms, n, byts = plan.kernel_time(cls)
+                us = ms * 1e3 / max(n, 1)
+                gbs = byts / max(n, 1) / (us * 1e-6) / 1e9
+                r = {"line_length": L, "avg_us": round(us, 2), "GB_s": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "launches": n}
+                if path == "dense":
+                    tf = 2.0 * L * N / (us * 1e-6) / 1e12
+                    r.update({"tflops": round(tf, 1), "frac_matrix_peak": round(tf / peak, 4)})
+                res[cls] = r
+            plan.profile(False)
+            plan.close()
+            out[f"{prec}/{path}"] = res
     return out
 
 
@@ -434,7 +450,7 @@ def main():
         extra["batch"] = batch.run()
     if not args.no_extra:
         extra["operators"] = gpu_operator_times()
-        extra["dense_transform"] = dense_transform_roofline()
+        extra["transforms_dns128"] = transform_paths_dns128()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -52,7 +52,9 @@ typedef struct h6_net_s* h6_net;
 /* Number of FP32 parameters (weights and biases of all layers). */
 long long h6net_param_count(void);
 
-/* Creates a network for grids of dims = {n'x, n'y, n'z} (each >= 1) and
+/* Creates a network for grids of dims = {n'x, n'y, n'z} (each >= 1, with
+ * 48 n'x n'y n'z < 2^31, i.e. up to about 350^3 unknowns: the convolutions
+ * address activations with 32-bit offsets; H6_ERR_ARG beyond) and
  * allocates its inference buffers (training buffers on the first training
  * call).  Parameters start at zero; set them with h6net_set_params.
  * hip_stream: stream for the set-up work.  On failure *out is NULL. */

@@ -107,7 +107,7 @@ std::vector<double> mode_lambdas(const AxisXform& a) {
 // the compute precision R, folded by their reflection symmetry: for the
 // forward then the inverse matrix W, We[j][p] = W[2j][p] (p < ceil(L/2)) and
 // Wo[j][p] = W[2j+1][p] (p < floor(L/2)), each [Hm][Hk] row-major and
-// zero-padded.  Inverse: W_mq = sin(pi (q+1)(m+1) / M) (sine basis) or
+// zero-padded (Hm a multiple of 32, Hk of kDenseKChunk).  Inverse: W_mq = sin(pi (q+1)(m+1) / M) (sine basis) or
 // cos(pi q m / M) (cosine basis); forward W^{-1} = (2/M) W (sine) or
 // (2/M) C W C, C = diag(1/2, 1, .., 1, 1/2) (cosine).  Angles are reduced
 // modulo 2M in integers.
@@ -118,7 +118,7 @@ template <typename R>
 hipError_t build_dense(AxisXform& ax, hipStream_t s) {
   const int L = ax.L, M = ax.M, h = L / 2, H = L - h;
   ax.Hm = (H + 31) / 32 * 32;
-  ax.Hk = (H + 15) / 16 * 16;
+  ax.Hk = (H + kDenseKChunk - 1) / kDenseKChunk * kDenseKChunk;
   const size_t one = size_t(ax.Hm) * ax.Hk;
   std::vector<R> hv(4 * one, R(0));     // [direction][parity][Hm][Hk]
   for (int m = 0; m < L; ++m)

@@ -46,6 +46,10 @@ enum KernelClass {
 };
 extern const char* const kKernelClassNames[KC_COUNT];
 
+// K extent staged per step by the dense transform kernels; the folded basis
+// matrices are padded to a multiple of it.
+constexpr int kDenseKChunk = 16;
+
 // Transform along one transverse axis (Section 3.3): a sine basis for a
 // Dirichlet pair, a cosine basis for a Neumann pair; M = n + 1.
 struct AxisXform {
@@ -55,7 +59,7 @@ struct AxisXform {
   int fast = 0;     // 1: Rader FFT path (M = 257), 2: Bluestein FFT path (odd M <= 255), 0: dense product
   int lines = 0;    // Rader path: lines (x) / columns (y) per workgroup (autotuned)
   void* wmat = nullptr;   // dense path: folded basis matrices We, Wo of the forward, then of the inverse
-  int Hm = 0, Hk = 0;     // their padded rows (multiple of 32) and columns (multiple of 16)
+  int Hm = 0, Hk = 0;     // their padded rows (multiple of 32) and columns (multiple of kDenseKChunk)
   RaderTables rader{};
   void* rader_mem = nullptr;   // one device allocation holding the tables
   BluesteinTables blue{};

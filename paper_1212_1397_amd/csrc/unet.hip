@@ -65,106 +65,202 @@ typedef unsigned int u4w __attribute__((ext_vector_type(4)));
 
 // The tiled convolution on the K = 32 instruction: two taps per instruction
 // (lanes 0-31 the first tap's channels of a 16-channel chunk, 32-63 the
-// second's), the input block of one chunk in LDS at a time and the weights of
-// one tap pair of that chunk double-buffered beside it (24-39 KB of LDS).
-// Steps s = (chunk, pair) run in order; the input block is restaged between
-// chunks.
-template <int CIN, int COUTP>
+// second's), the input block of one chunk in LDS and the weight fragments
+// read by each lane straight from the (L2-resident) packed weights into
+// registers a few steps ahead, so the steps s = (chunk, tap pair) run without
+// workgroup barriers; the next chunk's input block is loaded into registers
+// halfway through a chunk and stored to LDS between chunks.
+// Rows (y extent of the block, 16-voxel MFMA rows per wave) of the forward
+// convolution's output block for COUTP output channels: 8 up to 32 channels,
+// 4 above (accumulator registers).
+__host__ __device__ constexpr int conv_rows(int coutp) { return coutp <= 32 ? 8 : 4; }
+
+// voxel offset of tap t (t = dx + 3 dy + 9 dz over -1..1 each, + 13) inside an
+// LDS input block of row length kHX and HY rows per plane
+template <int HY>
+__host__ __device__ constexpr int tap_off(int t) {
+  return (t % 3 - 1) + kHX * ((t / 3) % 3 - 1) + kHX * HY * (t / 9 - 1);
+}
+
+// The tiled convolution on the K = 32 instruction: a workgroup owns a block
+// of 16 x MT x 4 output voxels (wave w: z offset w, MFMA row m: y offset m,
+// 16 voxels along x), two taps per instruction (lanes 0-31 the first tap's
+// channels of a 16-channel chunk, 32-63 the second's).  The input block of
+// one chunk with its one-voxel halo sits in LDS; the weight fragments are
+// read by each lane straight from the (L2-resident) packed weights into
+// registers a few steps ahead, so the steps (chunk, tap pair) run without
+// workgroup barriers; the next chunk's input block is loaded into registers
+// halfway through a chunk and stored to LDS between chunks.  BF16 results go
+// through LDS so that every lane stores 16-byte pieces (8 channels of one
+// voxel).  With CU > 0 the first CU chunks of the input are the nearest-
+// neighbour upsampling of `up` (a grid of half the size, gu): voxel v reads
+// up[v / 2], so the decoder's concatenated input is never materialised; the
+// remaining chunks come from `in`.  (Workgroups that march over several z blocks, reusing the x-y
+// part of the gather offsets, measured slower: the compiler keeps more
+// registers live across the march.)
+template <int CIN, int COUTP, int CU>
 __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16* __restrict__ W,
                                                             const float* __restrict__ bias, View out,
                                                             float* __restrict__ out32, int cout, int relu,
-                                                            Grid3 g, int ntx, int nty) {
-  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = 4;
-  constexpr int NP = 14, NS = KC * NP;               // tap pairs per chunk, steps
-  constexpr int RS = 16 + 8;                          // weight row stride (bf16): 16-byte aligned rows
-  constexpr int HV = kHX * kHY * kHZ;
-  __shared__ __attribute__((aligned(16))) bf16 xs[HV][16];
-  __shared__ __attribute__((aligned(16))) bf16 ws[2][2][COUTP * RS];
+                                                            Grid3 g, int ntx, int nty, View up, Grid3 gu) {
+  constexpr int NT = COUTP / 16, KC = CIN / 16, MT = conv_rows(COUTP), HY = MT + 2;
+  constexpr int NP = 14;                              // tap pairs per chunk (the last one: tap 26 + zeros)
+  constexpr int HV = kHX * HY * kHZ;
+  constexpr int NPIECE = HV * 4, NPER = (NPIECE + 255) / 256;   // 8-byte pieces of an input block
+  constexpr size_t TAPW = size_t(COUTP) * CIN;        // weights per tap
+  constexpr int OV = 16 * MT;                         // output voxels per wave
+  constexpr int LDS_IN = HV * 32, LDS_OUT = 4 * OV * COUTP * 2;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
+  bf16 (*xs)[16] = reinterpret_cast<bf16 (*)[16]>(lds);
   const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
   const int i = l & 15, half = (l >> 4) & 1, second = l >> 5;
   const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
-  const int x0 = bx * kTX, y0 = by * kTY, z0 = bz * kTZ;
-  // input block with halo of chunk kc: every global load issued before the first LDS store
-  auto stage_x = [&](int kc) {
-    constexpr int NPIECE = HV * 4, NPER = (NPIECE + 255) / 256;
-    s4 val[NPER];
+  const int x0 = bx * kTX, y0 = by * MT, z0 = bz * kTZ;
+  // gather offsets of this thread's pieces of the input block (element offsets
+  // of channel 4 q of the source's first chunk; -1 outside the grid), the
+  // same for every chunk of one source; sh = 1: voxel v of the grid reads
+  // voxel v / 2 of the source
+  int goff[NPER];
+  auto set_offsets = [&](const View& v, Grid3 gs, int sh) {
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
       const int idx = tid + 256 * k;
       const int q = idx & 3, hv = idx >> 2;
-      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int hx = hv % kHX, hy = (hv / kHX) % HY, hz = hv / (kHX * HY);
       const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
       const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
-      const long long v = inside ? gx + (long long)g.X * (gy + (long long)g.Y * gz) : 0;
-      val[k] = *reinterpret_cast<const s4*>(in.p + v * in.cs + in.coff + (inside ? 16 * kc + 4 * q : 0));
-      if (!inside) val[k] = s4{0, 0, 0, 0};
+      goff[k] = inside ? ((gx >> sh) + gs.X * ((gy >> sh) + gs.Y * (gz >> sh))) * v.cs + v.coff + 4 * q : -1;
     }
+  };
+  s4 xv[NPER];
+  auto load_x = [&](int kc) {      // chunk kc of the input (channels 16 kc .. 16 kc + 15)
+    const bf16* src = (CU > 0 && kc < CU) ? up.p : in.p;
+    const int c0 = 16 * ((CU > 0 && kc >= CU) ? kc - CU : kc);
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      xv[k] = *reinterpret_cast<const s4*>(src + (goff[k] >= 0 ? goff[k] + c0 : 0));
+      if (goff[k] < 0) xv[k] = s4{0, 0, 0, 0};
+    }
+  };
+  if (CU > 0)
+    set_offsets(up, gu, 1);
+  else
+    set_offsets(in, g, 0);
+  auto store_x = [&]() {
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
       const int idx = tid + 256 * k;
-      if (idx < NPIECE) *reinterpret_cast<s4*>(&xs[idx >> 2][4 * (idx & 3)]) = val[k];
+      if (idx < NPIECE) *reinterpret_cast<s4*>(&xs[idx >> 2][4 * (idx & 3)]) = xv[k];
     }
   };
-  // weights of step st: taps 2p, 2p + 1 (zero past tap 26), channels of chunk kc
-  auto stage_w = [&](int st, int b) {
-    const int kc = st / NP, tp = 2 * (st % NP);
-    for (int idx = tid; idx < 2 * COUTP * 4; idx += 256) {
-      const int q = idx & 3, co = (idx >> 2) % COUTP, u = (idx >> 2) / COUTP, tap = tp + u;
-      s4 val = s4{0, 0, 0, 0};
-      if (tap < 27) val = *reinterpret_cast<const s4*>(W + ((size_t)tap * COUTP + co) * CIN + 16 * kc + 4 * q);
-      *reinterpret_cast<s4*>(&ws[b][u][co * RS + 4 * q]) = val;
-    }
-  };
-  f4 acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
-  stage_x(0);
-  stage_w(0, 0);
-  __syncthreads();
-  for (int st = 0; st < NS; ++st) {
-    const int b = st & 1, p = st % NP;
-    if (st + 1 < NS) stage_w(st + 1, b ^ 1);
-    const int tp = 2 * p;
-    const int tc = tp + second < 27 ? tp + second : 26;     // tap 27 reads tap 26's input, zero weights
-    const int dz = tc / 9 - 1, dy = (tc / 3) % 3 - 1, dx = tc % 3 - 1;
-    bf8v a[MT];
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int hv = (i + 1 + dx) + kHX * ((m + 1 + dy) + kHY * (wave + 1 + dz));
-      a[m] = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w*>(&xs[hv][8 * half]));
-    }
+  // B fragments: lane (i, half, second) holds channels 16 kc + 8 half .. + 7 of
+  // output channel 16 t + i for tap 2 pp + second; tap 27 (pp = 13, second
+  // lanes) reads tap 26 and is zeroed
+  const int wlo = (second * COUTP + i) * CIN + 8 * half;
+  auto load_b = [&](int kc, int pp, u4w (&bf)[NT]) {
+    const bf16* wk = W + 2 * pp * TAPW + 16 * kc;
+    const int lo = wlo - ((pp == NP - 1 && second) ? int(TAPW) : 0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const bf8v bfr = __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w*>(&ws[b][second][(t * 16 + i) * RS + 8 * half]));
-#pragma unroll
-      for (int m = 0; m < MT; ++m) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bfr, acc[m][t], 0, 0, 0);
+      bf[t] = *reinterpret_cast<const u4w*>(wk + lo + 16 * t * CIN);
+      if (pp == NP - 1 && second) bf[t] = u4w{0u, 0u, 0u, 0u};
     }
+  };
+  // LDS row of the lane's A fragment at tap offset 0: voxel (i + 1, m + 1, wave + 1)
+  const int abase = (i + 1) + kHX * (1 + HY * (wave + 1));
+  constexpr int D = NT == 1 ? 6 : (NT == 2 ? 4 : 2);    // weight fragments are loaded D steps ahead
+  {
+    load_x(0);
+    f4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.f, 0.f, 0.f, 0.f};
+    u4w bq[NP][NT];
+#pragma unroll
+    for (int j = 0; j < D; ++j) load_b(0, j, bq[j]);
+    store_x();
     __syncthreads();
-    if (KC > 1 && p == NP - 1 && st + 1 < NS) {      // next chunk: restage the input block
-      stage_x(st / NP + 1);
-      __syncthreads();
-    }
-  }
-  const int oz = z0 + wave;
+    for (int kc = 0; kc < KC; ++kc) {
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int oy = y0 + m;
+      for (int pp = 0; pp < NP; ++pp) {
+        if (pp + D < NP) load_b(kc, pp + D, bq[pp + D]);
+        else if (kc + 1 < KC) load_b(kc + 1, pp + D - NP, bq[pp + D - NP]);
+        if (KC > 1 && pp == NP / 2 && kc + 1 < KC) {
+          if (CU > 0 && kc + 1 == CU) set_offsets(in, g, 0);      // the rest of the input comes from `in`
+          load_x(kc + 1);
+        }
+        // taps 2 pp (lanes 0-31) and 2 pp + 1 (lanes 32-63; tap 27 reads tap 26's input)
+        const int off = second ? tap_off<HY>(2 * pp + 1 < 27 ? 2 * pp + 1 : 26) : tap_off<HY>(2 * pp);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const bf8v a =
+              __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w*>(&xs[abase + off + kHX * m][8 * half]));
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf8v, bq[pp][t]),
+                                                                acc[m][t], 0, 0, 0);
+        }
+      }
+      if (kc + 1 < KC) {      // next chunk: its input block replaces this one
+        __syncthreads();
+        store_x();
+        __syncthreads();
+      }
+    }
+    const int oz = z0 + wave, oxb = x0 + 4 * (l >> 4);
+    if (out32) {
+      if (oz < g.Z) {
+        const long long vz = (long long)g.X * g.Y * oz;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int oy = y0 + m;
+          if (oy >= g.Y) continue;
+          const long long vm = vz + (long long)g.X * oy + oxb;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + i;
+            if (co >= cout) continue;
+            const float bc = bias ? bias[co] : 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              if (oxb + e >= g.X) continue;
+              float val = acc[m][t][e] + bc;
+              if (relu) val = fmaxf(val, 0.f);
+              out32[(vm + e) * 2 + co] = val;
+            }
+          }
+        }
+      }
+      return;
+    }
+    // BF16 results of this wave to LDS as [voxel x + 16 m][channel], then 16-byte pieces to memory
+    __syncthreads();                                  // every wave is done with the input block
+    bf16* ost = reinterpret_cast<bf16*>(lds) + wave * (OV * COUTP);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + i;
+      const float bc = bias ? bias[co] : 0.f;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ox = x0 + 4 * (l >> 4) + e;
-        if (ox >= g.X || oy >= g.Y || oz >= g.Z || co >= cout) continue;
-        const long long vo = ox + (long long)g.X * (oy + (long long)g.Y * oz);
-        float val = acc[m][t][e] + (bias ? bias[co] : 0.f);
-        if (relu) val = fmaxf(val, 0.f);
-        if (out32)
-          out32[vo * 2 + co] = val;
-        else
-          out.p[vo * out.cs + out.coff + co] = f2bf(val);
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float val = acc[m][t][e] + bc;
+          if (relu) val = fmaxf(val, 0.f);
+          ost[(4 * (l >> 4) + e + 16 * m) * COUTP + co] = f2bf(val);
+        }
+    }
+    __syncthreads();
+    if (oz < g.Z) {
+      constexpr int C8 = COUTP / 8;
+      const long long vz = (long long)g.X * g.Y * oz;
+#pragma unroll
+      for (int k = l; k < OV * C8; k += 64) {
+        const int v = k / C8, c8 = k - v * C8;
+        const int x = x0 + (v & 15), y = y0 + (v >> 4);
+        if (x < g.X && y < g.Y && 8 * c8 < cout)
+          *reinterpret_cast<u4w*>(out.p + (vz + (long long)g.X * y + x) * out.cs + out.coff + 8 * c8) =
+              *reinterpret_cast<const u4w*>(ost + v * COUTP + 8 * c8);
       }
     }
   }
@@ -644,19 +740,33 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 #define H6_CONV_CASES(X) \
   X(16, 16) X(16, 32) X(16, 48) X(48, 16) X(96, 32) X(64, 32) X(32, 32) X(32, 64) X(32, 96) X(32, 16) X(64, 64)
+// decoder layers whose first `cu` input chunks are the upsampled coarser level
+#define H6_CONV_UP_CASES(X) X(96, 32, 4) X(48, 16, 2)
 
+// out = act(conv(in)); with cu > 0 the first cu 16-channel chunks of the input are
+// the nearest-neighbour upsampling of `up` (grid gu = half(g)) and the rest come from `in`
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
-                int cout, int relu, Grid3 g, hipStream_t s) {
-  const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + kTY - 1) / kTY, ntz = (g.Z + kTZ - 1) / kTZ;
+                int cout, int relu, Grid3 g, hipStream_t s, View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0},
+                int cu = 0) {
+  const int rows = conv_rows(coutp);
+  const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + rows - 1) / rows, ntz = (g.Z + kTZ - 1) / kTZ;
   const unsigned grid = unsigned(ntx) * nty * ntz;
-#define H6_CONV(CI, CO)                                                                              \
-  if (cinp == CI && coutp == CO) {                                                                   \
-    hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO>), dim3(grid), dim3(256), 0, s, in, W, bias, out, \
-                       out32, cout, relu, g, ntx, nty);                                              \
-    return hipGetLastError();                                                                        \
+#define H6_CONV(CI, CO)                                                                                   \
+  if (cu == 0 && cinp == CI && coutp == CO) {                                                             \
+    hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, 0>), dim3(grid), dim3(256), 0, s, in, W, bias, out,  \
+                       out32, cout, relu, g, ntx, nty, up, gu);                                           \
+    return hipGetLastError();                                                                             \
   }
   H6_CONV_CASES(H6_CONV)
 #undef H6_CONV
+#define H6_CONV_UP(CI, CO, CUP)                                                                             \
+  if (cu == CUP && cinp == CI && coutp == CO) {                                                             \
+    hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, CUP>), dim3(grid), dim3(256), 0, s, in, W, bias, out, \
+                       out32, cout, relu, g, ntx, nty, up, gu);                                             \
+    return hipGetLastError();                                                                               \
+  }
+  H6_CONV_UP_CASES(H6_CONV_UP)
+#undef H6_CONV_UP
   return hipErrorInvalidValue;
 }
 
@@ -703,13 +813,18 @@ hipError_t wgrad(View dz, View xin, int cinp, int coutp, float* part, float* bpa
 View vw(bf16* p, int cs, int coff = 0) { return View{p, cs, coff}; }
 
 // one layer: out = act(conv(in)) with the layer's packed weights
-hipError_t layer_fwd(h6_net N, int L, View in, View out, float* out32, Grid3 g, hipStream_t s) {
+hipError_t layer_fwd(h6_net N, int L, View in, View out, float* out32, Grid3 g, hipStream_t s,
+                     View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0}, int cu = 0) {
   const LayerDef& d = kLayers[L];
   return conv(in, r16(d.cin), N->wf[L], r16(d.cout), N->w32 + N->off[L] + (long long)d.cout * d.cin * 27,
-              out, out32, d.cout, d.relu, g, s);
+              out, out32, d.cout, d.relu, g, s, up, gu, cu);
 }
 
-hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s) {
+// fuse_up (inference): the decoder convolutions read the upsampled coarser
+// level directly instead of the materialised concatenations C2 / C1 (channels
+// 0..63 / 0..31 of those stay unwritten); training keeps them for the
+// weight gradients
+hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s, bool fuse_up = false) {
   const Grid3 g1 = N->g1, g2 = N->g2, g3 = N->g3;
   hipError_t e = launch_norm2(r, size_t(g1.P()), N->partials, N->d_scal, s);
   if (e != hipSuccess) return e;
@@ -726,13 +841,21 @@ hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s) {
                      vw(N->Pl2, 32), g3, 32);
   TRY(layer_fwd(N, B3A, vw(N->Pl2, 32), vw(N->T3, 64), nullptr, g3, s));
   TRY(layer_fwd(N, B3B, vw(N->T3, 64), vw(N->B3, 64), nullptr, g3, s));
-  hipLaunchKernelGGL(up8_kernel, dim3(nblk(g2.P() * 8)), dim3(256), 0, s, vw(N->B3, 64), g3,
-                     vw(N->C2, 96, 0), g2, 64);
-  TRY(layer_fwd(N, D2A, vw(N->C2, 96), vw(N->T2b, 32), nullptr, g2, s));
+  if (fuse_up) {
+    TRY(layer_fwd(N, D2A, vw(N->C2, 96, 64), vw(N->T2b, 32), nullptr, g2, s, vw(N->B3, 64), g3, 4));
+  } else {
+    hipLaunchKernelGGL(up8_kernel, dim3(nblk(g2.P() * 8)), dim3(256), 0, s, vw(N->B3, 64), g3,
+                       vw(N->C2, 96, 0), g2, 64);
+    TRY(layer_fwd(N, D2A, vw(N->C2, 96), vw(N->T2b, 32), nullptr, g2, s));
+  }
   TRY(layer_fwd(N, D2B, vw(N->T2b, 32), vw(N->D2, 32), nullptr, g2, s));
-  hipLaunchKernelGGL(up8_kernel, dim3(nblk(g1.P() * 4)), dim3(256), 0, s, vw(N->D2, 32), g2,
-                     vw(N->C1, 48, 0), g1, 32);
-  TRY(layer_fwd(N, D1A, vw(N->C1, 48), vw(N->T1b, 16), nullptr, g1, s));
+  if (fuse_up) {
+    TRY(layer_fwd(N, D1A, vw(N->C1, 48, 32), vw(N->T1b, 16), nullptr, g1, s, vw(N->D2, 32), g2, 2));
+  } else {
+    hipLaunchKernelGGL(up8_kernel, dim3(nblk(g1.P() * 4)), dim3(256), 0, s, vw(N->D2, 32), g2,
+                       vw(N->C1, 48, 0), g1, 32);
+    TRY(layer_fwd(N, D1A, vw(N->C1, 48), vw(N->T1b, 16), nullptr, g1, s));
+  }
   TRY(layer_fwd(N, D1B, vw(N->T1b, 16), vw(N->D1, 16), nullptr, g1, s));
   TRY(layer_fwd(N, OUT, vw(N->D1, 16), View{nullptr, 0, 0}, N->Y, g1, s));
 #undef TRY
@@ -867,6 +990,12 @@ h6_status h6net_create(const int dims[3], void* hip_stream, h6_net* out) {
   if (!out) return H6_ERR_ARG;
   *out = nullptr;
   if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return H6_ERR_ARG;
+  // the convolutions gather with 32-bit element offsets into the widest
+  // activation buffers (48 channels on the grid, 96 on the half grid)
+  {
+    const Grid3 a{dims[0], dims[1], dims[2]}, b = half(a);
+    if (a.P() * 48 >= (1LL << 31) || b.P() * 96 >= (1LL << 31)) return H6_ERR_ARG;
+  }
   h6_net N = new (std::nothrow) h6_net_s();
   if (!N) return H6_ERR_ALLOC;
   N->g1 = Grid3{dims[0], dims[1], dims[2]};
@@ -929,7 +1058,7 @@ h6_status h6net_get_params(h6_net N, float* params, long long count, void* hip_s
 h6_status h6net_forward(h6_net N, const void* r, double kh, void* c, void* hip_stream) {
   if (!N || !r || !c || r == c) return H6_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (forward(N, static_cast<const double2*>(r), kh, s) != hipSuccess) return H6_ERR_HIP;
+  if (forward(N, static_cast<const double2*>(r), kh, s, true) != hipSuccess) return H6_ERR_HIP;
   hipLaunchKernelGGL(output_kernel, dim3(nblk(N->g1.P())), dim3(256), 0, s, N->Y, N->d_scal, N->g1.P(), c, 0);
   return hipGetLastError() == hipSuccess ? H6_OK : H6_ERR_HIP;
 }
@@ -1051,7 +1180,7 @@ namespace h6 {
 
 // z += correction(q) for the solver (complex64 z in mixed plans)
 hipError_t net_apply_add(h6_net N, const double2* q, double kh, void* z, bool z_f32, hipStream_t s) {
-  hipError_t e = forward(N, q, kh, s);
+  hipError_t e = forward(N, q, kh, s, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(output_kernel, dim3(nblk(N->g1.P())), dim3(256), 0, s, N->Y, N->d_scal, N->g1.P(), z,
                      z_f32 ? 2 : 1);

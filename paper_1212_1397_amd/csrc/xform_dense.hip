@@ -20,9 +20,9 @@
 // v_mfma_f64_16x16x4f64 in complex128 ones).  A workgroup of 4 waves owns the
 // 64 consecutive outputs m = 64 b .. 64 b + 63 (32 even and 32 odd ones, j =
 // 32 b .. 32 b + 31) of 32 lines (x) or 64 columns (y), folding the line
-// halves into u and v as it stages 16-wide K chunks in LDS.  We and Wo are
-// stored zero-padded to [Hm][Hk] (Hm a multiple of 32, Hk of 16), so operand
-// reads of them need no bounds checks.
+// halves into u and v as it stages K chunks in LDS.  We and Wo are stored
+// zero-padded to [Hm][Hk] (Hm a multiple of 32, Hk of the K chunk), so
+// operand reads of them need no bounds checks.
 #include "h6_internal.h"
 
 namespace h6 {
@@ -55,7 +55,11 @@ template <> struct Mma<double> {
 };
 
 constexpr int kT = 64;       // output tile edge
-constexpr int kKC = 16;      // K chunk staged per step
+constexpr int kKC = kDenseKChunk;                  // K chunk staged per step
+constexpr int kXL = (kT / 2) * kKC / 256;          // (line, p) values of a chunk per thread (x)
+constexpr int kWL = kT * kKC / 256;                // W values of a chunk per thread
+constexpr int kYL = kKC * kT / 256;                // (p, column) values of a chunk per thread (y)
+static_assert(kWL == kYL, "the y kernel stages W and data in one loop");
 constexpr int kPad = kKC + 1;
 
 template <typename R, typename Tin, typename Tout>
@@ -80,10 +84,10 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
   // coalesced reads per value, one ascending and one descending along the
   // line) and 64 rows x 16 p of We / Wo (padded: always in bounds); the next
   // chunk's loads are issued before the current chunk's MFMAs
-  R ure[2], uim[2], vre[2], vim[2], wv4[4];
+  R ure[kXL], uim[kXL], vre[kXL], vim[kXL], wv4[kWL];
   auto load = [&](int p0) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kXL; ++j) {
       const int i = tid + 256 * j;
       const int ll = i / kKC, pp = i % kKC;
       const int line = line0 + ll, p = p0 + pp;
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
       }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kWL; ++j) {
       const int i = tid + 256 * j;
       const int r = i / kKC;
       wv4[j] = W[(size_t(r >> 5) * Hm + j0 + (r & 31)) * Hk + p0 + i % kKC];
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
   load(0);
   for (int p0 = 0; p0 < H; p0 += kKC) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kXL; ++j) {
       const int i = tid + 256 * j;
       const int ll = i / kKC, pp = i % kKC;
       const int wv = ll >> 3, li = ll & 7;
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(256) void dense_x_kernel(const Tin* __restrict__ in
       Av[16 * wv + M::xrow(li, 1)][pp] = vim[j];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kWL; ++j) {
       const int i = tid + 256 * j;
       Ws[i / kKC][i % kKC] = wv4[j];
     }
@@ -204,10 +208,10 @@ __global__ __launch_bounds__(256) void dense_y_kernel(const R* __restrict__ in, 
   // one K chunk in registers (64 rows x 16 p of We / Wo, 16 rows x 64 columns
   // of u and v from two coalesced plane rows each); the next chunk is loaded
   // during the MFMAs
-  R wv4[4], uv4[4], vv4[4];
+  R wv4[kWL], uv4[kYL], vv4[kYL];
   auto load = [&](int p0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kWL; ++j) {
       const int i = tid + 256 * j;
       const int r = i / kKC;
       wv4[j] = W[(size_t(r >> 5) * Hm + j0 + (r & 31)) * Hk + p0 + i % kKC];
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(256) void dense_y_kernel(const R* __restrict__ in, 
   load(0);
   for (int p0 = 0; p0 < H; p0 += kKC) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kWL; ++j) {
       const int i = tid + 256 * j;
       Ws[i / kKC][i % kKC] = wv4[j];
       Us[i / kT][i % kT] = uv4[j];

@@ -66,6 +66,9 @@ def test_network_rejects_bad_arguments():
     bad = (ctypes.c_int * 3)(0, 4, 4)
     assert h6._lib.h6net_create(bad, None, ctypes.byref(out)) == h6.H6_ERR_ARG
     assert not out.value
+    big = (ctypes.c_int * 3)(400, 400, 400)      # 48 * 400^3 >= 2^31: beyond 32-bit activation offsets
+    assert h6._lib.h6net_create(big, None, ctypes.byref(out)) == h6.H6_ERR_ARG
+    assert not out.value
     assert h6._lib.h6net_forward(None, None, 0.0, None, None) == h6.H6_ERR_ARG
     assert h6._lib.helmholtz6_attach_net(None, None) == h6.H6_ERR_ARG
     loss = ctypes.c_double()
