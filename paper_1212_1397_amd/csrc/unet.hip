@@ -95,14 +95,20 @@ __host__ __device__ constexpr int tap_off(int t) {
 // voxel).  With CU > 0 the first CU chunks of the input are the nearest-
 // neighbour upsampling of `up` (a grid of half the size, gu): voxel v reads
 // up[v / 2], so the decoder's concatenated input is never materialised; the
-// remaining chunks come from `in`.  (Workgroups that march over several z blocks, reusing the x-y
+// remaining chunks come from `in`.  With CU < 0 (first layer, inference) the
+// input is formed on the fly from the residual fr: channels r re / rms,
+// r im / rms, kh (zero for r = 0) and zeros, with rms^2 = *fnrm / voxels
+// (the features of h6net.h), so that array is never materialised.
+// (Workgroups that march over several z blocks, reusing the x-y
 // part of the gather offsets, measured slower: the compiler keeps more
 // registers live across the march.)
 template <int CIN, int COUTP, int CU>
 __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16* __restrict__ W,
                                                             const float* __restrict__ bias, View out,
                                                             float* __restrict__ out32, int cout, int relu,
-                                                            Grid3 g, int ntx, int nty, View up, Grid3 gu) {
+                                                            Grid3 g, int ntx, int nty, View up, Grid3 gu,
+                                                            const double2* __restrict__ fr,
+                                                            const double* __restrict__ fnrm, float fkh) {
   constexpr int NT = COUTP / 16, KC = CIN / 16, MT = conv_rows(COUTP), HY = MT + 2;
   constexpr int NP = 14;                              // tap pairs per chunk (the last one: tap 26 + zeros)
   constexpr int HV = kHX * HY * kHZ;
@@ -133,6 +139,28 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
     }
   };
   s4 xv[NPER];
+  if (CU < 0) {      // features from the residual: goff = 4 voxel + q
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      const int idx = tid + 256 * k;
+      const int q = idx & 3, hv = idx >> 2;
+      const int hx = hv % kHX, hy = (hv / kHX) % HY, hz = hv / (kHX * HY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
+      goff[k] = inside ? 4 * (gx + g.X * (gy + g.Y * gz)) + q : -1;
+    }
+    const double ms = *fnrm / double(g.P());
+    const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+    const bf16 kb = f2bf(ms > 0.0 ? fkh : 0.f);
+#pragma unroll
+    for (int k = 0; k < NPER; ++k) {
+      xv[k] = s4{0, 0, 0, 0};
+      if (goff[k] >= 0 && (goff[k] & 3) == 0) {
+        const double2 a = fr[goff[k] >> 2];
+        xv[k] = s4{short(f2bf(float(a.x * inv))), short(f2bf(float(a.y * inv))), short(kb), 0};
+      }
+    }
+  }
   auto load_x = [&](int kc) {      // chunk kc of the input (channels 16 kc .. 16 kc + 15)
     const bf16* src = (CU > 0 && kc < CU) ? up.p : in.p;
     const int c0 = 16 * ((CU > 0 && kc >= CU) ? kc - CU : kc);
@@ -144,7 +172,7 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   };
   if (CU > 0)
     set_offsets(up, gu, 1);
-  else
+  else if (CU == 0)
     set_offsets(in, g, 0);
   auto store_x = [&]() {
 #pragma unroll
@@ -170,7 +198,7 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   const int abase = (i + 1) + kHX * (1 + HY * (wave + 1));
   constexpr int D = NT == 1 ? 6 : (NT == 2 ? 4 : 2);    // weight fragments are loaded D steps ahead
   {
-    load_x(0);
+    if (CU >= 0) load_x(0);
     f4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
@@ -741,20 +769,22 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 #define H6_CONV_CASES(X) \
   X(16, 16) X(16, 32) X(16, 48) X(48, 16) X(96, 32) X(64, 32) X(32, 32) X(32, 64) X(32, 96) X(32, 16) X(64, 64)
 // decoder layers whose first `cu` input chunks are the upsampled coarser level
-#define H6_CONV_UP_CASES(X) X(96, 32, 4) X(48, 16, 2)
+// (cu = -1: the first layer reading the residual's features)
+#define H6_CONV_UP_CASES(X) X(96, 32, 4) X(48, 16, 2) X(16, 16, -1)
 
 // out = act(conv(in)); with cu > 0 the first cu 16-channel chunks of the input are
 // the nearest-neighbour upsampling of `up` (grid gu = half(g)) and the rest come from `in`
+// cu < 0: the input is the features of the residual fr (first layer, cinp = 16)
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s, View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0},
-                int cu = 0) {
+                int cu = 0, const double2* fr = nullptr, const double* fnrm = nullptr, float fkh = 0.f) {
   const int rows = conv_rows(coutp);
   const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + rows - 1) / rows, ntz = (g.Z + kTZ - 1) / kTZ;
   const unsigned grid = unsigned(ntx) * nty * ntz;
 #define H6_CONV(CI, CO)                                                                                   \
   if (cu == 0 && cinp == CI && coutp == CO) {                                                             \
     hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, 0>), dim3(grid), dim3(256), 0, s, in, W, bias, out,  \
-                       out32, cout, relu, g, ntx, nty, up, gu);                                           \
+                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh);                            \
     return hipGetLastError();                                                                             \
   }
   H6_CONV_CASES(H6_CONV)
@@ -762,7 +792,7 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
 #define H6_CONV_UP(CI, CO, CUP)                                                                             \
   if (cu == CUP && cinp == CI && coutp == CO) {                                                             \
     hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, CUP>), dim3(grid), dim3(256), 0, s, in, W, bias, out, \
-                       out32, cout, relu, g, ntx, nty, up, gu);                                             \
+                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh);                              \
     return hipGetLastError();                                                                               \
   }
   H6_CONV_UP_CASES(H6_CONV_UP)
@@ -814,35 +844,46 @@ View vw(bf16* p, int cs, int coff = 0) { return View{p, cs, coff}; }
 
 // one layer: out = act(conv(in)) with the layer's packed weights
 hipError_t layer_fwd(h6_net N, int L, View in, View out, float* out32, Grid3 g, hipStream_t s,
-                     View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0}, int cu = 0) {
+                     View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0}, int cu = 0,
+                     const double2* fr = nullptr, float fkh = 0.f) {
   const LayerDef& d = kLayers[L];
   return conv(in, r16(d.cin), N->wf[L], r16(d.cout), N->w32 + N->off[L] + (long long)d.cout * d.cin * 27,
-              out, out32, d.cout, d.relu, g, s, up, gu, cu);
+              out, out32, d.cout, d.relu, g, s, up, gu, cu, fr, N->d_scal, fkh);
 }
 
-// fuse_up (inference): the decoder convolutions read the upsampled coarser
-// level directly instead of the materialised concatenations C2 / C1 (channels
-// 0..63 / 0..31 of those stay unwritten); training keeps them for the
-// weight gradients
+// fuse_up (inference): the first convolution forms the input features from r
+// itself, and the decoder convolutions read the upsampled coarser level
+// directly instead of the materialised concatenations C2 / C1, whose memory
+// then holds the encoder's skip outputs compactly; training keeps the
+// features and the concatenations for the weight gradients
 hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s, bool fuse_up = false) {
   const Grid3 g1 = N->g1, g2 = N->g2, g3 = N->g3;
   hipError_t e = launch_norm2(r, size_t(g1.P()), N->partials, N->d_scal, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(features_kernel, dim3(nblk(g1.P())), dim3(256), 0, s, r, N->d_scal, g1.P(),
-                     float(kh), N->X0);
-#define TRY(x) if ((e = (x)) != hipSuccess) return e
-  TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s));
-  TRY(layer_fwd(N, E1B, vw(N->T1, 16), vw(N->C1, 48, 32), nullptr, g1, s));
-  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g2.P() * 2)), dim3(256), 0, s, vw(N->C1, 48, 32), g1,
-                     vw(N->Pl1, 16), g2, 16);
+  if (!fuse_up)
+    hipLaunchKernelGGL(features_kernel, dim3(nblk(g1.P())), dim3(256), 0, s, r, N->d_scal, g1.P(),
+                       float(kh), N->X0);
+#define TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+  // skip outputs of the encoder: channels 32..47 of C1 / 64..95 of C2 when the
+  // concatenations are materialised, else compact 16- / 32-channel arrays at
+  // the start of C1 / C2 (no partly read cache lines)
+  const View skip1 = fuse_up ? vw(N->C1, 16) : vw(N->C1, 48, 32);
+  const View skip2 = fuse_up ? vw(N->C2, 32) : vw(N->C2, 96, 64);
+  if (fuse_up) {
+    TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s, View{nullptr, 0, 0}, Grid3{0, 0, 0}, -1,
+                  r, float(kh)));
+  } else {
+    TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s));
+  }
+  TRY(layer_fwd(N, E1B, vw(N->T1, 16), skip1, nullptr, g1, s));
+  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g2.P() * 2)), dim3(256), 0, s, skip1, g1, vw(N->Pl1, 16), g2, 16);
   TRY(layer_fwd(N, E2A, vw(N->Pl1, 16), vw(N->T2, 32), nullptr, g2, s));
-  TRY(layer_fwd(N, E2B, vw(N->T2, 32), vw(N->C2, 96, 64), nullptr, g2, s));
-  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g3.P() * 4)), dim3(256), 0, s, vw(N->C2, 96, 64), g2,
-                     vw(N->Pl2, 32), g3, 32);
+  TRY(layer_fwd(N, E2B, vw(N->T2, 32), skip2, nullptr, g2, s));
+  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g3.P() * 4)), dim3(256), 0, s, skip2, g2, vw(N->Pl2, 32), g3, 32);
   TRY(layer_fwd(N, B3A, vw(N->Pl2, 32), vw(N->T3, 64), nullptr, g3, s));
   TRY(layer_fwd(N, B3B, vw(N->T3, 64), vw(N->B3, 64), nullptr, g3, s));
   if (fuse_up) {
-    TRY(layer_fwd(N, D2A, vw(N->C2, 96, 64), vw(N->T2b, 32), nullptr, g2, s, vw(N->B3, 64), g3, 4));
+    TRY(layer_fwd(N, D2A, skip2, vw(N->T2b, 32), nullptr, g2, s, vw(N->B3, 64), g3, 4));
   } else {
     hipLaunchKernelGGL(up8_kernel, dim3(nblk(g2.P() * 8)), dim3(256), 0, s, vw(N->B3, 64), g3,
                        vw(N->C2, 96, 0), g2, 64);
@@ -850,7 +891,7 @@ hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s, bool fu
   }
   TRY(layer_fwd(N, D2B, vw(N->T2b, 32), vw(N->D2, 32), nullptr, g2, s));
   if (fuse_up) {
-    TRY(layer_fwd(N, D1A, vw(N->C1, 48, 32), vw(N->T1b, 16), nullptr, g1, s, vw(N->D2, 32), g2, 2));
+    TRY(layer_fwd(N, D1A, skip1, vw(N->T1b, 16), nullptr, g1, s, vw(N->D2, 32), g2, 2));
   } else {
     hipLaunchKernelGGL(up8_kernel, dim3(nblk(g1.P() * 4)), dim3(256), 0, s, vw(N->D2, 32), g2,
                        vw(N->C1, 48, 0), g1, 32);
@@ -885,7 +926,7 @@ hipError_t layer_bwd(h6_net N, int L, View act, View gout, View xin, View gin, G
 hipError_t backward(h6_net N, hipStream_t s) {
   const Grid3 g1 = N->g1, g2 = N->g2, g3 = N->g3;
   hipError_t e;
-#define TRY(x) if ((e = (x)) != hipSuccess) return e
+#define TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
   TRY(layer_bwd(N, OUT, View{nullptr, 0, 0}, vw(N->dY, 16), vw(N->D1, 16), vw(N->dD1, 16), g1, s));
   TRY(layer_bwd(N, D1B, vw(N->D1, 16), vw(N->dD1, 16), vw(N->T1b, 16), vw(N->dT1b, 16), g1, s));
   TRY(layer_bwd(N, D1A, vw(N->T1b, 16), vw(N->dT1b, 16), vw(N->C1, 48), vw(N->dC1, 48), g1, s));
