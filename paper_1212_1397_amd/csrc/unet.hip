@@ -127,39 +127,49 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   // same for every chunk of one source; sh = 1: voxel v of the grid reads
   // voxel v / 2 of the source
   int goff[NPER];
-  auto set_offsets = [&](const View& v, Grid3 gs, int sh) {
+  // fn(k, gx, gy, gz, inside) for this thread's pieces k: piece k is channel
+  // quad q = tid & 3 of block voxel hv = tid / 4 + 64 k, walked incrementally
+  // (64 voxels = 64 / kHX rows + 64 % kHX) instead of dividing per piece
+  auto for_pieces = [&](auto&& fn) {
+    const int hv0 = tid >> 2;
+    int hx = hv0 % kHX, hy = (hv0 / kHX) % HY, hz = hv0 / (kHX * HY);
+    static_assert(64 / kHX + 1 < HY, "one row wrap per step");
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
-      const int idx = tid + 256 * k;
-      const int q = idx & 3, hv = idx >> 2;
-      const int hx = hv % kHX, hy = (hv / kHX) % HY, hz = hv / (kHX * HY);
       const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
-      goff[k] = inside ? ((gx >> sh) + gs.X * ((gy >> sh) + gs.Y * (gz >> sh))) * v.cs + v.coff + 4 * q : -1;
+      const bool inside = hz < kHZ && unsigned(gx) < unsigned(g.X) && unsigned(gy) < unsigned(g.Y) &&
+                          unsigned(gz) < unsigned(g.Z);
+      fn(k, gx, gy, gz, inside);
+      hx += 64 % kHX;
+      const int cx = hx >= kHX ? 1 : 0;
+      hx -= cx * kHX;
+      hy += 64 / kHX + cx;
+      const int cy = hy >= HY ? 1 : 0;
+      hy -= cy * HY;
+      hz += cy;
     }
   };
+  const int q4 = 4 * (tid & 3);
+  // gather offsets (element offsets of channel 4 q of the source's first
+  // chunk; -1 outside the grid), the same for every chunk of one source;
+  // sh = 1: voxel v of the grid reads voxel v / 2 of the source
+  auto set_offsets = [&](const View& v, Grid3 gs, int sh) {
+    for_pieces([&](int k, int gx, int gy, int gz, bool inside) {
+      goff[k] = inside ? ((gx >> sh) + gs.X * ((gy >> sh) + gs.Y * (gz >> sh))) * v.cs + v.coff + q4 : -1;
+    });
+  };
   s4 xv[NPER];
-  if (CU < 0) {      // features from the residual: goff = 4 voxel + q
-#pragma unroll
-    for (int k = 0; k < NPER; ++k) {
-      const int idx = tid + 256 * k;
-      const int q = idx & 3, hv = idx >> 2;
-      const int hx = hv % kHX, hy = (hv / kHX) % HY, hz = hv / (kHX * HY);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      const bool inside = idx < NPIECE && gx >= 0 && gx < g.X && gy >= 0 && gy < g.Y && gz >= 0 && gz < g.Z;
-      goff[k] = inside ? 4 * (gx + g.X * (gy + g.Y * gz)) + q : -1;
-    }
+  if (CU < 0) {      // features from the residual (channels 0..3 of quad 0, zeros elsewhere)
     const double ms = *fnrm / double(g.P());
     const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
     const bf16 kb = f2bf(ms > 0.0 ? fkh : 0.f);
-#pragma unroll
-    for (int k = 0; k < NPER; ++k) {
+    for_pieces([&](int k, int gx, int gy, int gz, bool inside) {
       xv[k] = s4{0, 0, 0, 0};
-      if (goff[k] >= 0 && (goff[k] & 3) == 0) {
-        const double2 a = fr[goff[k] >> 2];
+      if (inside && q4 == 0) {
+        const double2 a = fr[gx + g.X * (gy + g.Y * gz)];
         xv[k] = s4{short(f2bf(float(a.x * inv))), short(f2bf(float(a.y * inv))), short(kb), 0};
       }
-    }
+    });
   }
   auto load_x = [&](int kc) {      // chunk kc of the input (channels 16 kc .. 16 kc + 15)
     const bf16* src = (CU > 0 && kc < CU) ? up.p : in.p;
