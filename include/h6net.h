@@ -6,7 +6,7 @@
  * eq. (scheme) is what a Krylov method (Section 2) must remove.  This
  * library adds a small convolutional network that maps a residual r to a
  * correction c, used as  z = A_p^{-1} r + c(r)  inside flexible GMRES, with
- * the plain A_p^{-1} r as fallback and judge.  The network is not part of the
+ * the plain A_p^{-1} r as fallback and acceptance test.  The network is not part of the
  * paper.
  *
  * Network (fixed): three levels with 16 / 32 / 64 channels, zero-padded 3x3x3
@@ -82,7 +82,7 @@ h6_status h6net_train_step(h6_net net, const void* r, double kh, const void* t, 
                            double* loss, void* hip_stream);
 
 /* Operator-weighted loss of a pair (r, t) on a plan's grid (the quantity the
- * solver's judge measures: with t = e - A_p^{-1} r, A t = r - A A_p^{-1} r):
+ * solver's acceptance test measures: with t = e - A_p^{-1} r, A t = r - A A_p^{-1} r):
  *   L_A = sum |A (c(r) - t)|^2 / sum |A t|^2,  A = the plan's operator of
  * eq. (scheme) (helmholtz6_apply_A), kh = Re(k) h of the plan.  The gradient
  * takes the adjoint of A as conj(A conj(.)), exact for all-Dirichlet faces

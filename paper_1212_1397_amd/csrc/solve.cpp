@@ -408,7 +408,7 @@ h6_status gmres(Ctx& c, const double2* F, double2* U, h6_solve_info* info, doubl
       } else {
         H6_TRY_HIP(pinv(j, first_done ? PINV_REST : PINV_ALL));
         if (j == 0 && flex && P->net) {
-          // judge of the correction for this cycle: ||q - A z|| with and without it
+          // acceptance test of the correction for this cycle: ||q - A z|| with and without it
           const size_t zb = N * (mixed ? sizeof(float2) : sizeof(double2));
           H6_TRY_HIP(apply_A_z(zj, w));
           H6_TRY_HIP(launch_diff_norm2(qj, w, N, P->partials, c.dev + kJudge, c.s));

@@ -207,7 +207,7 @@ def test_learned_fgmres_converges_and_falls_back(h6):
     U0, info0 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
     assert info0["status"] == "ok"
     net = h6.Net(plan.dims)
-    # a zero correction passes the judge: every step uses it and the iterates
+    # a zero correction passes the acceptance test: every step uses it and the iterates
     # are those of the plain solve, bit for bit
     net.set_params(np.zeros(net.count, dtype=np.float32))
     plan.attach_net(net)
@@ -221,7 +221,7 @@ def test_learned_fgmres_converges_and_falls_back(h6):
     U1, info1 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
     assert info1["status"] == "ok" and info1["rel_resid"] <= w.tol
     assert float(torch.linalg.norm(U1 - U0) / torch.linalg.norm(U0)) < 1e-6
-    # a grossly wrong correction is rejected by the judge: plain iterations
+    # a grossly wrong correction is rejected by the acceptance test: plain iterations
     net.set_params(h6.pack_net_params(params_for_test(out_scale=1e5)))
     U2, info2 = plan.solve(F, method="fgmres", restart=w.restart, tol=w.tol, maxit=300)
     assert plan.learned_steps() == 0
@@ -234,7 +234,7 @@ def test_committed_weights_gain(h6):
     gains over the plain preconditioner, as it comes out: on fresh pairs
     (residual, target) of a held-out 128^3 problem the corrected
     preconditioner's residual |A (c - t)| against the plain one's |A t| (the
-    quantity the solver's judge compares), and mixed FGMRES(30) on the
+    quantity the solver's acceptance test compares), and mixed FGMRES(30) on the
     128 x 130 x 130 workload with and without the correction."""
     import os
     from paper_1212_1397_amd import learned
@@ -254,7 +254,7 @@ def test_committed_weights_gain(h6):
           f"{res['learned']['iters']} steps ({res['learned']['steps_with_correction']} with the "
           f"correction), solution difference {res['solution_rel_diff']:.2e}", flush=True)
     # the network lowers the preconditioner's residual on held-out pairs, the
-    # judge accepts it on every step, and the corrected solve needs fewer
+    # acceptance test takes it on every step, and the corrected solve needs fewer
     # steps than the plain one (measured: 9 against 10)
     assert float(np.mean(ratios)) < 1.0
     assert res["plain"]["rel_resid"] <= 1e-8 and res["learned"]["rel_resid"] <= 1e-8
