@@ -517,7 +517,11 @@ h6_status setup_impl(const h6_params* p, hipStream_t s, h6_plan* out, std::strin
     if (P->ax[a].M == kRaderM && !std::getenv("H6_DENSE_TRANSFORMS")) e = build_rader(P->ax[a], s);
     else if (bluestein_ok(P->ax[a].M) && P->ax[a].L <= 256 && !std::getenv("H6_DENSE_TRANSFORMS")) {
       e = build_bluestein(P->ax[a], s);
-      if (e == hipSuccess) P->ax[a].fast = 2;     // untuned default; the autotuner may pick the dense product
+      // untuned default: the chirp-z path where its FFT length is nearly all
+      // signal (2M - 2 >= 15/16 P; measured faster there), else the dense
+      // product; the autotuner times both
+      const int M = P->ax[a].M;
+      if (e == hipSuccess && 16 * (2 * M - 2) >= 15 * bluestein_length(M)) P->ax[a].fast = 2;
     }
     P->ax[a].lines = a == 0 ? 4 : 16;     // untuned default: best on gfx950 at 256^3
   }

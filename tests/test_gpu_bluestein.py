@@ -10,7 +10,7 @@ those of the other A_p^{-1} parity tests: 1e-12 relative in FP64, 5e-5 for the
 complex64 preconditioner.  The same plans built with the dense transforms
 (H6_DENSE_TRANSFORMS set at setup) must agree with the oracle too and must
 not be bit-identical to the chirp-z results, which shows the switch took the
-other path.
+other path.  The chirp-z path is forced through the autotuner's cache file.
 """
 import numpy as np
 import pytest
@@ -35,6 +35,19 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
+def force_paths(plan, tmp_path, xfast, yfast):
+    """Choose the transform path per axis (0 dense, 2 chirp-z) through the
+    autotuner's cache file (the untuned default takes chirp-z only where its
+    FFT length is nearly all signal)."""
+    h6 = _h6()
+    arch = torch.cuda.get_device_properties(0).gcnArchName
+    nx, ny, nz = plan.dims
+    path = tmp_path / f"tune_{nx}_{ny}_{nz}_{xfast}{yfast}.txt"
+    path.write_text(f"h6tune3 {arch} {nx} {ny} {nz} {h6.PRECISIONS[plan.precision]} tz=16 xfast={xfast} "
+                    f"yfast={yfast} xlines=4 ylines=16\n")
+    plan.autotune(str(path))
+
+
 CASES = [
     # x sine P = 512 (M = 201), y cosine P = 512 (M = 131)
     ((200, 130, 3), 20.0 + 0.3j, "DDNNSS"),
@@ -50,29 +63,35 @@ CASES = [
 
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("mixed", 5e-5)])
 @pytest.mark.parametrize("n,k,bc", CASES)
-def test_bluestein_pinv_parity(n, k, bc, prec, bound):
+def test_bluestein_pinv_parity(n, k, bc, prec, bound, tmp_path):
     h6 = _h6()
     prob = oracle.Problem(n, 1.0 / (max(n) + 1), complex(k), tuple(bc))
     x = random_field(prob.shape, seed=21)
     ref = oracle.apply_Pinv(prob, x)
     plan = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+    force_paths(plan, tmp_path, 2, 2)
     z = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
     plan.close()
     assert relerr(z, ref) <= bound
 
 
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("mixed", 5e-5)])
-def test_dense_switch_takes_the_other_path(monkeypatch, prec, bound):
+def test_dense_switch_takes_the_other_path(monkeypatch, tmp_path, prec, bound):
+    """H6_DENSE_TRANSFORMS at setup builds no chirp-z tables: a cache line
+    asking for chirp-z then falls back to the dense product, which differs
+    in rounding from the chirp-z result of a plan built without it."""
     h6 = _h6()
     n, k, bc = (200, 130, 3), 20.0 + 0.3j, "DDNNSS"
     prob = oracle.Problem(n, 1.0 / (max(n) + 1), complex(k), tuple(bc))
     x = random_field(prob.shape, seed=5)
     ref = oracle.apply_Pinv(prob, x)
     plan = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+    force_paths(plan, tmp_path, 2, 2)
     zb = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
     plan.close()
     monkeypatch.setenv("H6_DENSE_TRANSFORMS", "1")
     plan = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+    force_paths(plan, tmp_path, 2, 2)
     zd = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
     plan.close()
     assert relerr(zb, ref) <= bound
@@ -80,13 +99,34 @@ def test_dense_switch_takes_the_other_path(monkeypatch, prec, bound):
     assert not np.array_equal(zb, zd)
 
 
-def test_bluestein_solve_parity():
+@pytest.mark.parametrize("M,default", [(129, 2), (127, 2), (121, 2), (119, 0), (97, 0), (255, 2), (241, 2),
+                                       (239, 0), (201, 0), (3, 0)])
+def test_untuned_default_path(tmp_path, M, default):
+    """Untuned plans take chirp-z only where 2M - 2 >= 15/16 of its FFT
+    length: the untuned result equals the forced choice of that path."""
+    h6 = _h6()
+    n = M - 1
+    prob = oracle.Problem((n, 2, 2), 1.0 / (n + 1), 5.0 + 0.1j, tuple("DDDDDD"))
+    x = random_field(prob.shape, seed=9)
+    plan = h6.Plan(prob.n, prob.h, prob.k, "DDDDDD", precision="mixed")
+    z0 = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
+    force_paths(plan, tmp_path, default, 0)
+    z1 = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
+    force_paths(plan, tmp_path, 2 - default, 0)
+    z2 = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
+    plan.close()
+    assert np.array_equal(z0, z1)
+    assert not np.array_equal(z0, z2)
+
+
+def test_bluestein_solve_parity(tmp_path):
     """A whole FGMRES solve with the chirp-z transforms inside its graphs."""
     h6 = _h6()
     n, k, bc = (96, 64, 40), 16.0 + 0.2j, "DDNNSS"
     prob = oracle.Problem(n, 1.0 / 97, complex(k), tuple(bc))
     F = random_field(prob.shape, seed=8)
     plan = h6.Plan(prob.n, prob.h, prob.k, bc)
+    force_paths(plan, tmp_path, 2, 2)
     U, info = plan.solve(to_gpu(F), method="fgmres", restart=30, tol=1e-11, maxit=400)
     assert info["status"] == "ok" and info["rel_resid"] <= 1e-11
     u = U.cpu().numpy()
