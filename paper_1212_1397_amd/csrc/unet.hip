@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   constexpr int NT = COUTP / 16, KC = CIN / 16, MT = conv_rows(COUTP), HY = MT + 2;
   constexpr int NP = 14;                              // tap pairs per chunk (the last one: tap 26 + zeros)
   constexpr int HV = kHX * HY * kHZ;
-  constexpr int NPIECE = HV * 4, NPER = (NPIECE + 255) / 256;   // 8-byte pieces of an input block
+  constexpr int NPIECE = HV * 2, NPER = (NPIECE + 255) / 256;   // 16-byte pieces of an input block
   constexpr size_t TAPW = size_t(COUTP) * CIN;        // weights per tap
   constexpr int OV = 16 * MT;                         // output voxels per wave
   constexpr int LDS_IN = HV * 32, LDS_OUT = 4 * OV * COUTP * 2;
@@ -128,46 +128,50 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
   // voxel v / 2 of the source
   int goff[NPER];
   // fn(k, gx, gy, gz, inside) for this thread's pieces k: piece k is channel
-  // quad q = tid & 3 of block voxel hv = tid / 4 + 64 k, walked incrementally
-  // (64 voxels = 64 / kHX rows + 64 % kHX) instead of dividing per piece
+  // octet q = tid & 1 of block voxel hv = tid / 2 + 128 k, walked
+  // incrementally (128 voxels = 128 / kHX rows + 128 % kHX) instead of
+  // dividing per piece
   auto for_pieces = [&](auto&& fn) {
-    const int hv0 = tid >> 2;
+    const int hv0 = tid >> 1;
     int hx = hv0 % kHX, hy = (hv0 / kHX) % HY, hz = hv0 / (kHX * HY);
-    static_assert(64 / kHX + 1 < HY, "one row wrap per step");
+    static_assert(128 / kHX + 1 < 2 * HY, "at most two plane wraps per step");
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
       const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
       const bool inside = hz < kHZ && unsigned(gx) < unsigned(g.X) && unsigned(gy) < unsigned(g.Y) &&
                           unsigned(gz) < unsigned(g.Z);
       fn(k, gx, gy, gz, inside);
-      hx += 64 % kHX;
+      hx += 128 % kHX;
       const int cx = hx >= kHX ? 1 : 0;
       hx -= cx * kHX;
-      hy += 64 / kHX + cx;
-      const int cy = hy >= HY ? 1 : 0;
-      hy -= cy * HY;
-      hz += cy;
+      hy += 128 / kHX + cx;
+#pragma unroll
+      for (int w2 = 0; w2 < 2; ++w2) {
+        const int cy = hy >= HY ? 1 : 0;
+        hy -= cy * HY;
+        hz += cy;
+      }
     }
   };
-  const int q4 = 4 * (tid & 3);
+  const int q8 = 8 * (tid & 1);
   // gather offsets (element offsets of channel 4 q of the source's first
   // chunk; -1 outside the grid), the same for every chunk of one source;
   // sh = 1: voxel v of the grid reads voxel v / 2 of the source
   auto set_offsets = [&](const View& v, Grid3 gs, int sh) {
     for_pieces([&](int k, int gx, int gy, int gz, bool inside) {
-      goff[k] = inside ? ((gx >> sh) + gs.X * ((gy >> sh) + gs.Y * (gz >> sh))) * v.cs + v.coff + q4 : -1;
+      goff[k] = inside ? ((gx >> sh) + gs.X * ((gy >> sh) + gs.Y * (gz >> sh))) * v.cs + v.coff + q8 : -1;
     });
   };
-  s4 xv[NPER];
-  if (CU < 0) {      // features from the residual (channels 0..3 of quad 0, zeros elsewhere)
+  u4w xv[NPER];
+  if (CU < 0) {      // features from the residual (channels 0..2 of octet 0, zeros elsewhere)
     const double ms = *fnrm / double(g.P());
     const double inv = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
-    const bf16 kb = f2bf(ms > 0.0 ? fkh : 0.f);
+    const unsigned kb = f2bf(ms > 0.0 ? fkh : 0.f);
     for_pieces([&](int k, int gx, int gy, int gz, bool inside) {
-      xv[k] = s4{0, 0, 0, 0};
-      if (inside && q4 == 0) {
+      xv[k] = u4w{0u, 0u, 0u, 0u};
+      if (inside && q8 == 0) {
         const double2 a = fr[gx + g.X * (gy + g.Y * gz)];
-        xv[k] = s4{short(f2bf(float(a.x * inv))), short(f2bf(float(a.y * inv))), short(kb), 0};
+        xv[k] = u4w{unsigned(f2bf(float(a.x * inv))) | (unsigned(f2bf(float(a.y * inv))) << 16), kb, 0u, 0u};
       }
     });
   }
@@ -176,8 +180,8 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
     const int c0 = 16 * ((CU > 0 && kc >= CU) ? kc - CU : kc);
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
-      xv[k] = *reinterpret_cast<const s4*>(src + (goff[k] >= 0 ? goff[k] + c0 : 0));
-      if (goff[k] < 0) xv[k] = s4{0, 0, 0, 0};
+      xv[k] = *reinterpret_cast<const u4w*>(src + (goff[k] >= 0 ? goff[k] + c0 : 0));
+      if (goff[k] < 0) xv[k] = u4w{0u, 0u, 0u, 0u};
     }
   };
   if (CU > 0)
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
 #pragma unroll
     for (int k = 0; k < NPER; ++k) {
       const int idx = tid + 256 * k;
-      if (idx < NPIECE) *reinterpret_cast<s4*>(&xs[idx >> 2][4 * (idx & 3)]) = xv[k];
+      if (idx < NPIECE) *reinterpret_cast<u4w*>(&xs[idx >> 1][8 * (idx & 1)]) = xv[k];
     }
   };
   // B fragments: lane (i, half, second) holds channels 16 kc + 8 half .. + 7 of
