@@ -33,11 +33,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
 __device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float(unsigned(v) << 16); }
-__device__ __forceinline__ bf16 f2bf(float f) {      // round to nearest even (finite inputs)
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return bf16(u >> 16);
-}
+// round to nearest even: the conversion instruction of gfx950 (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ bf16 f2bf(float f) { return __builtin_bit_cast(bf16, static_cast<__bf16>(f)); }
 
 struct Grid3 {
   int X, Y, Z;
