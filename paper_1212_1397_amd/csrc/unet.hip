@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
                                                             float* __restrict__ out32, int cout, int relu,
                                                             Grid3 g, int ntx, int nty, View up, Grid3 gu,
                                                             const double2* __restrict__ fr,
-                                                            const double* __restrict__ fnrm, float fkh) {
+                                                            const double* __restrict__ fnrm, float fkh,
+                                                            View pout, Grid3 gp) {
   constexpr int NT = COUTP / 16, KC = CIN / 16, MT = conv_rows(COUTP), HY = MT + 2;
   constexpr int NP = 14;                              // tap pairs per chunk (the last one: tap 26 + zeros)
   constexpr int HV = kHX * HY * kHZ;
@@ -300,6 +301,38 @@ __global__ __launch_bounds__(256) void conv_tile_x32_kernel(View in, const bf16*
         if (x < g.X && y < g.Y && 8 * c8 < cout)
           *reinterpret_cast<u4w*>(out.p + (vz + (long long)g.X * y + x) * out.cs + out.coff + 8 * c8) =
               *reinterpret_cast<const u4w*>(ost + v * COUTP + 8 * c8);
+      }
+    }
+    // pout: the 2 x 2 x 2 average pool of the block's results on the half grid
+    // gp (blocks are even-aligned; children outside the grid add nothing,
+    // divisor 8, children summed z, y, x in FP32 as pool8_kernel does)
+    if (MT % 2 == 0 && pout.p) {
+      constexpr int C8 = COUTP / 8, PY = MT / 2, PV = 8 * PY * 2;
+      const bf16* res = reinterpret_cast<const bf16*>(lds);
+      for (int k = tid; k < PV * C8; k += 256) {
+        const int pv = k / C8, c8 = k - pv * C8;
+        const int px = pv & 7, py = (pv >> 3) % PY, pz = pv / (8 * PY);
+        const int qx = x0 / 2 + px, qy = y0 / 2 + py, qz = z0 / 2 + pz;
+        if (qx >= gp.X || qy >= gp.Y || qz >= gp.Z) continue;
+        float sacc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int dz = 0; dz < 2; ++dz)
+          for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+              const int fx = 2 * px + dx, fy = 2 * py + dy, fz = 2 * pz + dz;
+              if (x0 + fx >= g.X || y0 + fy >= g.Y || z0 + fz >= g.Z) continue;
+              const u4w w = *reinterpret_cast<const u4w*>(res + fz * (OV * COUTP) + (fx + 16 * fy) * COUTP + 8 * c8);
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk) {
+                sacc[2 * kk] += bf2f(bf16(w[kk] & 0xffffu));
+                sacc[2 * kk + 1] += bf2f(bf16(w[kk] >> 16));
+              }
+            }
+        u4w o;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          o[kk] = unsigned(f2bf(sacc[2 * kk] * 0.125f)) | (unsigned(f2bf(sacc[2 * kk + 1] * 0.125f)) << 16);
+        *reinterpret_cast<u4w*>(pout.p + (qx + (long long)gp.X * (qy + (long long)gp.Y * qz)) * pout.cs +
+                                pout.coff + 8 * c8) = o;
       }
     }
   }
@@ -785,17 +818,21 @@ unsigned nblk(long long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 // out = act(conv(in)); with cu > 0 the first cu 16-channel chunks of the input are
 // the nearest-neighbour upsampling of `up` (grid gu = half(g)) and the rest come from `in`
-// cu < 0: the input is the features of the residual fr (first layer, cinp = 16)
+// cu < 0: the input is the features of the residual fr (first layer, cinp = 16);
+// pout.p != nullptr (up to 32 output channels): the output's 2 x 2 x 2 average
+// pool also goes to pout on the half grid gp
 hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, View out, float* out32,
                 int cout, int relu, Grid3 g, hipStream_t s, View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0},
-                int cu = 0, const double2* fr = nullptr, const double* fnrm = nullptr, float fkh = 0.f) {
+                int cu = 0, const double2* fr = nullptr, const double* fnrm = nullptr, float fkh = 0.f,
+                View pout = View{nullptr, 0, 0}, Grid3 gp = Grid3{0, 0, 0}) {
+  if (pout.p && (conv_rows(coutp) % 2 != 0 || out32)) return hipErrorInvalidValue;
   const int rows = conv_rows(coutp);
   const int ntx = (g.X + kTX - 1) / kTX, nty = (g.Y + rows - 1) / rows, ntz = (g.Z + kTZ - 1) / kTZ;
   const unsigned grid = unsigned(ntx) * nty * ntz;
 #define H6_CONV(CI, CO)                                                                                   \
   if (cu == 0 && cinp == CI && coutp == CO) {                                                             \
     hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, 0>), dim3(grid), dim3(256), 0, s, in, W, bias, out,  \
-                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh);                            \
+                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh, pout, gp);                  \
     return hipGetLastError();                                                                             \
   }
   H6_CONV_CASES(H6_CONV)
@@ -803,7 +840,7 @@ hipError_t conv(View in, int cinp, const bf16* W, int coutp, const float* bias, 
 #define H6_CONV_UP(CI, CO, CUP)                                                                             \
   if (cu == CUP && cinp == CI && coutp == CO) {                                                             \
     hipLaunchKernelGGL((conv_tile_x32_kernel<CI, CO, CUP>), dim3(grid), dim3(256), 0, s, in, W, bias, out, \
-                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh);                              \
+                       out32, cout, relu, g, ntx, nty, up, gu, fr, fnrm, fkh, pout, gp);                    \
     return hipGetLastError();                                                                               \
   }
   H6_CONV_UP_CASES(H6_CONV_UP)
@@ -856,10 +893,11 @@ View vw(bf16* p, int cs, int coff = 0) { return View{p, cs, coff}; }
 // one layer: out = act(conv(in)) with the layer's packed weights
 hipError_t layer_fwd(h6_net N, int L, View in, View out, float* out32, Grid3 g, hipStream_t s,
                      View up = View{nullptr, 0, 0}, Grid3 gu = Grid3{0, 0, 0}, int cu = 0,
-                     const double2* fr = nullptr, float fkh = 0.f) {
+                     const double2* fr = nullptr, float fkh = 0.f, View pout = View{nullptr, 0, 0},
+                     Grid3 gp = Grid3{0, 0, 0}) {
   const LayerDef& d = kLayers[L];
   return conv(in, r16(d.cin), N->wf[L], r16(d.cout), N->w32 + N->off[L] + (long long)d.cout * d.cin * 27,
-              out, out32, d.cout, d.relu, g, s, up, gu, cu, fr, N->d_scal, fkh);
+              out, out32, d.cout, d.relu, g, s, up, gu, cu, fr, N->d_scal, fkh, pout, gp);
 }
 
 // fuse_up (inference): the first convolution forms the input features from r
@@ -886,11 +924,22 @@ hipError_t forward(h6_net N, const double2* r, double kh, hipStream_t s, bool fu
   } else {
     TRY(layer_fwd(N, E1A, vw(N->X0, 16), vw(N->T1, 16), nullptr, g1, s));
   }
-  TRY(layer_fwd(N, E1B, vw(N->T1, 16), skip1, nullptr, g1, s));
-  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g2.P() * 2)), dim3(256), 0, s, skip1, g1, vw(N->Pl1, 16), g2, 16);
+  // in inference the encoder's pools come from the convolutions' epilogues
+  if (fuse_up) {
+    TRY(layer_fwd(N, E1B, vw(N->T1, 16), skip1, nullptr, g1, s, View{nullptr, 0, 0}, Grid3{0, 0, 0}, 0, nullptr,
+                  0.f, vw(N->Pl1, 16), g2));
+  } else {
+    TRY(layer_fwd(N, E1B, vw(N->T1, 16), skip1, nullptr, g1, s));
+    hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g2.P() * 2)), dim3(256), 0, s, skip1, g1, vw(N->Pl1, 16), g2, 16);
+  }
   TRY(layer_fwd(N, E2A, vw(N->Pl1, 16), vw(N->T2, 32), nullptr, g2, s));
-  TRY(layer_fwd(N, E2B, vw(N->T2, 32), skip2, nullptr, g2, s));
-  hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g3.P() * 4)), dim3(256), 0, s, skip2, g2, vw(N->Pl2, 32), g3, 32);
+  if (fuse_up) {
+    TRY(layer_fwd(N, E2B, vw(N->T2, 32), skip2, nullptr, g2, s, View{nullptr, 0, 0}, Grid3{0, 0, 0}, 0, nullptr,
+                  0.f, vw(N->Pl2, 32), g3));
+  } else {
+    TRY(layer_fwd(N, E2B, vw(N->T2, 32), skip2, nullptr, g2, s));
+    hipLaunchKernelGGL(pool8_kernel, dim3(nblk(g3.P() * 4)), dim3(256), 0, s, skip2, g2, vw(N->Pl2, 32), g3, 32);
+  }
   TRY(layer_fwd(N, B3A, vw(N->Pl2, 32), vw(N->T3, 64), nullptr, g3, s));
   TRY(layer_fwd(N, B3B, vw(N->T3, 64), vw(N->B3, 64), nullptr, g3, s));
   if (fuse_up) {
