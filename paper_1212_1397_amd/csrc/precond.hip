@@ -226,29 +226,35 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   hipEvent_t ev;
 
   const double Nd = double(P->N);
+  // the first error a transform launcher reports without launching (a shape
+  // its kernels do not take); launch failures proper show in hipGetLastError
+  hipError_t refused = hipSuccess;
+  auto note = [&](hipError_t e) {
+    if (refused == hipSuccess && e != hipSuccess) refused = e;
+  };
   auto xform_x = [&](bool inv, auto* src, auto* dst, int accumulate) {
     timing_begin(P, KC_XFORM_X, s, &ev);
     if (X.fast == 1)
-      (void)launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines,
-                              P->skip);
+      note(launch_rader_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.rader, s, accumulate, X.lines,
+                             P->skip));
     else if (X.fast == 2)
-      (void)launch_bluestein_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.blue, s, accumulate, P->skip);
+      note(launch_bluestein_x<R>(X.neumann, inv, src, dst, nlines_x, X.L, X.blue, s, accumulate, P->skip));
     else
-      (void)launch_dense_x<R>(X, inv, src, dst, nlines_x, accumulate, s, P->skip);
+      note(launch_dense_x<R>(X, inv, src, dst, nlines_x, accumulate, s, P->skip));
     timing_end(P, KC_XFORM_X, s, ev, Nd * (sizeof(*src) + sizeof(*dst) * (accumulate ? 2 : 1)));
   };
   auto xform_y = [&](bool inv, const T2* src, T2* dst) {
     timing_begin(P, KC_XFORM_Y, s, &ev);
     if (Y.fast == 1)
-      (void)launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines, P->skip);
+      note(launch_rader_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.rader, s, Y.lines, P->skip));
     else if (Y.fast == 2)
-      (void)launch_bluestein_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.blue, s, P->skip);
+      note(launch_bluestein_y<R>(Y.neumann, inv, src, dst, nx, Y.L, nz, Y.blue, s, P->skip));
     else
-      (void)launch_dense_y<R>(Y, inv, src, dst, nx, nz, s, P->skip);
+      note(launch_dense_y<R>(Y, inv, src, dst, nx, nz, s, P->skip));
     timing_end(P, KC_XFORM_Y, s, ev, Nd * 2 * sizeof(T2));
   };
   if (part & PINV_FIRST) xform_x(false, r, w0, 0);
-  if (!(part & PINV_REST)) return hipGetLastError();
+  if (!(part & PINV_REST)) return refused != hipSuccess ? refused : hipGetLastError();
   xform_y(false, w0, w1);
   timing_begin(P, KC_TRIDIAG, s, &ev);
   {
@@ -269,7 +275,7 @@ hipError_t pinv_impl(h6_plan P, const Tin* r, Tout* z, hipStream_t s, int part, 
   timing_end(P, KC_TRIDIAG, s, ev, Nd * 2 * sizeof(T2));
   xform_y(true, w0, w1);
   xform_x(true, static_cast<const T2*>(w1), z, acc);
-  return hipGetLastError();
+  return refused != hipSuccess ? refused : hipGetLastError();
 }
 
 }  // namespace

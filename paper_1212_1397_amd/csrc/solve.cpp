@@ -767,10 +767,16 @@ h6_status queue_create(h6_plan* plans, int count, int m, int lanes, h6_queue* ou
         queue_destroy(Q);
         return s1;
       }
-      // the kernel variants chosen for the group's plans
+      // the kernel variants chosen for the group's plans (transform path and
+      // width where the lane plan has that path's tables)
       ln.P->stencil_tz = src->stencil_tz;
-      for (int a = 0; a < 2; ++a)
-        if (ln.P->ax[a].fast == src->ax[a].fast) ln.P->ax[a].lines = src->ax[a].lines;
+      for (int a = 0; a < 2; ++a) {
+        const int f = src->ax[a].fast;
+        if (f == 0 || (f == 1 && ln.P->ax[a].rader_mem) || (f == 2 && ln.P->ax[a].blue_mem)) {
+          ln.P->ax[a].fast = f;
+          ln.P->ax[a].lines = src->ax[a].lines;
+        }
+      }
       ln.P->use_graphs = 2;                           // device least-squares state
       s1 = ensure(ln.P, H6_FGMRES, m);
       if (s1 != H6_OK) {
