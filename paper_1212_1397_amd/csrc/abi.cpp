@@ -216,13 +216,19 @@ hipError_t build_bluestein(AxisXform& ax, hipStream_t s) {
     sq[q] = std::sin(M_PI * q / M);
     cq[q] = std::cos(M_PI * q / M);
   }
+  // FFT_P(b) as a plain DFT over the nonzero b_j (j < M and j > P - M), with
+  // exp(-2 pi i t / P) tabulated once (t = j k mod P)
+  std::vector<std::complex<long double>> wp(P);
+  for (int t = 0; t < P; ++t) {
+    const long double ang = -2.0L * M_PIl * (long double)t / P;
+    wp[t] = std::complex<long double>(cosl(ang), sinl(ang));
+  }
+  std::vector<int> nz;
+  for (int j = 0; j < P; ++j)
+    if (b[j] != std::complex<long double>(0.0L)) nz.push_back(j);
   for (int k = 0; k < P; ++k) {
     std::complex<long double> acc = 0.0L;
-    for (int j = 0; j < P; ++j) {
-      if (b[j] == std::complex<long double>(0.0L)) continue;
-      const long double ang = -2.0L * M_PIl * (long double)((long long)j * k % P) / P;
-      acc += b[j] * std::complex<long double>(cosl(ang), sinl(ang));
-    }
+    for (int j : nz) acc += b[j] * wp[(long long)j * k % P];
     bhat[k] = make_double2(double(acc.real() / P), double(acc.imag() / P));
   }
   for (int t = 0; t < P; ++t)
