@@ -516,22 +516,41 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(View dz, View xin, floa
 
 // grad (parameter layout) of one layer from the partials, summed over the
 // G workgroup rows in order.
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, const float* __restrict__ bpart,
-                                    int G, int cin, int cout, int cinp, int coutp, float* __restrict__ gw,
-                                    float* __restrict__ gb) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nw = cout * cin * 27;
-  if (idx < nw) {
-    const int tap = idx % 27, ci = (idx / 27) % cin, co = idx / (27 * cin);
-    float s = 0.f;
-    for (int q = 0; q < G; ++q) s += part[(((size_t)q * 27 + tap) * coutp + co) * cinp + ci];
-    gw[idx] = s;
-  } else if (idx < nw + cout) {
-    const int co = idx - nw;
-    float s = 0.f;
-    for (int q = 0; q < G; ++q) s += bpart[(size_t)q * coutp + co];
-    gb[co] = s;
+// Second stage of the weight gradients: gw = sum over the G partial rows, in
+// the parameter layout.  A workgroup takes 64 consecutive entries of the
+// partial layout [tap][co][ci] (coalesced reads) and splits the rows four
+// ways (row q to slice q mod 4, each slice summed in row order); the four
+// slice sums are added in slice order, so the result is deterministic.
+// Workgroups past the weights do the bias rows the same way.
+constexpr int kWrW = 64, kWrS = 4;
+__global__ __launch_bounds__(kWrW * kWrS) void wgrad_reduce_kernel(const float* __restrict__ part,
+                                                                   const float* __restrict__ bpart, int G, int cin,
+                                                                   int cout, int cinp, int coutp,
+                                                                   float* __restrict__ gw, float* __restrict__ gb) {
+  const int lane = threadIdx.x % kWrW, slice = threadIdx.x / kWrW;
+  const int npad = 27 * coutp * cinp;
+  const int nwb = (npad + kWrW - 1) / kWrW;
+  const bool bias = int(blockIdx.x) >= nwb;
+  const int e = (bias ? int(blockIdx.x) - nwb : int(blockIdx.x)) * kWrW + lane;
+  const int n = bias ? coutp : npad;
+  const size_t stride = bias ? size_t(coutp) : size_t(npad);
+  const float* __restrict__ src = bias ? bpart : part;
+  float a = 0.f;
+  if (e < n)
+    for (int q = slice; q < G; q += kWrS) a += src[size_t(q) * stride + e];
+  __shared__ float red[kWrS][kWrW];
+  red[slice][lane] = a;
+  __syncthreads();
+  if (slice != 0 || e >= n) return;
+  float t = red[0][lane];
+#pragma unroll
+  for (int k = 1; k < kWrS; ++k) t += red[k][lane];
+  if (bias) {
+    if (e < cout) gb[e] = t;
+    return;
   }
+  const int ci = e % cinp, co = (e / cinp) % coutp, tap = e / (cinp * coutp);
+  if (co < cout && ci < cin) gw[(size_t(co) * cin + ci) * 27 + tap] = t;
 }
 
 // BF16 weight copies of one layer from the FP32 master (parameter layout):
@@ -559,18 +578,6 @@ __global__ void features_kernel(const double2* __restrict__ r, const double* __r
   d[0] = f2bf(float(a.x * inv));
   d[1] = f2bf(float(a.y * inv));
   d[2] = f2bf(ms > 0.0 ? kh : 0.f);
-}
-
-// gradient of the pool, added to din: din[v] += dout[v / 2] / 8
-__global__ void pool_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
-  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= gi.P() * C) return;
-  const int c = int(idx % C);
-  const long long v = idx / C;
-  const int x = int(v % gi.X), y = int((v / gi.X) % gi.Y), z = int(v / ((long long)gi.X * gi.Y));
-  const long long vo = (x / 2) + (long long)go.X * ((y / 2) + (long long)go.Y * (z / 2));
-  bf16* d = din.p + v * din.cs + din.coff + c;
-  *d = f2bf(bf2f(*d) + 0.125f * bf2f(dout.p[vo * dout.cs + dout.coff + c]));
 }
 
 // forward 2x2x2 average pool (extent ceil(n/2), divisor 8) and nearest-
@@ -619,31 +626,82 @@ __global__ void up8_kernel(View in, Grid3 gi, View out, Grid3 go, int C) {
       *reinterpret_cast<const u4v*>(in.p + vi * in.cs + in.coff + c);
 }
 
+// backward element-wise steps, 8 channels (16 bytes) per thread like the
+// forward pool and upsampling (channel counts are multiples of 8)
+__device__ __forceinline__ void unpack8(u4v w, float (&f)[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[2 * k] = bf2f(bf16(w[k] & 0xffffu));
+    f[2 * k + 1] = bf2f(bf16(w[k] >> 16));
+  }
+}
+__device__ __forceinline__ u4v pack8(const float (&f)[8]) {
+  u4v w;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = unsigned(f2bf(f[2 * k])) | (unsigned(f2bf(f[2 * k + 1])) << 16);
+  return w;
+}
+
+// gradient of the pool, added to din: din[v] += dout[v / 2] / 8
+__global__ void pool_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int C8 = C / 8;
+  if (idx >= gi.P() * C8) return;
+  const int c = 8 * int(idx % C8);
+  const long long v = idx / C8;
+  const int x = int(v % gi.X), y = int((v / gi.X) % gi.Y), z = int(v / ((long long)gi.X * gi.Y));
+  const long long vo = (x / 2) + (long long)go.X * ((y / 2) + (long long)go.Y * (z / 2));
+  u4v* d = reinterpret_cast<u4v*>(din.p + v * din.cs + din.coff + c);
+  float a[8], g[8];
+  unpack8(*d, a);
+  unpack8(*reinterpret_cast<const u4v*>(dout.p + vo * dout.cs + dout.coff + c), g);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = a[k] + 0.125f * g[k];
+  *d = pack8(a);
+}
+
 // gradient of the upsampling: din[v] = sum of dout over the children of v
 __global__ void up_back_kernel(View dout, Grid3 go, View din, Grid3 gi, int C) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= gi.P() * C) return;
-  const int c = int(idx % C);
-  const long long v = idx / C;
+  const int C8 = C / 8;
+  if (idx >= gi.P() * C8) return;
+  const int c = 8 * int(idx % C8);
+  const long long v = idx / C8;
   const int x = int(v % gi.X), y = int((v / gi.X) % gi.Y), z = int(v / ((long long)gi.X * gi.Y));
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int d = 0; d < 2; ++d) {
         const int xo = 2 * x + d, yo = 2 * y + b, zo = 2 * z + a;
-        if (xo < go.X && yo < go.Y && zo < go.Z)
-          s += bf2f(dout.p[(xo + (long long)go.X * (yo + (long long)go.Y * zo)) * dout.cs + dout.coff + c]);
+        if (xo < go.X && yo < go.Y && zo < go.Z) {
+          float g[8];
+          unpack8(*reinterpret_cast<const u4v*>(
+                      dout.p + (xo + (long long)go.X * (yo + (long long)go.Y * zo)) * dout.cs + dout.coff + c),
+                  g);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) s[k] += g[k];
+        }
       }
-  din.p[v * din.cs + din.coff + c] = f2bf(s);
+  *reinterpret_cast<u4v*>(din.p + v * din.cs + din.coff + c) = pack8(s);
 }
 
 // ReLU gradient: g *= (a > 0)
 __global__ void relu_back_kernel(View gv, View av, long long P, int C) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= P * C) return;
-  const int c = int(idx % C);
-  const long long v = idx / C;
-  if (!(bf2f(av.p[v * av.cs + av.coff + c]) > 0.f)) gv.p[v * gv.cs + gv.coff + c] = 0;
+  const int C8 = C / 8;
+  if (idx >= P * C8) return;
+  const int c = 8 * int(idx % C8);
+  const long long v = idx / C8;
+  const u4v a = *reinterpret_cast<const u4v*>(av.p + v * av.cs + av.coff + c);
+  u4v* gp = reinterpret_cast<u4v*>(gv.p + v * gv.cs + gv.coff + c);
+  u4v g = *gp;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned lo = (bf2f(bf16(a[k] & 0xffffu)) > 0.f) ? 0x0000ffffu : 0u;
+    const unsigned hi = (bf2f(bf16(a[k] >> 16)) > 0.f) ? 0xffff0000u : 0u;
+    g[k] &= lo | hi;
+  }
+  *gp = g;
 }
 
 // correction c = s (y0 + i y1): mode 0 writes complex128, 1 adds to complex128,
@@ -971,13 +1029,14 @@ hipError_t layer_bwd(h6_net N, int L, View act, View gout, View xin, View gin, G
   const int cinp = r16(d.cin), coutp = r16(d.cout);
   hipError_t e;
   if (d.relu)
-    hipLaunchKernelGGL(relu_back_kernel, dim3(nblk(g.P() * d.cout)), dim3(256), 0, s, gout, act, g.P(),
+    hipLaunchKernelGGL(relu_back_kernel, dim3(nblk(g.P() * d.cout / 8)), dim3(256), 0, s, gout, act, g.P(),
                        d.cout);
   int G = 0;
   if ((e = wgrad(gout, xin, cinp, coutp, N->part, N->bpart, g, s, &G)) != hipSuccess) return e;
   const long long nw = (long long)d.cout * d.cin * 27;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nblk(nw + d.cout)), dim3(256), 0, s, N->part, N->bpart,
-                     G, d.cin, d.cout, cinp, coutp, N->grad + N->off[L], N->grad + N->off[L] + nw);
+  const unsigned nrb = unsigned((27 * coutp * cinp + kWrW - 1) / kWrW + (coutp + kWrW - 1) / kWrW);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(nrb), dim3(kWrW * kWrS), 0, s, N->part, N->bpart, G, d.cin,
+                     d.cout, cinp, coutp, N->grad + N->off[L], N->grad + N->off[L] + nw);
   if (gin.p)
     return conv(gout, coutp, N->wb[L], cinp, nullptr, gin, nullptr, cinp, 0, g, s);
   return hipGetLastError();
@@ -990,19 +1049,19 @@ hipError_t backward(h6_net N, hipStream_t s) {
   TRY(layer_bwd(N, OUT, View{nullptr, 0, 0}, vw(N->dY, 16), vw(N->D1, 16), vw(N->dD1, 16), g1, s));
   TRY(layer_bwd(N, D1B, vw(N->D1, 16), vw(N->dD1, 16), vw(N->T1b, 16), vw(N->dT1b, 16), g1, s));
   TRY(layer_bwd(N, D1A, vw(N->T1b, 16), vw(N->dT1b, 16), vw(N->C1, 48), vw(N->dC1, 48), g1, s));
-  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g2.P() * 32)), dim3(256), 0, s, vw(N->dC1, 48, 0), g1,
+  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g2.P() * 4)), dim3(256), 0, s, vw(N->dC1, 48, 0), g1,
                      vw(N->dD2, 32), g2, 32);
   TRY(layer_bwd(N, D2B, vw(N->D2, 32), vw(N->dD2, 32), vw(N->T2b, 32), vw(N->dT2b, 32), g2, s));
   TRY(layer_bwd(N, D2A, vw(N->T2b, 32), vw(N->dT2b, 32), vw(N->C2, 96), vw(N->dC2, 96), g2, s));
-  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g3.P() * 64)), dim3(256), 0, s, vw(N->dC2, 96, 0), g2,
+  hipLaunchKernelGGL(up_back_kernel, dim3(nblk(g3.P() * 8)), dim3(256), 0, s, vw(N->dC2, 96, 0), g2,
                      vw(N->dB3, 64), g3, 64);
   TRY(layer_bwd(N, B3B, vw(N->B3, 64), vw(N->dB3, 64), vw(N->T3, 64), vw(N->dT3, 64), g3, s));
   TRY(layer_bwd(N, B3A, vw(N->T3, 64), vw(N->dT3, 64), vw(N->Pl2, 32), vw(N->dPl2, 32), g3, s));
-  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g2.P() * 32)), dim3(256), 0, s, vw(N->dPl2, 32), g3,
+  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g2.P() * 4)), dim3(256), 0, s, vw(N->dPl2, 32), g3,
                      vw(N->dC2, 96, 64), g2, 32);
   TRY(layer_bwd(N, E2B, vw(N->C2, 96, 64), vw(N->dC2, 96, 64), vw(N->T2, 32), vw(N->dT2, 32), g2, s));
   TRY(layer_bwd(N, E2A, vw(N->T2, 32), vw(N->dT2, 32), vw(N->Pl1, 16), vw(N->dPl1, 16), g2, s));
-  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g1.P() * 16)), dim3(256), 0, s, vw(N->dPl1, 16), g2,
+  hipLaunchKernelGGL(pool_back_kernel, dim3(nblk(g1.P() * 2)), dim3(256), 0, s, vw(N->dPl1, 16), g2,
                      vw(N->dC1, 48, 32), g1, 16);
   TRY(layer_bwd(N, E1B, vw(N->C1, 48, 32), vw(N->dC1, 48, 32), vw(N->T1, 16), vw(N->dT1, 16), g1, s));
   TRY(layer_bwd(N, E1A, vw(N->T1, 16), vw(N->dT1, 16), vw(N->X0, 16), View{nullptr, 0, 0}, g1, s));
