@@ -434,6 +434,7 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(View dz, View xin, floa
   constexpr int HV = kHX * kHY * kHZ, NV = kTX * kTY * kTZ;
   constexpr int DS = NV + 4;                          // dzT row stride (bf16)
   constexpr int NTT = 7;                              // taps per wave (27 = 4 x 7 - 1)
+  static_assert(256 % COUTP == 0, "bias partials: whole channel groups per workgroup");
   __shared__ __attribute__((aligned(16))) bf16 dzT[COUTP * DS];
   __shared__ __attribute__((aligned(16))) bf16 xh[HV * CINP];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, i = l & 15, kq = l >> 4;
@@ -470,8 +471,8 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(View dz, View xin, floa
       *reinterpret_cast<s4*>(&xh[hv * CINP + 4 * cq]) = a;
     }
     __syncthreads();
-    if (tid < COUTP)
-      for (int v = 0; v < NV; ++v) bsum += bf2f(dzT[tid * DS + v]);
+    // bias partials: thread tid sums channel tid % COUTP over voxels tid / COUTP + k 256 / COUTP
+    for (int v = tid / COUTP; v < NV; v += 256 / COUTP) bsum += bf2f(dzT[(tid % COUTP) * DS + v]);
 #pragma unroll
     for (int tt = 0; tt < NTT; ++tt) {
       const int t = wave + 4 * tt;
@@ -511,11 +512,17 @@ __global__ __launch_bounds__(256) void wgrad_tile_kernel(View dz, View xin, floa
           for (int e = 0; e < 4; ++e) dst[(ta * 16 + 4 * kq + e) * CINP + tb * 16 + i] = acc[tt][ta * NB + tb][e];
     }
   }
-  if (tid < COUTP) bpart[(size_t)gi * COUTP + tid] = bsum;
+  // the 256 / COUTP bias partials of each channel, added in thread order
+  __shared__ float bred[256];
+  bred[tid] = bsum;
+  __syncthreads();
+  if (tid < COUTP) {
+    float t = 0.f;
+    for (int k = tid; k < 256; k += COUTP) t += bred[k];
+    bpart[(size_t)gi * COUTP + tid] = t;
+  }
 }
 
-// grad (parameter layout) of one layer from the partials, summed over the
-// G workgroup rows in order.
 // Second stage of the weight gradients: gw = sum over the G partial rows, in
 // the parameter layout.  A workgroup takes 64 consecutive entries of the
 // partial layout [tap][co][ci] (coalesced reads) and splits the rows four
