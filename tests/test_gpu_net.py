@@ -119,6 +119,29 @@ def test_forward_is_homogeneous_and_zero_safe(h6):
     assert torch.count_nonzero(z) == 0
 
 
+@pytest.mark.parametrize("dims", [(17, 8, 6), BIG])
+def test_inference_forward_equals_training_forward(h6, dims):
+    """Inference forms the input features inside the first convolution, takes
+    the encoder's pools from the convolution epilogues and reads the
+    decoder's upsampled inputs on the fly; training materialises all three
+    (its weight gradients need them).  Both compute the same values in the
+    same order, so the training call's loss L = sum |c - t|^2 / sum |t|^2
+    (FP64 sums over its own forward output) equals the loss of the inference
+    output up to the rounding of those sums.  Odd grid sizes exercise the
+    pools' missing children."""
+    p = params_for_test(out_scale=100.0)
+    net = h6.Net(dims)
+    net.set_params(h6.pack_net_params(p))
+    shape = (dims[2], dims[1], dims[0])
+    r = random_field(shape, 13)
+    t = random_field(shape, 14)
+    c = net.forward(torch.from_numpy(r).cuda(), KH).cpu().numpy()
+    loss, _ = net.gradients(torch.from_numpy(r).cuda(), KH, torch.from_numpy(t).cuda())
+    host = float(np.sum(np.abs(c - t) ** 2) / np.sum(np.abs(t) ** 2))
+    print(f"dims {dims}: training loss {loss:.15e}, from the inference output {host:.15e}", flush=True)
+    assert abs(loss - host) <= 1e-12 * host
+
+
 @pytest.mark.parametrize("dims", [(12, 10, 9), BIG])
 @pytest.mark.parametrize("regime", ["active", "mixed"])
 def test_gradients_match_oracle(h6, regime, dims):
