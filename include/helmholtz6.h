@@ -273,8 +273,11 @@ h6_status helmholtz6_set_graphs(h6_plan plan, int enable);
  * (stencil z-chunk depth 8, 16 or 32 planes per workgroup; for n'x or n'y + 1
  * = 257 also the dense transform against the Rader transform at 4 or 8 lines
  * per workgroup along x and 8 or 16 columns along y; for an odd n + 1 up to
- * 255 the dense transform against the Bluestein transform) and keeps the
- * fastest.  With
+ * 255 the dense transform against the Bluestein (chirp-z) transform) and
+ * keeps the fastest.  Untuned plans use Rader for n + 1 = 257, Bluestein
+ * where 2(n + 1) - 2 fills at least 15/16 of its FFT length (256 or 512),
+ * else the dense transform; with the environment variable
+ * H6_DENSE_TRANSFORMS set at setup only the dense transform is built.  With
  * cache_path != NULL the choice is read from, or appended to, that text file
  * (one line per grid shape, precision and device).  Synchronous. */
 h6_status helmholtz6_autotune(h6_plan plan, const char* cache_path, void* hip_stream);
