@@ -164,3 +164,23 @@ def test_autotuner_cache_selects_the_transform_path(tmp_path, prec, bound):
     plan.close()
     assert np.array_equal(got[(2, 2)], z_def)
     assert not np.array_equal(got[(0, 0)], z_def)
+
+
+def test_bluestein_every_odd_M(tmp_path):
+    """Every odd M = 3 .. 255 (both convolution lengths, every output-slot
+    count of the post-processing) in the sine and the cosine basis on x,
+    FP64, against the oracle."""
+    h6 = _h6()
+    worst = 0.0
+    for M in range(3, 256, 2):
+        for bc in ("DDDDDD", "NNDDDD"):
+            prob = oracle.Problem((M - 1, 2, 2), 1.0 / M, 3.0 + 0.2j, tuple(bc))
+            x = random_field(prob.shape, seed=M)
+            plan = h6.Plan(prob.n, prob.h, prob.k, bc)
+            force_paths(plan, tmp_path, 2, 0)
+            z = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
+            plan.close()
+            e = relerr(z, oracle.apply_Pinv(prob, x))
+            worst = max(worst, e)
+            assert e <= 1e-12, (M, bc, e)
+    print(f"worst relative error over odd M = 3..255: {worst:.1e}", flush=True)
