@@ -253,3 +253,45 @@ def test_sks_returns_with_its_stream_idle(prec):
             pl.apply_Pinv(x, out, stream=other)
         other.synchronize()
         assert torch.equal(out, ref), maxit
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-12), ("mixed", 5e-5)])
+def test_z_solve_every_length(prec, bound):
+    """The partitioned z solver for every n'z it takes (3 .. 544 with
+    Sommerfeld faces: every segment count and rows-per-segment tier),
+    through apply_Pinv against the oracle."""
+    h6 = _h6()
+    worst = 0.0
+    for nz in range(1, 543):
+        prob = _problem((2, 3, nz), 4.0 + 0.3j, "DDDDSS")
+        x = random_field(prob.shape, seed=nz)
+        plan = h6.Plan(prob.n, prob.h, prob.k, "DDDDSS", precision=prec)
+        z = plan.apply_Pinv(to_gpu(x)).cpu().numpy()
+        plan.close()
+        e = relerr(z, oracle.apply_Pinv(prob, x))
+        worst = max(worst, e)
+        assert e <= bound, (nz, e)
+    print(f"{prec}: worst relative error over n'z = 3..544: {worst:.1e}", flush=True)
+
+
+def test_random_shapes_and_faces():
+    """Seeded random grids (1..80 per axis: every stencil-tile tail) and face
+    patterns (x, y: D or N pairs; z faces any of D, N, S): apply_A and
+    apply_Pinv against the oracle."""
+    h6 = _h6()
+    rng = np.random.default_rng(2024)
+    for case in range(30):
+        n = tuple(int(v) for v in rng.integers(1, 81, size=3))
+        bc = "".join([2 * rng.choice(["D", "N"]), 2 * rng.choice(["D", "N"]),
+                      rng.choice(["D", "N", "S"]), rng.choice(["D", "N", "S"])])
+        k = complex(rng.uniform(1.0, 12.0), rng.uniform(0.0, 0.5))
+        prob = _problem(n, k, bc)
+        try:
+            plan = h6.Plan(prob.n, prob.h, prob.k, bc)
+        except h6.H6Error as exc:       # only a singular A_p (k on its spectrum) may be refused
+            assert exc.status == h6.H6_ERR_SINGULAR, (n, bc, k)
+            continue
+        x = random_field(prob.shape, seed=case)
+        assert relerr(plan.apply_A(to_gpu(x)).cpu().numpy(), oracle.apply_A(prob, x)) <= 1e-12, (n, bc, k)
+        assert relerr(plan.apply_Pinv(to_gpu(x)).cpu().numpy(), oracle.apply_Pinv(prob, x)) <= 1e-12, (n, bc, k)
+        plan.close()
