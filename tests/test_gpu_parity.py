@@ -295,3 +295,32 @@ def test_random_shapes_and_faces():
         assert relerr(plan.apply_A(to_gpu(x)).cpu().numpy(), oracle.apply_A(prob, x)) <= 1e-12, (n, bc, k)
         assert relerr(plan.apply_Pinv(to_gpu(x)).cpu().numpy(), oracle.apply_Pinv(prob, x)) <= 1e-12, (n, bc, k)
         plan.close()
+
+
+def test_random_solves():
+    """Seeded random small problems (8..36 unknowns per axis, random face
+    patterns, k with 0 <= Im k <= 0.3) through FP64 GMRES(m), FP64 SKS and
+    mixed FGMRES(m) against the oracle's GMRES at tol 1e-11: every solve
+    converges, meets its tolerance, and agrees with the oracle's solution to
+    1e-9 (FP64) or 1e-6 (mixed, the bound of the complex64 preconditioner's
+    tests); the FP64 GMRES step count is the oracle's within one."""
+    h6 = _h6()
+    rng = np.random.default_rng(77)
+    for case in range(8):
+        n = tuple(int(v) for v in rng.integers(8, 37, size=3))
+        bc = "".join([2 * rng.choice(["D", "N"]), 2 * rng.choice(["D", "N"]),
+                      rng.choice(["D", "N", "S"]), rng.choice(["D", "N", "S"])])
+        k = complex(rng.uniform(2.0, 6.0), rng.uniform(0.0, 0.3))
+        m = int(rng.integers(3, 31))
+        prob = _problem(n, k, bc)
+        F = random_field(prob.shape, seed=100 + case)
+        U_orc, info = oracle.solve(prob, F, "gmres", restart=m, tol=1e-11, maxit=400)
+        assert info.status == "ok", (n, bc, k)
+        for prec, method, bound in (("fp64", "gmres", 1e-9), ("fp64", "sks", 1e-9), ("mixed", "fgmres", 1e-6)):
+            plan = h6.Plan(prob.n, prob.h, prob.k, bc, precision=prec)
+            U, gi = plan.solve(to_gpu(F), method=method, restart=m, tol=1e-11, maxit=400)
+            plan.close()
+            assert gi["status"] == "ok" and gi["rel_resid"] <= 1e-11, (n, bc, k, method, gi["status"])
+            assert relerr(U.cpu().numpy(), U_orc) <= bound, (n, bc, k, method)
+            if method == "gmres":
+                assert abs(gi["iters"] - info.iters) <= 1, (n, bc, k, gi["iters"], info.iters)
